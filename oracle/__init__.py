@@ -1,0 +1,384 @@
+"""Python access to the CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it; the product package never imports it.  The oracle
+is a plain, slow C statement of the method (see oracle.h for the section map
+and the readings of what the paper leaves open).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = ["leb.c", "transport.c", "mlp.c"]
+_lib = None
+
+N_PARAMS = 17603
+N_FEATS = 76
+
+
+def build() -> None:
+    """Compile liboracle.so: plain C11, IEEE arithmetic, no contraction."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-Wall", "-Wno-unknown-pragmas"]
+    cmd += [os.path.join(_HERE, s) for s in _SRC] + ["-o", _SO + ".tmp", "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+
+
+class OCam(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("look_at", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y_deg", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class OMedium(ctypes.Structure):
+    _fields_ = [("albedo", ctypes.c_float), ("g", ctypes.c_float)]
+
+
+class OLight(ctypes.Structure):
+    _fields_ = [("sun_dir", ctypes.c_float * 3), ("sun_irradiance", ctypes.c_float * 3),
+                ("env_radiance", ctypes.c_float * 3)]
+
+
+class OBuildOpts(ctypes.Structure):
+    _fields_ = [("want_mode", ctypes.c_int32), ("uniform_depth", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("majorant_mode", ctypes.c_int32), ("variation_tau", ctypes.c_double),
+                ("target_px", ctypes.c_float), ("density_scale", ctypes.c_float), ("max_tets", ctypes.c_int64),
+                ("rand_seed", ctypes.c_uint64), ("rand_thresh", ctypes.c_int32), ("shuffle_seed", ctypes.c_uint64)]
+
+
+class ORenderOpts(ctypes.Structure):
+    _fields_ = [("max_bounces", ctypes.c_int32), ("transmittance", ctypes.c_int32),
+                ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32)]
+
+
+class ORenderStats(ctypes.Structure):
+    _fields_ = [("tet_steps", ctypes.c_int64), ("null_collisions", ctypes.c_int64),
+                ("real_collisions", ctypes.c_int64), ("escapes", ctypes.c_int64), ("truncated", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _p(a, t):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        vp = ctypes.c_void_p
+        L.oracle_leb_build.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(OCam), ctypes.POINTER(OBuildOpts),
+                                       ctypes.POINTER(vp)]
+        L.oracle_grid_num_tets.argtypes = [vp]
+        L.oracle_grid_num_tets.restype = ctypes.c_int64
+        L.oracle_grid_max_depth.argtypes = [vp]
+        L.oracle_grid_export.argtypes = [vp] * 8
+        L.oracle_grid_free.argtypes = [vp]
+        L.oracle_grid_free.restype = None
+        L.oracle_box_stats.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+        L.oracle_want.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(OCam), ctypes.POINTER(OBuildOpts),
+                                  ctypes.c_int64, vp, vp, vp, vp]
+        L.oracle_locate.argtypes = [vp, ctypes.c_int64, vp, vp]
+        L.oracle_walk.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
+        L.oracle_tet_render.argtypes = [vp, ctypes.POINTER(OCam), ctypes.POINTER(OMedium), ctypes.POINTER(OLight),
+                                        ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ORenderOpts), vp,
+                                        ctypes.c_int64, vp, ctypes.POINTER(ORenderStats), ctypes.c_int32]
+        L.oracle_dda_render.argtypes = [vp, ctypes.c_int32, ctypes.c_float, ctypes.POINTER(OCam),
+                                        ctypes.POINTER(OMedium), ctypes.POINTER(OLight), ctypes.c_int32,
+                                        ctypes.c_uint64, ctypes.POINTER(ORenderOpts), vp, ctypes.c_int64, vp,
+                                        ctypes.POINTER(ORenderStats), ctypes.c_int32]
+        L.oracle_philox4x32_10.argtypes = [vp, vp, vp]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_uniform.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 5
+        L.oracle_uniform.restype = ctypes.c_float
+        L.oracle_hg_sample_mu.argtypes = [ctypes.c_float, ctypes.c_float]
+        L.oracle_hg_sample_mu.restype = ctypes.c_float
+        L.oracle_hg_eval.argtypes = [ctypes.c_float, ctypes.c_float]
+        L.oracle_hg_eval.restype = ctypes.c_float
+        L.oracle_hg_direction.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+        L.oracle_hg_direction.restype = None
+        L.oracle_camera_ray.argtypes = [ctypes.POINTER(OCam), ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                        ctypes.c_float, vp, vp]
+        L.oracle_camera_ray.restype = None
+        L.oracle_nrc_encode.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
+        L.oracle_mlp_forward.argtypes = [vp, ctypes.c_int64, vp, vp]
+        L.oracle_mlp_backward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.oracle_nrc_loss_grad.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
+        L.oracle_adam_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _vp(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def make_cam(c: dict) -> OCam:
+    k = OCam()
+    k.pos[:] = [float(x) for x in c["pos"]]
+    k.look_at[:] = [float(x) for x in c["look_at"]]
+    k.up[:] = [float(x) for x in c["up"]]
+    k.fov_y_deg = float(c["fov_y_deg"])
+    k.width = int(c["width"])
+    k.height = int(c["height"])
+    return k
+
+
+def make_medium(m: dict) -> OMedium:
+    return OMedium(float(m["albedo"]), float(m["g"]))
+
+
+def make_light(l: dict) -> OLight:
+    o = OLight()
+    o.sun_dir[:] = [float(x) for x in l["sun_dir"]]
+    o.sun_irradiance[:] = [float(x) for x in l["sun_irradiance"]]
+    o.env_radiance[:] = [float(x) for x in l["env_radiance"]]
+    return o
+
+
+def make_build_opts(b: dict) -> OBuildOpts:
+    o = OBuildOpts()
+    o.want_mode = int(b.get("want_mode", 0))
+    o.uniform_depth = int(b.get("uniform_depth", 0))
+    o.max_depth = int(b.get("max_depth", 24))
+    o.majorant_mode = int(b.get("majorant_mode", 0))
+    o.variation_tau = float(b.get("variation_tau", 0.0))
+    o.target_px = float(b.get("target_px", 1.0))
+    o.density_scale = float(b.get("density_scale", 1.0))
+    o.max_tets = int(b.get("max_tets", 1 << 26))
+    o.rand_seed = int(b.get("rand_seed", 0))
+    o.rand_thresh = int(b.get("rand_thresh", 0))
+    o.shuffle_seed = int(b.get("shuffle_seed", 0))
+    return o
+
+
+def make_render_opts(r: dict) -> ORenderOpts:
+    return ORenderOpts(int(r.get("max_bounces", 8)), int(r.get("transmittance", 0)),
+                       int(r.get("max_steps_per_path", 1 << 20)), int(r.get("sample_offset", 0)))
+
+
+class Grid:
+    """A grid built by the oracle (owns the C handle)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().oracle_grid_free(self._h)
+            self._h = None
+
+    @property
+    def num_tets(self) -> int:
+        return int(lib().oracle_grid_num_tets(self._h))
+
+    @property
+    def max_depth(self) -> int:
+        return int(lib().oracle_grid_max_depth(self._h))
+
+    def export(self) -> dict:
+        n = self.num_tets
+        out = dict(ids=np.empty(n, np.uint64), verts=np.empty((n, 4, 3), np.int32), nbr=np.empty((n, 4), np.uint32),
+                   sigma=np.empty(n, np.float32), majorant=np.empty(n, np.float32), codes=np.empty((n, 4), np.uint8),
+                   offsets=np.empty((n, 4), np.int32))
+        _check(lib().oracle_grid_export(self._h, _vp(out["ids"]), _vp(out["verts"]), _vp(out["nbr"]),
+                                        _vp(out["sigma"]), _vp(out["majorant"]), _vp(out["codes"]),
+                                        _vp(out["offsets"])), "oracle_grid_export")
+        return out
+
+    def locate(self, pts: np.ndarray) -> np.ndarray:
+        pts = np.ascontiguousarray(pts, dtype=np.float32).reshape(-1, 3)
+        out = np.empty(len(pts), np.int64)
+        _check(lib().oracle_locate(self._h, len(pts), _vp(pts), _vp(out)), "oracle_locate")
+        return out
+
+    def walk(self, o, d, start: int, max_out: int = 100000):
+        o = np.ascontiguousarray(o, np.float32)
+        d = np.ascontiguousarray(d, np.float32)
+        tets = np.empty(max_out, np.int64)
+        faces = np.empty(max_out, np.int32)
+        tex = np.empty(max_out, np.float32)
+        n = ctypes.c_int32()
+        _check(lib().oracle_walk(self._h, _vp(o), _vp(d), int(start), max_out, _vp(tets), _vp(faces), _vp(tex),
+                                 ctypes.byref(n)), "oracle_walk")
+        k = n.value
+        return tets[:k], faces[:k], tex[:k]
+
+    def render(self, camera: dict, medium: dict, light: dict, spp: int, seed: int, render: dict | None = None,
+               pixels: np.ndarray | None = None, threads: int = 1):
+        """Average radiance per pixel: (H, W, 3) for the whole image, or
+        (len(pixels), 3) for a pixel subset.  Returns (image, stats)."""
+        cam = make_cam(camera)
+        ro = make_render_opts(render or {})
+        st = ORenderStats()
+        if pixels is not None:
+            pixels = np.ascontiguousarray(pixels, np.int32)
+            out = np.empty((len(pixels), 3), np.float32)
+            npx = len(pixels)
+        else:
+            out = np.empty((cam.height, cam.width, 3), np.float32)
+            npx = 0
+        _check(lib().oracle_tet_render(self._h, ctypes.byref(cam), ctypes.byref(make_medium(medium)),
+                                       ctypes.byref(make_light(light)), int(spp), int(seed), ctypes.byref(ro),
+                                       _vp(pixels), npx, _vp(out), ctypes.byref(st), int(threads)),
+               "oracle_tet_render")
+        return out, st.as_dict()
+
+
+def leb_build(density: np.ndarray, n: int, camera: dict, build: dict) -> Grid:
+    density = np.ascontiguousarray(density, np.float32)
+    assert density.size == n ** 3
+    h = ctypes.c_void_p()
+    cam = make_cam(camera)
+    bo = make_build_opts(build)
+    _check(lib().oracle_leb_build(_vp(density), int(n), ctypes.byref(cam), ctypes.byref(bo), ctypes.byref(h)),
+           "oracle_leb_build")
+    return Grid(h)
+
+
+def leb_build_status(density: np.ndarray, n: int, camera: dict, build: dict) -> int:
+    """Status code of a build (0 = ok), freeing the grid."""
+    density = np.ascontiguousarray(density, np.float32)
+    h = ctypes.c_void_p()
+    rc = lib().oracle_leb_build(_vp(density), int(n), ctypes.byref(make_cam(camera)),
+                                ctypes.byref(make_build_opts(build)), ctypes.byref(h))
+    if rc == 0:
+        lib().oracle_grid_free(h)
+    return rc
+
+
+def box_stats(density: np.ndarray, n: int, lo, hi):
+    density = np.ascontiguousarray(density, np.float32)
+    lo = np.ascontiguousarray(lo, np.int32)
+    hi = np.ascontiguousarray(hi, np.int32)
+    mn, mx = ctypes.c_float(), ctypes.c_float()
+    s, c = ctypes.c_double(), ctypes.c_double()
+    _check(lib().oracle_box_stats(_vp(density), n, _vp(lo), _vp(hi), ctypes.byref(mn), ctypes.byref(mx),
+                                  ctypes.byref(s), ctypes.byref(c)), "oracle_box_stats")
+    return mn.value, mx.value, s.value, c.value
+
+
+def want(density, n, camera, build, verts, depth, ids) -> np.ndarray:
+    density = np.ascontiguousarray(density, np.float32)
+    verts = np.ascontiguousarray(verts, np.int32)
+    depth = np.ascontiguousarray(depth, np.int32)
+    ids = np.ascontiguousarray(ids, np.uint64)
+    out = np.empty(len(depth), np.uint8)
+    _check(lib().oracle_want(_vp(density), n, ctypes.byref(make_cam(camera)), ctypes.byref(make_build_opts(build)),
+                             len(depth), _vp(verts), _vp(depth), _vp(ids), _vp(out)), "oracle_want")
+    return out.astype(bool)
+
+
+def dda_render(density, n, density_scale, camera, medium, light, spp, seed, render=None, pixels=None, threads=1):
+    density = np.ascontiguousarray(density, np.float32)
+    cam = make_cam(camera)
+    ro = make_render_opts(render or {})
+    st = ORenderStats()
+    if pixels is not None:
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        out = np.empty((len(pixels), 3), np.float32)
+        npx = len(pixels)
+    else:
+        out = np.empty((cam.height, cam.width, 3), np.float32)
+        npx = 0
+    _check(lib().oracle_dda_render(_vp(density), int(n), float(density_scale), ctypes.byref(cam),
+                                   ctypes.byref(make_medium(medium)), ctypes.byref(make_light(light)), int(spp),
+                                   int(seed), ctypes.byref(ro), _vp(pixels), npx, _vp(out), ctypes.byref(st),
+                                   int(threads)), "oracle_dda_render")
+    return out, st.as_dict()
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    o = np.empty(4, np.uint32)
+    lib().oracle_philox4x32_10(_vp(c), _vp(k), _vp(o))
+    return o
+
+
+def uniform(seed, pixel, sample, bounce, stream, draw) -> float:
+    return float(lib().oracle_uniform(seed, pixel, sample, bounce, stream, draw))
+
+
+def hg_sample_mu(g, u) -> float:
+    return float(lib().oracle_hg_sample_mu(g, u))
+
+
+def hg_eval(g, mu) -> float:
+    return float(lib().oracle_hg_eval(g, mu))
+
+
+def hg_direction(d, g, u1, u2) -> np.ndarray:
+    d = np.ascontiguousarray(d, np.float32)
+    o = np.empty(3, np.float32)
+    lib().oracle_hg_direction(_vp(d), g, u1, u2, _vp(o))
+    return o
+
+
+def camera_ray(camera: dict, px, py, u0, u1):
+    o = np.empty(3, np.float32)
+    d = np.empty(3, np.float32)
+    lib().oracle_camera_ray(ctypes.byref(make_cam(camera)), px, py, u0, u1, _vp(o), _vp(d))
+    return o, d
+
+
+def nrc_encode(pos, dirs, sigma_norm) -> np.ndarray:
+    pos = np.ascontiguousarray(pos, np.float32).reshape(-1, 3)
+    dirs = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
+    sn = np.ascontiguousarray(sigma_norm, np.float32).reshape(-1)
+    out = np.empty((len(pos), N_FEATS), np.float32)
+    _check(lib().oracle_nrc_encode(len(pos), _vp(pos), _vp(dirs), _vp(sn), _vp(out)), "oracle_nrc_encode")
+    return out
+
+
+def mlp_forward(params, x) -> np.ndarray:
+    params = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, N_FEATS)
+    y = np.empty((len(x), 3), np.float64)
+    _check(lib().oracle_mlp_forward(_vp(params), len(x), _vp(x), _vp(y)), "oracle_mlp_forward")
+    return y
+
+
+def mlp_backward(params, x, dy):
+    params = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, N_FEATS)
+    dy = np.ascontiguousarray(dy, np.float64).reshape(-1, 3)
+    y = np.empty((len(x), 3), np.float64)
+    g = np.empty(N_PARAMS, np.float64)
+    _check(lib().oracle_mlp_backward(_vp(params), len(x), _vp(x), _vp(dy), _vp(y), _vp(g)), "oracle_mlp_backward")
+    return y, g
+
+
+def nrc_loss_grad(y, target):
+    y = np.ascontiguousarray(y, np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(target, np.float64).reshape(-1, 3)
+    loss = ctypes.c_double()
+    dy = np.empty_like(y)
+    _check(lib().oracle_nrc_loss_grad(len(y), _vp(y), _vp(t), ctypes.byref(loss), _vp(dy)), "oracle_nrc_loss_grad")
+    return loss.value, dy
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.99, eps=1e-8):
+    for a in (params, grads, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _check(lib().oracle_adam_step(len(params), _vp(params), _vp(grads), _vp(m), _vp(v), int(step), lr, beta1, beta2,
+                                  eps), "oracle_adam_step")

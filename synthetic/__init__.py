@@ -1,0 +1,136 @@
+"""Seeded synthetic inputs (density volumes and scene descriptions).
+
+The paper renders OpenVDB production assets (a cloud and an explosion) that
+are not available here; these seeded volumes stand in for them with the
+shapes and sizes the workloads call for.  This module holds none of the
+rendering method's arithmetic: both the oracle and the GPU path take its
+output as plain input.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+def build() -> None:
+    """Compile the generator library (host C, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           os.path.join(_HERE, "gen.c"), "-o", _SO + ".tmp", "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_SO + ".tmp", _SO)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        f32p = ctypes.POINTER(ctypes.c_float)
+        lib.synth_blobs.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, f32p]
+        lib.synth_cloud_raw.argtypes = [ctypes.c_uint64, ctypes.c_int32, f32p]
+        lib.synth_plume_raw.argtypes = [ctypes.c_uint64, ctypes.c_int32, f32p]
+        _lib = lib
+    return _lib
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def blobs(seed: int, n: int, nblobs: int = 8) -> np.ndarray:
+    """Sum of `nblobs` seeded Gaussian blobs on an n^3 grid (float32,
+    x fastest): centres U[0.2,0.8]^3, std-devs U[0.05,0.2], peaks U[2,10]."""
+    out = np.empty(n * n * n, dtype=np.float32)
+    _load().synth_blobs(seed, n, nblobs, _fptr(out))
+    return out
+
+
+def _threshold(raw: np.ndarray, keep_fraction: float, peak: float) -> np.ndarray:
+    """Keep the top `keep_fraction` of voxels (value minus the cut), scaled so
+    that the maximum is `peak`."""
+    cut = np.partition(raw, int((1.0 - keep_fraction) * raw.size))[int((1.0 - keep_fraction) * raw.size)]
+    v = np.maximum(raw - cut, 0.0).astype(np.float32)
+    m = float(v.max())
+    if m > 0:
+        v *= np.float32(peak / m)
+    return v
+
+
+def cloud(seed: int, n: int = 256, keep_fraction: float = 0.2, peak: float = 20.0) -> np.ndarray:
+    """fBm cloud (6 octaves gradient noise, ellipsoidal falloff), cut at the
+    (1 - keep_fraction) quantile and scaled to `peak` extinction."""
+    raw = np.empty(n * n * n, dtype=np.float32)
+    _load().synth_cloud_raw(seed, n, _fptr(raw))
+    return _threshold(raw, keep_fraction, peak)
+
+
+def plume(seed: int, n: int = 1024, keep_fraction: float = 0.05, peak: float = 50.0) -> np.ndarray:
+    """Smoke plume (curl-advected fBm, height falloff), ~5 % occupancy."""
+    raw = np.empty(n * n * n, dtype=np.float32)
+    _load().synth_plume_raw(seed, n, _fptr(raw))
+    return _threshold(raw, keep_fraction, peak)
+
+
+def _unit(v):
+    l = math.sqrt(sum(x * x for x in v))
+    return [x / l for x in v]
+
+
+LIGHT_DEFAULT = dict(sun_dir=_unit([0.3, 0.8, -0.5]), sun_irradiance=[3.0, 2.9, 2.7],
+                     env_radiance=[0.25, 0.30, 0.40])
+
+
+def scene(name: str, **over) -> dict:
+    """Scene description: density + camera + medium + light + build/render
+    options.  Names: 'tiny' (blobs, uniform depth 9, 64^2, 16 spp),
+    'cloud' (256^3 fBm cloud, adaptive, 1024^2, 32 spp), 'plume'
+    (1024^3 plume), or 'blobs_adaptive' (small adaptive test scene)."""
+    if name == "tiny":
+        s = dict(density_fn=lambda: blobs(0, 64), n=64,
+                 camera=dict(pos=[0.5, 0.5, -1.2], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=40.0,
+                             width=64, height=64),
+                 medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
+                 build=dict(want_mode=1, uniform_depth=9, max_depth=9, majorant_mode=0, variation_tau=0.0,
+                            target_px=1.0, density_scale=1.0, max_tets=1 << 20),
+                 render=dict(spp=16, max_bounces=8, transmittance=0, max_steps_per_path=1 << 20))
+    elif name == "cloud":
+        s = dict(density_fn=lambda: cloud(1, 256), n=256,
+                 camera=dict(pos=[0.5, 0.45, -0.9], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=45.0,
+                             width=1024, height=1024),
+                 medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
+                 build=dict(want_mode=0, uniform_depth=0, max_depth=24, majorant_mode=0, variation_tau=0.05,
+                            target_px=1.0, density_scale=1.0, max_tets=1 << 26),
+                 render=dict(spp=32, max_bounces=32, transmittance=0, max_steps_per_path=1 << 20))
+    elif name == "plume":
+        s = dict(density_fn=lambda: plume(2, 1024), n=1024,
+                 camera=dict(pos=[0.5, 0.45, -0.9], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=45.0,
+                             width=1024, height=1024),
+                 medium=dict(albedo=0.95, g=0.6), light=dict(LIGHT_DEFAULT),
+                 build=dict(want_mode=0, uniform_depth=0, max_depth=30, majorant_mode=0, variation_tau=0.05,
+                            target_px=1.0, density_scale=1.0, max_tets=1 << 27),
+                 render=dict(spp=32, max_bounces=64, transmittance=0, max_steps_per_path=1 << 20))
+    elif name == "blobs_adaptive":
+        s = dict(density_fn=lambda: blobs(3, 32), n=32,
+                 camera=dict(pos=[0.4, 0.6, -1.0], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=40.0,
+                             width=48, height=40),
+                 medium=dict(albedo=0.8, g=-0.2), light=dict(LIGHT_DEFAULT),
+                 build=dict(want_mode=0, uniform_depth=0, max_depth=15, majorant_mode=1, variation_tau=0.3,
+                            target_px=2.0, density_scale=1.5, max_tets=1 << 22),
+                 render=dict(spp=8, max_bounces=6, transmittance=0, max_steps_per_path=1 << 20))
+    else:
+        raise KeyError(name)
+    for k, v in over.items():
+        if isinstance(v, dict) and isinstance(s.get(k), dict):
+            s[k] = {**s[k], **v}
+        else:
+            s[k] = v
+    return s
