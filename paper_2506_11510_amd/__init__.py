@@ -1,0 +1,146 @@
+"""Adaptive tetrahedral grids for volumetric path tracing on MI355X (gfx950).
+
+Python face of libtetvol.so (include/tetvol.h): argument marshalling around
+the C ABI.  The LEB grid build, the tet walk, delta tracking, scattering and
+the radiance cache all run in the library's HIP kernels; torch tensors only
+hold device memory and supply streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import TetError, check, lib
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else None
+
+
+def _ptr(t):
+    """(pointer, on_device) of a contiguous torch tensor or numpy array."""
+    if isinstance(t, np.ndarray):
+        assert t.flags.c_contiguous
+        return ctypes.c_void_p(t.ctypes.data), 0
+    assert t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr()), int(t.is_cuda)
+
+
+def density_struct(density, n: int, density_scale: float = 1.0) -> _abi.TetDensity:
+    p, dev = _ptr(density)
+    return _abi.TetDensity(p, int(n), dev, float(density_scale))
+
+
+class Grid:
+    """A device-resident tet grid (owns the library handle)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().tet_grid_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n = ctypes.c_int64()
+        d = ctypes.c_int32()
+        st = _abi.TetBuildStats()
+        check(lib().tet_grid_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(st)), "tet_grid_info")
+        return {**st.as_dict(), "num_tets": n.value, "max_depth": d.value}
+
+    @property
+    def num_tets(self) -> int:
+        return self.info()["num_tets"]
+
+    def export(self) -> dict:
+        """Host copies of ids, neighbour links, extinction, majorant, vertices."""
+        n = self.num_tets
+        out = dict(ids=np.empty(n, np.uint64), nbr=np.empty((n, 4), np.uint32), sigma=np.empty(n, np.float32),
+                   majorant=np.empty(n, np.float32), verts=np.empty((n, 4, 3), np.int32))
+        check(lib().tet_grid_export(self._h, out["ids"].ctypes.data, out["nbr"].ctypes.data,
+                                    out["sigma"].ctypes.data, out["majorant"].ctypes.data,
+                                    out["verts"].ctypes.data, 0, _stream()), "tet_grid_export")
+        return out
+
+    def locate(self, pts):
+        """Tet index of each point (torch CUDA tensor (N,3) float32 -> int64
+        tensor, or numpy on the host)."""
+        if isinstance(pts, np.ndarray):
+            pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+            out = np.empty(len(pts), np.int64)
+            check(lib().tet_locate(self._h, pts.ctypes.data, len(pts), out.ctypes.data, 0, _stream()), "tet_locate")
+            return out
+        import torch
+        pts = pts.contiguous().float().reshape(-1, 3)
+        out = torch.empty(pts.shape[0], dtype=torch.int64, device=pts.device)
+        check(lib().tet_locate(self._h, ctypes.c_void_p(pts.data_ptr()), pts.shape[0],
+                               ctypes.c_void_p(out.data_ptr()), 1, _stream()), "tet_locate")
+        return out
+
+
+def leb_build(density, n: int, camera: dict, target_cell_px: float = 1.0, build: dict | None = None,
+              density_scale: float | None = None) -> Grid:
+    """Builds the adaptive conforming tet grid from an n^3 density (torch CUDA
+    tensor or numpy array, x fastest)."""
+    b = dict(build or {})
+    scale = b.pop("density_scale", 1.0) if density_scale is None else density_scale
+    target = b.pop("target_px", target_cell_px)
+    for k in ("shuffle_seed",):
+        b.pop(k, None)
+    ds = density_struct(density, n, scale)
+    cam = _abi.make_camera(camera)
+    opts = _abi.make_build_opts(b)
+    h = ctypes.c_void_p()
+    check(lib().leb_build(ctypes.byref(ds), ctypes.byref(cam), float(target), ctypes.byref(opts), _stream(),
+                          ctypes.byref(h)), "leb_build")
+    return Grid(h)
+
+
+def render(grid: Grid, camera: dict, medium: dict, light: dict, spp: int, seed: int, render: dict | None = None,
+           out=None):
+    """Renders (H, W, 3) float32 radiance into a torch CUDA tensor.  Returns
+    (image, stats)."""
+    import torch
+    cam = _abi.make_camera(camera)
+    if out is None:
+        out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")
+    st = _abi.TetRenderStats()
+    p, dev = _ptr(out)
+    check(lib().tet_render(grid.handle, ctypes.byref(cam), ctypes.byref(_abi.make_medium(medium)),
+                           ctypes.byref(_abi.make_light(light)), int(spp), int(seed),
+                           ctypes.byref(_abi.make_render_opts(render)), p, dev, _stream(), ctypes.byref(st)),
+          "tet_render")
+    return out, st.as_dict()
+
+
+def dda_render(density, n: int, density_scale: float, camera: dict, medium: dict, light: dict, spp: int, seed: int,
+               render: dict | None = None, out=None):
+    """Same integrator on the regular voxel grid (regular-grid reference)."""
+    import torch
+    cam = _abi.make_camera(camera)
+    if out is None:
+        out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")
+    st = _abi.TetRenderStats()
+    ds = density_struct(density, n, density_scale)
+    p, dev = _ptr(out)
+    check(lib().dda_render(ctypes.byref(ds), ctypes.byref(cam), ctypes.byref(_abi.make_medium(medium)),
+                           ctypes.byref(_abi.make_light(light)), int(spp), int(seed),
+                           ctypes.byref(_abi.make_render_opts(render)), p, dev, _stream(), ctypes.byref(st)),
+          "dda_render")
+    return out, st.as_dict()
+
+
+def release_cache():
+    lib().tet_release_cache()
+
+
+__all__ = ["Grid", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]

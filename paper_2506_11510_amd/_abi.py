@@ -1,0 +1,160 @@
+"""ctypes binding of libtetvol.so (include/tetvol.h).  Argument marshalling
+only: every step of the method runs in the library's HIP kernels.  Device
+buffers are torch tensors (memory and streams); torch does no compute here."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libtetvol.so")
+
+TET_OK, TET_ERR_INVALID_ARG, TET_ERR_OUT_OF_MEMORY, TET_ERR_CAPACITY = 0, -1, -2, -3
+TET_ERR_DEVICE, TET_ERR_NUMERIC, TET_ERR_UNSUPPORTED, TET_ERR_INTERNAL = -4, -5, -6, -7
+
+_lib = None
+
+
+class TetError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class TetDensity(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int32), ("on_device", ctypes.c_int32),
+                ("density_scale", ctypes.c_float)]
+
+
+class TetCamera(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("look_at", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y_deg", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class TetMedium(ctypes.Structure):
+    _fields_ = [("albedo", ctypes.c_float), ("g", ctypes.c_float)]
+
+
+class TetLight(ctypes.Structure):
+    _fields_ = [("sun_dir", ctypes.c_float * 3), ("sun_irradiance", ctypes.c_float * 3),
+                ("env_radiance", ctypes.c_float * 3)]
+
+
+class TetBuildOpts(ctypes.Structure):
+    _fields_ = [("want_mode", ctypes.c_int32), ("uniform_depth", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("majorant_mode", ctypes.c_int32), ("variation_tau", ctypes.c_double), ("max_tets", ctypes.c_int64),
+                ("rand_seed", ctypes.c_uint64), ("rand_thresh", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class TetRenderOpts(ctypes.Structure):
+    _fields_ = [("max_bounces", ctypes.c_int32), ("transmittance", ctypes.c_int32),
+                ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32),
+                ("samples_per_item", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+class TetRenderStats(ctypes.Structure):
+    _fields_ = [("tet_steps", ctypes.c_int64), ("null_collisions", ctypes.c_int64),
+                ("real_collisions", ctypes.c_int64), ("escapes", ctypes.c_int64), ("truncated", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TetBuildStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("max_depth", ctypes.c_int32), ("num_tets", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes) for every entry point of include/tetvol.h
+VP = ctypes.c_void_p
+SIGNATURES = {
+    "tet_build_opts_defaults": (None, [ctypes.POINTER(TetBuildOpts)]),
+    "tet_render_opts_defaults": (None, [ctypes.POINTER(TetRenderOpts)]),
+    "leb_build": (ctypes.c_int, [ctypes.POINTER(TetDensity), ctypes.POINTER(TetCamera), ctypes.c_float,
+                                 ctypes.POINTER(TetBuildOpts), VP, ctypes.POINTER(VP)]),
+    "tet_grid_info": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(TetBuildStats)]),
+    "tet_grid_export": (ctypes.c_int, [VP, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),
+    "tet_render": (ctypes.c_int, [VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium), ctypes.POINTER(TetLight),
+                                  ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32,
+                                  VP, ctypes.POINTER(TetRenderStats)]),
+    "tet_locate": (ctypes.c_int, [VP, VP, ctypes.c_int64, VP, ctypes.c_int32, VP]),
+    "dda_render": (ctypes.c_int, [ctypes.POINTER(TetDensity), ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium),
+                                  ctypes.POINTER(TetLight), ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32, VP,
+                                  ctypes.POINTER(TetRenderStats)]),
+    "tet_grid_free": (None, [VP]),
+    "tet_release_cache": (None, []),
+    "tet_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built (there is no
+    fallback implementation)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python paper_2506_11510_amd/build.py)")
+        L = ctypes.CDLL(SO_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str):
+    if rc != TET_OK:
+        msg = lib().tet_last_error()
+        raise TetError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+
+def make_camera(c: dict) -> TetCamera:
+    k = TetCamera()
+    k.pos[:] = [float(x) for x in c["pos"]]
+    k.look_at[:] = [float(x) for x in c["look_at"]]
+    k.up[:] = [float(x) for x in c["up"]]
+    k.fov_y_deg = float(c["fov_y_deg"])
+    k.width = int(c["width"])
+    k.height = int(c["height"])
+    return k
+
+
+def make_medium(m: dict) -> TetMedium:
+    return TetMedium(float(m["albedo"]), float(m["g"]))
+
+
+def make_light(l: dict) -> TetLight:
+    o = TetLight()
+    o.sun_dir[:] = [float(x) for x in l["sun_dir"]]
+    o.sun_irradiance[:] = [float(x) for x in l["sun_irradiance"]]
+    o.env_radiance[:] = [float(x) for x in l["env_radiance"]]
+    return o
+
+
+def make_build_opts(b: dict | None) -> TetBuildOpts:
+    o = TetBuildOpts()
+    lib().tet_build_opts_defaults(ctypes.byref(o))
+    for k, v in (b or {}).items():
+        if hasattr(o, k) and k != "reserved":
+            setattr(o, k, type(getattr(o, k))(v))
+    return o
+
+
+def make_render_opts(r: dict | None) -> TetRenderOpts:
+    o = TetRenderOpts()
+    lib().tet_render_opts_defaults(ctypes.byref(o))
+    for k, v in (r or {}).items():
+        if hasattr(o, k):
+            setattr(o, k, type(getattr(o, k))(v))
+    return o

@@ -1,0 +1,849 @@
+// build.hip -- data-parallel construction of the adaptive, conforming
+// tetrahedral grid (paper, "Grid Construction").
+//
+// The paper refines from its control cube by Maubach's longest-edge
+// bisection and propagates every bisection to neighbours by a deterministic
+// rule that keeps the grid conforming.  Here the same grid is reached by
+// level-synchronous rounds:
+//   mark:  a leaf splits if it is wanted (subdivision criteria) or if a mesh
+//          vertex sits on the midpoint of one of its edges (a hanging vertex:
+//          some neighbour across that edge has been bisected);
+//   scan:  exclusive scan of (1 + split) gives every leaf its new position;
+//          children replace their parent in place, so depth-first order is
+//          kept without sorting;
+//   split: Maubach children are written and the new midpoint vertices are
+//          inserted into a device hash set of mesh vertices.
+// Every split made is necessary in any conforming refinement without wanted
+// leaves, and the rounds stop at a conforming, want-free grid, so the result
+// is the unique minimal one -- the grid the recursive propagation builds.
+//
+// Finalize: extinction / majorant per tet from the density pyramid, face
+// orientation codes, and face neighbours found by locating a point just
+// outside each face (face centroid pushed outward by a symbolic epsilon):
+// exact integer descent from the root, then a binary search of the sorted
+// depth-first keys.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace tv {
+
+// ---------------------------------------------------------------- pyramid
+__global__ void k_pyramid_level(const float* __restrict__ dens, const float* __restrict__ cmn,
+                                const float* __restrict__ cmx, const double* __restrict__ csum, int32_t m,
+                                float* __restrict__ mn, float* __restrict__ mx, double* __restrict__ sum) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)m * m * m;
+  if (idx >= total) return;
+  int64_t i = idx % m, j = (idx / m) % m, k = idx / ((int64_t)m * m);
+  int64_t pm = 2 * (int64_t)m;
+  float lo[8], hi[8];
+  double s[8];
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    int64_t c = (2 * i + (q & 1)) + pm * ((2 * j + ((q >> 1) & 1)) + pm * (2 * k + ((q >> 2) & 1)));
+    if (dens) {
+      float v = dens[c];
+      lo[q] = v;
+      hi[q] = v;
+      s[q] = (double)v;
+    } else {
+      lo[q] = cmn[c];
+      hi[q] = cmx[c];
+      s[q] = csum[c];
+    }
+  }
+  float a = lo[0], b = hi[0];
+#pragma unroll
+  for (int q = 1; q < 8; q++) {
+    a = lo[q] < a ? lo[q] : a;
+    b = hi[q] > b ? hi[q] : b;
+  }
+  mn[idx] = a;
+  mx[idx] = b;
+  sum[idx] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+__global__ void k_check_density(const float* __restrict__ d, int64_t n, int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float v = d[i];
+    if (!(v >= 0.0f) || isinf(v)) atomicOr(bad, 1);
+  }
+}
+
+// Statistics D(box) of the voxels overlapping the open lattice box (lo, hi):
+// voxel range [lo / vs, ceil(hi / vs)) per axis, summarised at the coarsest
+// pyramid level whose cells tile that range, cells combined in ascending
+// z, y, x order.
+__device__ inline void box_stats(const Pyramid& P, const int32_t lo[3], const int32_t hi[3], float& mn, float& mx,
+                                 double& sum, double& cnt) {
+  int sh = kLatBits - P.L;  // voxel size 2^sh lattice units
+  int32_t r0[3], r1[3];
+  int l = P.L;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    r0[a] = lo[a] >> sh;
+    r1[a] = (hi[a] + (1 << sh) - 1) >> sh;
+    if (r0[a] != 0) l = min(l, (int)__builtin_ctz((uint32_t)r0[a]));
+    l = min(l, (int)__builtin_ctz((uint32_t)r1[a]));
+  }
+  int64_t m = (int64_t)P.n >> l;
+  double s = 0.0;
+  float a = 0.0f, b = 0.0f;
+  bool first = true;
+  int64_t cells = 0;
+  for (int32_t k = r0[2] >> l; k < (r1[2] >> l); k++)
+    for (int32_t j = r0[1] >> l; j < (r1[1] >> l); j++)
+      for (int32_t i = r0[0] >> l; i < (r1[0] >> l); i++) {
+        int64_t o = i + m * (j + m * (int64_t)k);
+        float cmn, cmx;
+        double cs;
+        if (l == 0) {
+          cmn = cmx = P.dens[o];
+          cs = (double)cmn;
+        } else {
+          cmn = P.mn[l][o];
+          cmx = P.mx[l][o];
+          cs = P.sum[l][o];
+        }
+        if (first || cmn < a) a = cmn;
+        if (first || cmx > b) b = cmx;
+        first = false;
+        s = s + cs;
+        cells++;
+      }
+  mn = a;
+  mx = b;
+  sum = s;
+  cnt = (double)cells * (double)(1ll << (3 * l));
+}
+
+__device__ inline void tet_box(const uint64_t v[4], int32_t lo[3], int32_t hi[3]) {
+  int32_t x[4] = {vx(v[0]), vx(v[1]), vx(v[2]), vx(v[3])};
+  int32_t y[4] = {vy(v[0]), vy(v[1]), vy(v[2]), vy(v[3])};
+  int32_t z[4] = {vz(v[0]), vz(v[1]), vz(v[2]), vz(v[3])};
+  lo[0] = min(min(x[0], x[1]), min(x[2], x[3]));
+  hi[0] = max(max(x[0], x[1]), max(x[2], x[3]));
+  lo[1] = min(min(y[0], y[1]), min(y[2], y[3]));
+  hi[1] = max(max(y[0], y[1]), max(y[2], y[3]));
+  lo[2] = min(min(z[0], z[1]), min(z[2], z[3]));
+  hi[2] = max(max(z[0], z[1]), max(z[2], z[3]));
+}
+
+__device__ inline double dot3d(const double* a, const double* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+// Camera criterion: frustum test of the centroid with bounding radius l =
+// longest edge, and projected size l k_px / z > target (all FP64).
+__device__ inline bool want_camera(const CamCrit& cc, const uint64_t v[4], int depth) {
+  int k = tag_of(depth);
+  uint64_t vk = k == 1 ? v[1] : (k == 2 ? v[2] : v[3]);
+  double w[3];
+  int64_t sx = (int64_t)vx(v[0]) + vx(v[1]) + vx(v[2]) + vx(v[3]);
+  int64_t sy = (int64_t)vy(v[0]) + vy(v[1]) + vy(v[2]) + vy(v[3]);
+  int64_t sz = (int64_t)vz(v[0]) + vz(v[1]) + vz(v[2]) + vz(v[3]);
+  w[0] = (double)sx * 0x1p-22 - cc.pos[0];
+  w[1] = (double)sy * 0x1p-22 - cc.pos[1];
+  w[2] = (double)sz * 0x1p-22 - cc.pos[2];
+  int64_t ex = (int64_t)vx(vk) - vx(v[0]), ey = (int64_t)vy(vk) - vy(v[0]), ez = (int64_t)vz(vk) - vz(v[0]);
+  int64_t l2i = ex * ex + ey * ey + ez * ez;
+  double l2 = (double)l2i * 0x1p-40;
+  double l = sqrt(l2);
+  if (dot3d(cc.f, w) < -l) return false;
+#pragma unroll
+  for (int s = 0; s < 4; s++)
+    if (dot3d(cc.side[s], w) < -l) return false;
+  double z2 = dot3d(w, w);
+  if (z2 <= l2) return true;
+  return l2 * cc.kpx2 > cc.tgt2 * z2;
+}
+
+__device__ inline bool want(const Pyramid& P, const CamCrit& cc, const WantParams& wp, const uint64_t v[4],
+                            uint64_t id) {
+  int depth = id_depth(id);
+  if (wp.mode == 1) return depth < wp.uniform_depth;
+  if (wp.mode == 2) return depth < wp.max_depth && (int32_t)(mix64(id ^ wp.rand_seed) & 0xFFFF) < wp.rand_thresh;
+  if (depth >= wp.max_depth) return false;
+  int32_t lo[3], hi[3];
+  tet_box(v, lo, hi);
+  float mn, mx;
+  double s, c;
+  box_stats(P, lo, hi, mn, mx, s, c);
+  double mean = s / c;
+  if (!(mean > 0.0)) return false;
+  if (!(((double)mx - (double)mn) > wp.tau * mean)) return false;
+  return want_camera(cc, v, depth);
+}
+
+// ---------------------------------------------------------------- vertex set
+__device__ inline bool vset_has(const uint64_t* __restrict__ tab, uint64_t mask, uint64_t key) {
+  uint64_t h = mix64(key) & mask;
+  for (;;) {
+    uint64_t e = tab[h];
+    if (e == key) return true;
+    if (e == kEmptyKey) return false;
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ inline void vset_insert(uint64_t* tab, uint64_t mask, uint64_t key, uint32_t* count) {
+  uint64_t h = mix64(key) & mask;
+  for (;;) {
+    unsigned long long prev = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)kEmptyKey,
+                                        (unsigned long long)key);
+    if (prev == kEmptyKey) {
+      atomicAdd(count, 1u);
+      return;
+    }
+    if (prev == key) return;
+    h = (h + 1) & mask;
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_vset_rehash(const uint64_t* __restrict__ old, int64_t ocap, uint64_t* tab, uint64_t mask,
+                              uint32_t* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ocap && old[i] != kEmptyKey) vset_insert(tab, mask, old[i], count);
+}
+
+__global__ void k_vset_seed(const uint64_t* __restrict__ verts, int64_t n, uint64_t* tab, uint64_t mask,
+                            uint32_t* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4 * n) vset_insert(tab, mask, verts[i], count);
+}
+
+// ---------------------------------------------------------------- rounds
+// flags bit 0: the subdivision criteria have been evaluated and said no.
+__global__ void k_mark(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
+                       uint8_t* __restrict__ flags, uint32_t* __restrict__ cnt, Pyramid P, CamCrit cc, WantParams wp,
+                       const uint64_t* __restrict__ vset, uint64_t vmask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
+  uint8_t fl = flags[i];
+  bool split = false;
+  if (!(fl & 1)) {
+    if (want(P, cc, wp, v, ids[i]))
+      split = true;
+    else
+      flags[i] = fl | 1;
+  }
+  if (!split) {
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = a + 1; b < 4; b++) {
+        int32_t x = vx(v[a]) + vx(v[b]), y = vy(v[a]) + vy(v[b]), z = vz(v[a]) + vz(v[b]);
+        if (((x | y | z) & 1) == 0 && !split) split = vset_has(vset, vmask, pack_vertex(x >> 1, y >> 1, z >> 1));
+      }
+  }
+  cnt[i] = split ? 2u : 1u;
+}
+
+__global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
+                        const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
+                        const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids, uint64_t* __restrict__ nverts,
+                        uint8_t* __restrict__ nflags, uint64_t* vset, uint64_t vmask, uint32_t* vcount) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t id = ids[i];
+  uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
+  int64_t o = offs[i];
+  if (cnt[i] == 1u) {
+    nids[o] = id;
+    nflags[o] = flags[i];
+#pragma unroll
+    for (int j = 0; j < 4; j++) nverts[4 * o + j] = v[j];
+    return;
+  }
+  int k = tag_of(id_depth(id));
+  uint64_t a[4], b[4], z;
+  switch (k) {  // first child: x_k -> z; second child: (x1..x_k, z, x_{k+1}..x3)
+    case 1:
+      z = vmid(v[0], v[1]);
+      a[0] = v[0]; a[1] = z; a[2] = v[2]; a[3] = v[3];
+      b[0] = v[1]; b[1] = z; b[2] = v[2]; b[3] = v[3];
+      break;
+    case 2:
+      z = vmid(v[0], v[2]);
+      a[0] = v[0]; a[1] = v[1]; a[2] = z; a[3] = v[3];
+      b[0] = v[1]; b[1] = v[2]; b[2] = z; b[3] = v[3];
+      break;
+    default:
+      z = vmid(v[0], v[3]);
+      a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = z;
+      b[0] = v[1]; b[1] = v[2]; b[2] = v[3]; b[3] = z;
+      break;
+  }
+  nids[o] = 2 * id;
+  nids[o + 1] = 2 * id + 1;
+  nflags[o] = 0;
+  nflags[o + 1] = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    nverts[4 * o + j] = a[j];
+    nverts[4 * (o + 1) + j] = b[j];
+  }
+  vset_insert(vset, vmask, z, vcount);
+}
+
+// ---------------------------------------------------------------- scan
+// Exclusive scan of n uint32 values, 1024 per block (256 threads x 4).
+constexpr int kScanThreads = 256, kScanItems = 4, kScanBlock = kScanThreads * kScanItems;
+
+__device__ inline uint32_t block_exclusive(uint32_t x, uint32_t* wsum, uint32_t* total) {
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / 64; w++) {
+    if (w < wid) pre += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return pre + inc - x;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t ws[kScanThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++)
+    if (base + q < n) s += in[base + q];
+  uint32_t tot;
+  block_exclusive(s, ws, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_blocks(uint32_t* bsum, int64_t nb, uint32_t* total) {
+  __shared__ uint32_t ws[kScanThreads / 64];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    int64_t i = base + threadIdx.x;
+    uint32_t x = i < nb ? bsum[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_exclusive(x, ws, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ bsum,
+                             uint32_t* __restrict__ out) {
+  __shared__ uint32_t ws[kScanThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems], s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++) {
+    v[q] = base + q < n ? in[base + q] : 0u;
+    s += v[q];
+  }
+  uint32_t ex = block_exclusive(s, ws, nullptr) + bsum[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++) {
+    if (base + q < n) out[base + q] = ex;
+    ex += v[q];
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+__global__ void k_keys(int64_t n, const uint64_t* __restrict__ ids, uint64_t* __restrict__ keys, int* maxd) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t id = ids[i];
+  int d = id_depth(id);
+  keys[i] = id << (60 - d);
+  atomicMax(maxd, d);
+}
+
+// Root Kuhn tets: vertex 1 = S e_p0, vertex 2 = S (e_p0 + e_p1), over the
+// axis orders (0,1,2), (0,2,1), (1,0,2), (1,2,0), (2,0,1), (2,1,0).
+__device__ inline void root_verts(int r, int64_t v[4][3]) {
+  const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1};
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) v[j][a] = j == 3 ? kLatS : 0;
+  for (int a = 0; a < 3; a++) {
+    if (a == p0[r]) { v[1][a] = kLatS; v[2][a] = kLatS; }
+    if (a == p1[r]) v[2][a] = kLatS;
+  }
+}
+
+__device__ inline int isgn(int64_t x) { return (x > 0) - (x < 0); }
+
+// Bisection step of the perturbed-point descent for a compile-time tag K:
+// the point is 3 * face centroid (q3) plus epsilon * outward normal.
+template <int K>
+__device__ inline void descend_perturbed(int64_t v[4][3], uint64_t& h, const int64_t q3[3], const int nout[3]) {
+  constexpr int J1 = K == 1 ? 2 : 1, J2 = K == 3 ? 2 : 3;
+  int64_t z[3], a[3], b[3], nn[3];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    z[i] = (v[0][i] + v[K][i]) >> 1;
+    a[i] = v[J1][i] - z[i];
+    b[i] = v[J2][i] - z[i];
+  }
+  nn[0] = a[1] * b[2] - a[2] * b[1];
+  nn[1] = a[2] * b[0] - a[0] * b[2];
+  nn[2] = a[0] * b[1] - a[1] * b[0];
+  int64_t s0 = nn[0] * (v[0][0] - z[0]) + nn[1] * (v[0][1] - z[1]) + nn[2] * (v[0][2] - z[2]);
+  int o = s0 < 0 ? -1 : 1;
+  int64_t side = 0, pert = 0;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    int u = isgn(nn[i]) * o;
+    side += u * (q3[i] - 3 * z[i]);
+    pert += u * nout[i];
+  }
+  bool first = side != 0 ? side > 0 : pert > 0;
+  if (first) {
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[K][i] = z[i];
+    h = 2 * h;
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; j++)
+#pragma unroll
+      for (int i = 0; i < 3; i++) v[j][i] = v[j + 1][i];
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[K][i] = z[i];
+    h = 2 * h + 1;
+  }
+}
+
+__device__ inline int64_t search_keys(const uint64_t* __restrict__ keys, int64_t n, uint64_t key) {
+  int64_t lo = 0, hi = n;  // first index with keys[i] > key
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] <= key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - 1;
+}
+
+// Outward unit normal of face f (opposite vertex f) and its lattice offset;
+// returns false when the normal is not one of the 18 orientations.
+__device__ inline bool face_normal(const int64_t v[4][3], int f, int un[3], int64_t& off) {
+  int idx[3], q = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+    if (j != f) idx[q++] = j;
+  int64_t e1[3], e2[3], n[3];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    e1[i] = v[idx[1]][i] - v[idx[0]][i];
+    e2[i] = v[idx[2]][i] - v[idx[0]][i];
+  }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < 3; i++) s += n[i] * (v[f][i] - v[idx[0]][i]);
+  if (s == 0) return false;
+  int64_t m = 0;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    if (s > 0) n[i] = -n[i];
+    int64_t ab = n[i] < 0 ? -n[i] : n[i];
+    m = ab > m ? ab : m;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    int64_t ab = n[i] < 0 ? -n[i] : n[i];
+    if (ab != 0 && ab != m) ok = false;
+    un[i] = isgn(n[i]);
+  }
+  int nz = (un[0] != 0) + (un[1] != 0) + (un[2] != 0);
+  if (nz > 2) ok = false;
+  off = un[0] * v[idx[0]][0] + un[1] * v[idx[0]][1] + un[2] * v[idx[0]][2];
+  return ok;
+}
+
+__global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
+                           const uint64_t* __restrict__ keys, int dmax, Pyramid P, float scale, int majorant_mode,
+                           TetRec* __restrict__ rec, int* __restrict__ err) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint64_t pv[4] = {verts[4 * t], verts[4 * t + 1], verts[4 * t + 2], verts[4 * t + 3]};
+  int64_t v[4][3];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    v[j][0] = vx(pv[j]);
+    v[j][1] = vy(pv[j]);
+    v[j][2] = vz(pv[j]);
+  }
+  TetRec r;
+  // medium: extinction = scale * mean(D), majorant tight or scale * max(D)
+  int32_t lo[3], hi[3];
+  tet_box(pv, lo, hi);
+  float mn, mx;
+  double s, c;
+  box_stats(P, lo, hi, mn, mx, s, c);
+  double mean = s / c;
+  r.sigma = (float)((double)scale * mean);
+  r.majorant = majorant_mode == 1 ? (float)((double)scale * (double)mx) : r.sigma;
+  r.normals = 0;
+  r.pad = 0;
+#pragma unroll 1
+  for (int f = 0; f < 4; f++) {
+    int un[3];
+    int64_t off;
+    if (!face_normal(v, f, un, off)) atomicOr(err, 2);
+    r.off[f] = ldexpf((float)off, -kLatBits);
+    r.normals |= (uint32_t)((un[0] + 1) | ((un[1] + 1) << 2) | ((un[2] + 1) << 4)) << (6 * f);
+    // boundary face: its three vertices share a coordinate equal to 0 or S
+    int idx[3], q = 0;
+    for (int j = 0; j < 4; j++)
+      if (j != f) idx[q++] = j;
+    bool bnd = false;
+    for (int a = 0; a < 3; a++) {
+      int64_t x = v[idx[0]][a];
+      if (v[idx[1]][a] == x && v[idx[2]][a] == x && (x == 0 || x == kLatS)) bnd = true;
+    }
+    if (bnd) {
+      r.nbr[f] = kBoundary;
+      continue;
+    }
+    int64_t q3[3];
+    for (int a = 0; a < 3; a++) q3[a] = v[idx[0]][a] + v[idx[1]][a] + v[idx[2]][a];
+    // root: coordinates in descending order along its axis order
+    const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1}, p2[6] = {2, 1, 2, 0, 1, 0};
+    int root = -1;
+    for (int rr = 0; rr < 6 && root < 0; rr++) {
+      int c01 = isgn(q3[p0[rr]] - q3[p1[rr]]);
+      if (!c01) c01 = isgn(un[p0[rr]] - un[p1[rr]]);
+      int c12 = isgn(q3[p1[rr]] - q3[p2[rr]]);
+      if (!c12) c12 = isgn(un[p1[rr]] - un[p2[rr]]);
+      if (c01 > 0 && c12 > 0) root = rr;
+    }
+    if (root < 0) {
+      atomicOr(err, 4);
+      r.nbr[f] = kBoundary;
+      continue;
+    }
+    int64_t w[4][3];
+    root_verts(root, w);
+    uint64_t h = 8 + root;
+    for (int d = 0; d < dmax; d += 3) {
+      descend_perturbed<3>(w, h, q3, un);
+      if (d + 1 < dmax) descend_perturbed<2>(w, h, q3, un);
+      if (d + 2 < dmax) descend_perturbed<1>(w, h, q3, un);
+    }
+    int64_t nb = search_keys(keys, n, h << (60 - dmax));
+    // back face: the neighbour's vertex that is not on face f
+    uint64_t fa = pv[idx[0]], fb = pv[idx[1]], fc = pv[idx[2]];
+    int bf = -1, hits = 0;
+    if (nb >= 0) {
+      for (int j = 0; j < 4; j++) {
+        uint64_t x = verts[4 * nb + j];
+        if (x == fa || x == fb || x == fc)
+          hits++;
+        else
+          bf = j;
+      }
+    }
+    if (nb < 0 || nb == t || hits != 3 || bf < 0) {
+      atomicOr(err, 1);
+      r.nbr[f] = kBoundary;
+    } else {
+      r.nbr[f] = ((uint32_t)nb << 2) | (uint32_t)bf;
+    }
+  }
+  rec[t] = r;
+}
+
+// ---------------------------------------------------------------- host
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+namespace {
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { release(); }
+  void swap_with(Buf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
+  void release() {
+    if (p) dev_free(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  bool ensure(size_t b) {
+    if (b <= bytes) return true;
+    release();
+    size_t nb = std::max<size_t>(b, 256);
+    p = dev_alloc(nb);
+    if (!p) return false;
+    bytes = nb;
+    return true;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+struct Leaves {
+  Buf ids, verts, flags;
+  int64_t cap = 0;
+  void swap_with(Leaves& o) {
+    ids.swap_with(o.ids);
+    verts.swap_with(o.verts);
+    flags.swap_with(o.flags);
+    std::swap(cap, o.cap);
+  }
+  bool ensure(int64_t n) {
+    if (n <= cap) return true;
+    int64_t c = std::max<int64_t>(n, cap + cap / 2);
+    if (!ids.ensure(c * 8) || !verts.ensure(c * 32) || !flags.ensure(c)) return false;
+    cap = c;
+    return true;
+  }
+};
+}  // namespace
+
+static int64_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, Buf& bsum, uint32_t* d_total, hipStream_t st) {
+  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (!bsum.ensure(nb * 4)) return -1;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, bsum.as<uint32_t>());
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, bsum.as<uint32_t>(), nb, d_total);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, bsum.as<uint32_t>(), out);
+  return 0;
+}
+
+int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, const tet_build_opts* opts_in,
+               hipStream_t st, tet_grid** out) {
+  if (!out) return fail(TET_ERR_INVALID_ARG, "leb_build: out is NULL");
+  *out = nullptr;
+  if (!dens || !dens->data) return fail(TET_ERR_INVALID_ARG, "leb_build: density is NULL");
+  int32_t n = dens->n;
+  if (n < 1 || n > 4096 || (n & (n - 1))) return fail(TET_ERR_INVALID_ARG, "leb_build: n must be a power of two <= 4096");
+  if (int rc = check_camera(cam)) return rc;
+  tet_build_opts o;
+  if (opts_in) o = *opts_in;
+  else tet_build_opts_defaults(&o);
+  if (o.want_mode < 0 || o.want_mode > 2 || o.max_tets < 6 || o.max_tets > (1ll << 30) || o.max_depth < 0 ||
+      o.max_depth > 56 || o.uniform_depth < 0 || o.uniform_depth > 56 || o.majorant_mode < 0 || o.majorant_mode > 1)
+    return fail(TET_ERR_INVALID_ARG, "leb_build: bad options");
+  if (o.want_mode == 0 && !(target_px > 0.0f)) return fail(TET_ERR_INVALID_ARG, "leb_build: target_cell_px must be > 0");
+  if (!(dens->density_scale >= 0.0f) || std::isinf(dens->density_scale))
+    return fail(TET_ERR_INVALID_ARG, "leb_build: bad density_scale");
+  int L = 0;
+  while ((1 << L) < n) L++;
+  int64_t nvox = (int64_t)n * n * n;
+
+  hipEvent_t e0, e1;
+  TV_HIP(hipEventCreate(&e0));
+  TV_HIP(hipEventCreate(&e1));
+  TV_HIP(hipEventRecord(e0, st));
+
+  // density on the device
+  Buf dcopy;
+  const float* d_dens = dens->data;
+  if (!dens->on_device) {
+    if (!dcopy.ensure(nvox * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: density copy");
+    TV_HIP(hipMemcpyAsync(dcopy.p, dens->data, nvox * 4, hipMemcpyHostToDevice, st));
+    d_dens = dcopy.as<float>();
+  }
+  // small device scratch: [0] density flag, [1] max depth, [2] finalize error, [4..] counters
+  Buf misc;
+  if (!misc.ensure(64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scratch");
+  TV_HIP(hipMemsetAsync(misc.p, 0, 64, st));
+  int* d_flag = misc.as<int>();
+  uint32_t* d_total = misc.as<uint32_t>() + 4;
+  uint32_t* d_vcount = misc.as<uint32_t>() + 5;
+  hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d_dens, nvox, d_flag);
+
+  // pyramid
+  Pyramid P;
+  memset(&P, 0, sizeof(P));
+  P.dens = d_dens;
+  P.n = n;
+  P.L = L;
+  std::vector<Buf> lv(3 * (L + 1));
+  for (int l = 1; l <= L; l++) {
+    int64_t m = (int64_t)n >> l, cells = m * m * m;
+    if (!lv[3 * l].ensure(cells * 4) || !lv[3 * l + 1].ensure(cells * 4) || !lv[3 * l + 2].ensure(cells * 8))
+      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: pyramid");
+    P.mn[l] = lv[3 * l].as<float>();
+    P.mx[l] = lv[3 * l + 1].as<float>();
+    P.sum[l] = lv[3 * l + 2].as<double>();
+    hipLaunchKernelGGL(k_pyramid_level, dim3(nblocks(cells, 256)), dim3(256), 0, st, l == 1 ? d_dens : nullptr,
+                       l == 1 ? nullptr : P.mn[l - 1], l == 1 ? nullptr : P.mx[l - 1],
+                       l == 1 ? nullptr : P.sum[l - 1], (int32_t)m, (float*)P.mn[l], (float*)P.mx[l],
+                       (double*)P.sum[l]);
+  }
+  int flag = 0;
+  TV_HIP(hipMemcpyAsync(&flag, d_flag, 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  if (flag) return fail(TET_ERR_NUMERIC, "leb_build: density has NaN, infinite or negative values");
+
+  CamCrit cc;
+  make_camcrit(*cam, target_px, &cc);
+  WantParams wp;
+  memset(&wp, 0, sizeof(wp));
+  wp.mode = o.want_mode;
+  wp.uniform_depth = o.uniform_depth;
+  wp.max_depth = o.max_depth;
+  wp.tau = o.variation_tau;
+  wp.rand_seed = o.rand_seed;
+  wp.rand_thresh = o.rand_thresh;
+
+  // roots
+  Leaves A, B;
+  if (!A.ensure(1 << 16) || !B.ensure(1 << 16)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+  {
+    uint64_t hid[6], hv[24];
+    const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1};
+    for (int r = 0; r < 6; r++) {
+      int32_t c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+      c1[p0[r]] = kLatS;
+      c2[p0[r]] = kLatS;
+      c2[p1[r]] = kLatS;
+      hid[r] = 8 + r;
+      hv[4 * r] = pack_vertex(0, 0, 0);
+      hv[4 * r + 1] = pack_vertex(c1[0], c1[1], c1[2]);
+      hv[4 * r + 2] = pack_vertex(c2[0], c2[1], c2[2]);
+      hv[4 * r + 3] = pack_vertex(kLatS, kLatS, kLatS);
+    }
+    TV_HIP(hipMemcpyAsync(A.ids.p, hid, sizeof(hid), hipMemcpyHostToDevice, st));
+    TV_HIP(hipMemcpyAsync(A.verts.p, hv, sizeof(hv), hipMemcpyHostToDevice, st));
+    TV_HIP(hipMemsetAsync(A.flags.p, 0, 6, st));
+  }
+  int64_t cur = 6;
+  // vertex hash set
+  Buf vs, vs_old, cntb, offb, bsum;
+  uint64_t vcap = 1 << 16;
+  if (!vs.ensure(vcap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)vcap,
+                     kEmptyKey);
+  hipLaunchKernelGGL(k_vset_seed, dim3(1), dim3(64), 0, st, A.verts.as<uint64_t>(), (int64_t)6, vs.as<uint64_t>(),
+                     vcap - 1, d_vcount);
+
+  uint32_t* hbuf = nullptr;
+  TV_HIP(hipHostMalloc((void**)&hbuf, 16, hipHostMallocDefault));
+  struct HostFree {
+    uint32_t* p;
+    ~HostFree() { if (p) (void)hipHostFree(p); }
+  } hf{hbuf};
+  int rounds = 0;
+  for (;;) {
+    if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
+    hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
+                       A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P, cc, wp,
+                       vs.as<uint64_t>(), vcap - 1);
+    if (scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
+      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scan");
+    TV_HIP(hipMemcpyAsync(hbuf, d_total, 8, hipMemcpyDeviceToHost, st));
+    TV_HIP(hipStreamSynchronize(st));
+    int64_t total = hbuf[0];
+    uint64_t vcount = hbuf[1];
+    if (total == cur) break;
+    rounds++;
+    if (total > o.max_tets) return fail(TET_ERR_CAPACITY, "leb_build: grid exceeds max_tets");
+    int64_t splits = total - cur;
+    if ((vcount + (uint64_t)splits) * 2 > vcap) {  // keep the vertex set at most half full
+      uint64_t ncap = vcap;
+      while ((vcount + (uint64_t)splits) * 4 > ncap) ncap <<= 1;
+      vs.swap_with(vs_old);
+      if (!vs.ensure(ncap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
+      hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(ncap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)ncap,
+                         kEmptyKey);
+      TV_HIP(hipMemsetAsync(d_vcount, 0, 4, st));
+      hipLaunchKernelGGL(k_vset_rehash, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs_old.as<uint64_t>(),
+                         (int64_t)vcap, vs.as<uint64_t>(), ncap - 1, d_vcount);
+      vs_old.release();
+      vcap = ncap;
+    }
+    if (!B.ensure(total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+    hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
+                       A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
+                       B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
+                       vcap - 1, d_vcount);
+    A.swap_with(B);
+    cur = total;
+  }
+  vs.release();
+  cntb.release();
+  offb.release();
+  bsum.release();
+  B.ids.release();
+  B.verts.release();
+  B.flags.release();
+
+  // finalize
+  tet_grid* g = new tet_grid();
+  memset(g, 0, sizeof(*g));
+  TV_HIP(hipGetDevice(&g->device));
+  g->n = cur;
+  g->ids = (uint64_t*)dev_alloc(cur * 8);
+  g->keys = (uint64_t*)dev_alloc(cur * 8);
+  g->verts = (uint64_t*)dev_alloc(cur * 32);
+  g->rec = (TetRec*)dev_alloc(cur * sizeof(TetRec));
+  if (!g->ids || !g->keys || !g->verts || !g->rec) {
+    tet_grid_free(g);
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: grid arrays");
+  }
+  hipError_t he = hipMemcpyAsync(g->ids, A.ids.p, cur * 8, hipMemcpyDeviceToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(g->verts, A.verts.p, cur * 32, hipMemcpyDeviceToDevice, st);
+  if (he == hipSuccess) {
+    hipLaunchKernelGGL(k_keys, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, g->ids, g->keys, d_flag + 1);
+    he = hipMemcpyAsync(&flag, d_flag + 1, 4, hipMemcpyDeviceToHost, st);
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) {
+    tet_grid_free(g);
+    return fail(TET_ERR_DEVICE, std::string("leb_build: ") + hipGetErrorString(he));
+  }
+  g->max_depth = flag;
+  hipLaunchKernelGGL(k_finalize, dim3(nblocks(cur, 128)), dim3(128), 0, st, cur, g->ids, g->verts, g->keys,
+                     g->max_depth, P, dens->density_scale, o.majorant_mode, g->rec, d_flag + 2);
+  int ferr = 0;
+  he = hipMemcpyAsync(&ferr, d_flag + 2, 4, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipEventRecord(e1, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) {
+    tet_grid_free(g);
+    return fail(TET_ERR_DEVICE, std::string("leb_build: ") + hipGetErrorString(he));
+  }
+  if (ferr) {
+    tet_grid_free(g);
+    return fail(TET_ERR_INTERNAL, "leb_build: grid failed the conformity check (code " + std::to_string(ferr) + ")");
+  }
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g->stats.rounds = rounds;
+  g->stats.max_depth = g->max_depth;
+  g->stats.num_tets = cur;
+  g->stats.ms = ms;
+  *out = g;
+  return TET_OK;
+}
+
+}  // namespace tv

@@ -1,0 +1,199 @@
+// common.h -- shared definitions of libtetvol (device helpers, grid object,
+// error state, device-memory cache).  gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/tetvol.h"
+
+namespace tv {
+
+// Lattice: world coordinates times 2^20 are exact integers.
+constexpr int kLatBits = 20;
+constexpr int32_t kLatS = 1 << kLatBits;
+constexpr uint32_t kBoundary = 0xFFFFFFFFu;
+constexpr uint64_t kEmptyKey = ~0ull;  // never a packed vertex (coords <= 2^20 < 2^21 - 1)
+constexpr int kMaxLevels = 13;          // pyramid levels for n <= 4096
+
+// Traversal record of one tet: everything a walk step reads, 48 bytes,
+// fetched as three 16-byte loads.
+struct alignas(16) TetRec {
+  float off[4];      // face plane offsets n_f . v in world units
+  uint32_t nbr[4];   // (index << 2) | back face, or kBoundary
+  uint32_t normals;  // 6 bits per face: (nx+1) | (ny+1) << 2 | (nz+1) << 4
+  float sigma;       // extinction
+  float majorant;    // >= sigma
+  uint32_t pad;
+};
+static_assert(sizeof(TetRec) == 48, "record size");
+
+// Density pyramid: level 0 is the input volume; levels 1..L hold per cell
+// min, max (FP32) and the FP64 sum of its 8 children combined as
+// ((c000 + c100) + (c010 + c110)) + ((c001 + c101) + (c011 + c111)).
+struct Pyramid {
+  const float* dens;
+  int32_t n, L;
+  const float* mn[kMaxLevels];
+  const float* mx[kMaxLevels];
+  const double* sum[kMaxLevels];
+};
+
+// Camera quantities of the camera criterion, FP64.
+struct CamCrit {
+  double pos[3], f[3], side[4][3];
+  double kpx2, tgt2;
+};
+
+// Camera ray frame, FP32 (rounded once from FP64).
+struct Frame {
+  float pos[3], f[3], r[3], u[3];
+  float tan_x, tan_y;
+  int32_t w, h;
+};
+
+struct WantParams {
+  int32_t mode, uniform_depth, max_depth, pad;
+  double tau;
+  uint64_t rand_seed;
+  int32_t rand_thresh;
+};
+
+// ---------------------------------------------------------------- device helpers
+__host__ __device__ inline uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return x;
+}
+
+__host__ __device__ inline uint64_t pack_vertex(int32_t x, int32_t y, int32_t z) {
+  return (uint64_t)(uint32_t)x | ((uint64_t)(uint32_t)y << 21) | ((uint64_t)(uint32_t)z << 42);
+}
+__host__ __device__ inline int32_t vx(uint64_t p) { return (int32_t)(p & 0x1FFFFF); }
+__host__ __device__ inline int32_t vy(uint64_t p) { return (int32_t)((p >> 21) & 0x1FFFFF); }
+__host__ __device__ inline int32_t vz(uint64_t p) { return (int32_t)((p >> 42) & 0x1FFFFF); }
+__host__ __device__ inline uint64_t vmid(uint64_t a, uint64_t b) {
+  return pack_vertex((vx(a) + vx(b)) >> 1, (vy(a) + vy(b)) >> 1, (vz(a) + vz(b)) >> 1);
+}
+
+// depth of a heap id: roots 8..13 (4 bits) are depth 0
+__host__ __device__ inline int id_depth(uint64_t id) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return 60 - __clzll(id);
+#else
+  return 60 - __builtin_clzll(id);
+#endif
+}
+__host__ __device__ inline int tag_of(int depth) { return 3 - depth % 3; }
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ inline uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Uniform in [0,1) with 24 bits: counter (pixel, sample, bounce << 8 | stream,
+// draw >> 2), word draw & 3.
+__device__ inline float uniform01(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t bounce, uint32_t stream,
+                                  uint32_t draw) {
+  uint4 r = philox10(make_uint4(pixel, sample, (bounce << 8) | stream, draw >> 2), (uint32_t)seed,
+                     (uint32_t)(seed >> 32));
+  uint32_t w = (draw & 3) == 0 ? r.x : (draw & 3) == 1 ? r.y : (draw & 3) == 2 ? r.z : r.w;
+  return (float)(w >> 8) * 0x1p-24f;
+}
+
+enum { kStreamCamera = 0, kStreamFlight = 1, kStreamPhase = 2, kStreamLight = 3 };
+
+__device__ inline float exp_tau(float u) { return (float)(-log((double)(1.0f - u))); }
+
+// Henyey-Greenstein density of the cosine between successive propagation
+// directions, FP64 rounded once.
+__device__ inline float hg_pdf(float g, float mu) {
+  double gg = (double)g, m = (double)mu;
+  double g2 = gg * gg;
+  double den = (1.0 + g2) - (2.0 * gg) * m;
+  return (float)((1.0 - g2) / (((4.0 * 3.14159265358979323846) * den) * sqrt(den)));
+}
+
+// Inverse HG cumulative distribution (isotropic limit 2u - 1 for |g| < 1e-3).
+__device__ inline float hg_mu(float g, float u) {
+  double gg = (double)g, uu = (double)u, mu;
+  if (fabs(gg) < 1e-3) {
+    mu = 2.0 * uu - 1.0;
+  } else {
+    double g2 = gg * gg;
+    double s = (1.0 - g2) / ((1.0 - gg) + (2.0 * gg) * uu);
+    mu = ((1.0 + g2) - s * s) / (2.0 * gg);
+  }
+  mu = mu < -1.0 ? -1.0 : (mu > 1.0 ? 1.0 : mu);
+  return (float)mu;
+}
+
+__device__ inline float3 normalize3(float3 v) {
+  float l = sqrtf((v.x * v.x + v.y * v.y) + v.z * v.z);
+  return make_float3(v.x / l, v.y / l, v.z / l);
+}
+
+// Scattered direction around d: polar cosine from HG, azimuth 2 pi u2, in
+// the branchless orthonormal basis of Duff et al. (2017).
+__device__ inline float3 hg_scatter(float3 d, float g, float u1, float u2) {
+  float mu = hg_mu(g, u1);
+  float q = 1.0f - mu * mu;
+  q = q < 0.0f ? 0.0f : q;
+  float st = sqrtf(q);
+  double phi = (2.0 * 3.14159265358979323846) * (double)u2;
+  float cp = (float)cos(phi), sp = (float)sin(phi);
+  float sign = copysignf(1.0f, d.z);
+  float a = -1.0f / (sign + d.z);
+  float b = (d.x * d.y) * a;
+  float3 t1 = make_float3(1.0f + ((sign * d.x) * d.x) * a, sign * b, -sign * d.x);
+  float3 t2 = make_float3(b, sign + (d.y * d.y) * a, -d.y);
+  float ca = st * cp, cb = st * sp;
+  float3 o = make_float3((t1.x * ca + t2.x * cb) + d.x * mu, (t1.y * ca + t2.y * cb) + d.y * mu,
+                         (t1.z * ca + t2.z * cb) + d.z * mu);
+  return normalize3(o);
+}
+
+// ---------------------------------------------------------------- host side
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+
+// Device-memory cache: blocks freed by the library are kept for reuse.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+#define TV_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return ::tv::fail(TET_ERR_DEVICE, std::string(#call) + ": " +   \
+                                            hipGetErrorString(e_));                        \
+  } while (0)
+
+// Camera frame / criterion quantities computed on the host in FP64.
+void make_frame(const tet_camera& c, Frame* fr);
+void make_camcrit(const tet_camera& c, float target_px, CamCrit* cc);
+int check_camera(const tet_camera* c);
+
+}  // namespace tv
+
+struct tet_grid {
+  int device;
+  int64_t n;
+  int32_t max_depth;
+  tet_build_stats stats;
+  uint64_t* ids;    // heap ids, depth-first order
+  uint64_t* keys;   // depth-first keys (sorted ascending)
+  uint64_t* verts;  // 4 packed lattice vertices per tet
+  tv::TetRec* rec;  // traversal records
+};

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Grids bit-exact (ids, neighbour links, vertices,
+extinction, majorant); images per the pixel bar in parity.py."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from parity import assert_grids_equal, assert_image_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tv():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_2506_11510_amd as tv
+    tv.lib()
+    return tv
+
+
+def gpu_build(tv, d, n, camera, build):
+    import torch
+    dt = torch.from_numpy(np.ascontiguousarray(d)).cuda()
+    return tv.leb_build(dt, n, camera, build=build)
+
+
+TINY = synthetic.scene("tiny")
+
+
+@pytest.fixture(scope="module")
+def tiny_density():
+    return TINY["density_fn"]()
+
+
+@pytest.mark.parametrize("depth", [0, 1, 2, 5, 9])
+def test_build_uniform_bitexact(tv, tiny_density, depth):
+    say(f"case build uniform depth {depth}")
+    b = dict(TINY["build"], uniform_depth=depth)
+    g = gpu_build(tv, tiny_density, 64, TINY["camera"], b)
+    o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
+    assert_grids_equal(g.export(), o.export(), f"uniform {depth}")
+    assert g.info()["max_depth"] == depth
+
+
+@pytest.mark.parametrize("seed,depth,thresh", [(0, 14, 40000), (1, 16, 30000), (2, 12, 60000), (3, 17, 22000)])
+def test_build_random_adaptive_bitexact(tv, tiny_density, seed, depth, thresh):
+    say(f"case build random seed {seed} depth {depth}")
+    b = dict(TINY["build"], want_mode=2, max_depth=depth, rand_seed=seed, rand_thresh=thresh)
+    g = gpu_build(tv, tiny_density, 64, TINY["camera"], b)
+    o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
+    assert_grids_equal(g.export(), o.export(), f"random {seed}")
+
+
+@pytest.mark.parametrize("maj,tau,tgt", [(1, 0.3, 2.0), (0, 0.1, 1.0), (1, 0.6, 0.5)])
+def test_build_criteria_bitexact(tv, maj, tau, tgt):
+    sc = synthetic.scene("blobs_adaptive")
+    d = sc["density_fn"]()
+    b = dict(sc["build"], majorant_mode=maj, variation_tau=tau, target_px=tgt)
+    say(f"case build criteria maj {maj} tau {tau} target {tgt}")
+    g = gpu_build(tv, d, 32, sc["camera"], b)
+    o = oracle.leb_build(d, 32, sc["camera"], b)
+    assert_grids_equal(g.export(), o.export(), "criteria")
+
+
+def test_locate_matches_oracle(tv, tiny_density):
+    say("case locate")
+    b = dict(TINY["build"], want_mode=2, max_depth=15, rand_seed=7, rand_thresh=40000)
+    g = gpu_build(tv, tiny_density, 64, TINY["camera"], b)
+    o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
+    rng = np.random.default_rng(0)
+    pts = rng.random((20000, 3)).astype(np.float32)
+    # points on lattice planes, edges and corners, and on the cube boundary
+    q = (rng.integers(0, 65, (4000, 3)) / 64.0).astype(np.float32)
+    pts = np.concatenate([pts, q, np.float32([[0, 0, 0], [1, 1, 1], [0.5, 0.5, 0.5], [1, 0, 0.25]])])
+    assert np.array_equal(g.locate(pts), o.locate(pts))
+
+
+def render_both(tv, g, o, sc, cam, spp, seed, ropts):
+    import torch
+    img, st = tv.render(g, cam, sc["medium"], sc["light"], spp, seed, ropts)
+    torch.cuda.synchronize()
+    ref, rst = o.render(cam, sc["medium"], sc["light"], spp, seed, ropts, threads=8)
+    return img.cpu().numpy(), st, ref, rst
+
+
+def test_render_tiny_parity(tv, tiny_density):
+    say("case render tiny 64x64 16spp")
+    sc = TINY
+    g = gpu_build(tv, tiny_density, 64, sc["camera"], sc["build"])
+    o = oracle.leb_build(tiny_density, 64, sc["camera"], sc["build"])
+    img, st, ref, rst = render_both(tv, g, o, sc, sc["camera"], 16, 1234, sc["render"])
+    assert_image_parity(img, ref, "tiny")
+    assert st["real_collisions"] > 0 and st["escapes"] > 0
+    # identical paths take identical numbers of steps (up to rare last-ulp
+    # differences of transcendental functions)
+    assert abs(st["tet_steps"] - rst["tet_steps"]) <= 1e-4 * rst["tet_steps"]
+
+
+@pytest.mark.parametrize("mode,per_item", [(0, 0), (1, 0), (2, 0), (0, 3)])
+def test_render_modes_parity(tv, mode, per_item):
+    """Loose majorants (null collisions), ratio / delta light transmittance,
+    and work items of a few samples accumulated with atomics."""
+    sc = synthetic.scene("blobs_adaptive")
+    d = sc["density_fn"]()
+    say(f"case render modes transmittance {mode} per_item {per_item}")
+    g = gpu_build(tv, d, 32, sc["camera"], sc["build"])
+    o = oracle.leb_build(d, 32, sc["camera"], sc["build"])
+    r = dict(sc["render"], transmittance=mode, samples_per_item=per_item)
+    img, st, ref, rst = render_both(tv, g, o, sc, sc["camera"], 8, 99, r)
+    assert_image_parity(img, ref, f"mode {mode}")
+    if mode == 0:
+        assert st["null_collisions"] > 0
+
+
+def test_render_ragged_sizes_and_offsets(tv, tiny_density):
+    """Image sizes that do not fill the 8x8 tiles, 1 spp, sample offsets."""
+    sc = TINY
+    g = gpu_build(tv, tiny_density, 64, sc["camera"], dict(sc["build"], uniform_depth=7))
+    o = oracle.leb_build(tiny_density, 64, sc["camera"], dict(sc["build"], uniform_depth=7))
+    for w, h, spp, off in [(1, 1, 1, 0), (13, 7, 3, 5), (70, 9, 2, 0)]:
+        say(f"case render ragged {w}x{h} spp {spp} offset {off}")
+        cam = dict(sc["camera"], width=w, height=h)
+        img, st, ref, rst = render_both(tv, g, o, sc, cam, spp, 7, dict(sc["render"], sample_offset=off))
+        assert_image_parity(img, ref, f"{w}x{h}")
+
+
+def test_dda_parity(tv):
+    import torch
+    say("case dda")
+    n = 32
+    d = synthetic.blobs(5, n)
+    cam = dict(pos=[0.3, 0.6, -1.5], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=40.0, width=40, height=32)
+    med = dict(albedo=0.9, g=0.3)
+    ropt = dict(max_bounces=8)
+    img, st = tv.dda_render(torch.from_numpy(d).cuda(), n, 1.5, cam, med, synthetic.LIGHT_DEFAULT, 8, 5, ropt)
+    ref, rst = oracle.dda_render(d, n, 1.5, cam, med, synthetic.LIGHT_DEFAULT, 8, 5, ropt, threads=8)
+    assert_image_parity(img.cpu().numpy(), ref, "dda")
+
+
+def test_build_errors(tv, tiny_density):
+    import torch
+    say("case build errors")
+    with pytest.raises(tv.TetError) as e:
+        gpu_build(tv, tiny_density, 64, TINY["camera"], dict(TINY["build"], max_tets=1000))
+    assert e.value.status == -3
+    bad = tiny_density.copy()
+    bad[77] = np.nan
+    with pytest.raises(tv.TetError) as e:
+        gpu_build(tv, bad, 64, TINY["camera"], TINY["build"])
+    assert e.value.status == -5
+    bad[77] = -2.0
+    with pytest.raises(tv.TetError) as e:
+        gpu_build(tv, bad, 64, TINY["camera"], TINY["build"])
+    assert e.value.status == -5
+    # host-side density gives the same grid as a device one
+    g1 = tv.leb_build(tiny_density, 64, TINY["camera"], build=TINY["build"])
+    g2 = gpu_build(tv, tiny_density, 64, TINY["camera"], TINY["build"])
+    assert np.array_equal(g1.export()["nbr"], g2.export()["nbr"])
+
+
+@pytest.mark.timeout(900)
+def test_cloud_full_size(tv):
+    """The benchmark workload: 256^3 fBm cloud, adaptive grid at 1 px,
+    1024^2, 32 spp, 32 bounces.  Grid bit-exact against the oracle's; image
+    checked on a strided pixel subset the oracle renders."""
+    import torch
+    sc = synthetic.scene("cloud")
+    d = sc["density_fn"]()
+    say("case cloud full size: gpu build")
+    g = gpu_build(tv, d, 256, sc["camera"], sc["build"])
+    say("case cloud full size: oracle build", g.info())
+    o = oracle.leb_build(d, 256, sc["camera"], sc["build"])
+    say("case cloud full size: compare grids")
+    assert_grids_equal(g.export(), o.export(), "cloud")
+    say("case cloud full size: gpu render")
+    img, st = tv.render(g, sc["camera"], sc["medium"], sc["light"], 32, 2024, sc["render"])
+    img = img.cpu().numpy().reshape(-1, 3)
+    say("case cloud full size: oracle subset", st)
+    pix = np.arange(0, 1024 * 1024, 4093, dtype=np.int32)
+    ref, rst = o.render(sc["camera"], sc["medium"], sc["light"], 32, 2024, sc["render"], pixels=pix, threads=8)
+    assert_image_parity(img[pix], ref, "cloud subset")
