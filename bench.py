@@ -1,0 +1,181 @@
+"""Benchmark: one step = the whole hot path on one MI355X -- LEB build of an
+adaptive conforming tet grid from a 256^3 fBm cloud density resident in HBM
+(1-pixel camera target), then a 1024 x 1024, 32 spp, 32-bounce render of it.
+
+Prints one JSON line.  `value` is Msamples/s of whole steps (build + render);
+tet-steps/s, render-only and build figures are reported beside it, with the
+render kernel's roofline fraction and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Msamples/s + tet-steps/s at 1024² 32spp; NRC vs plain speedup at equal RMSE"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_TET_STEP = 32  # algorithmic bytes per walk step (compact tet record)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_cloud1024_traffic.json")
+KERNEL_SOURCES = ["paper_2506_11510_amd/csrc/render.hip", "paper_2506_11510_amd/csrc/common.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per render launch from the committed rocprofv3 counter runs,
+    or None when the kernel source changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(sc, d, n_threads: int) -> dict:
+    """The oracle, as it stands, on a bounded sample of the step: its full
+    LEB build (single thread) and a strided subset of the image's pixels at
+    full spp (OpenMP threads); the render time is scaled to the full image."""
+    import numpy as np
+    import oracle
+    cam = sc["camera"]
+    t0 = time.perf_counter()
+    g = oracle.leb_build(d, sc["n"], cam, sc["build"])
+    t_build = time.perf_counter() - t0
+    W, H = cam["width"], cam["height"]
+    stride = 1021
+    pix = np.arange(0, W * H, stride, dtype=np.int32)
+    t0 = time.perf_counter()
+    _, st = g.render(cam, sc["medium"], sc["light"], sc["render"]["spp"], 2024, sc["render"], pixels=pix,
+                     threads=n_threads)
+    t_render = time.perf_counter() - t0
+    t_render_full = t_render * (W * H) / len(pix)
+    samples = W * H * sc["render"]["spp"]
+    return {"value": samples / (t_build + t_render_full) / 1e6, "unit": "Msamples/s", "cores": n_threads,
+            "kind": "oracle",
+            "sample": (f"oracle LEB build of the full grid ({g.num_tets} tets, 1 thread, {t_build:.1f} s) + render "
+                       f"of every {stride}th pixel ({len(pix)} px x {sc['render']['spp']} spp, {n_threads} threads, "
+                       f"{t_render:.1f} s, {st['tet_steps']} tet steps) scaled to {W}x{H}; host: {cpu_model()}"),
+            "build_s": t_build, "render_s_full_image": t_render_full,
+            "tet_steps_per_s": st["tet_steps"] / t_render}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--render-only", action="store_true", help="time only the render (grid built once)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the method's hot path is "
+              "single-GPU here; sharding across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    import paper_2506_11510_amd as tv
+
+    sc = synthetic.scene("cloud")
+    cam, spp = sc["camera"], sc["render"]["spp"]
+    d = sc["density_fn"]()
+    dev = torch.from_numpy(d).cuda()
+    out = torch.empty((cam["height"], cam["width"], 3), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(seed):
+        g = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+        _, st = tv.render(g, cam, sc["medium"], sc["light"], spp, seed, sc["render"], out=out)
+        return g, st
+
+    grid = None
+    if args.render_only:
+        grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+    for i in range(args.warmup):
+        if args.render_only:
+            tv.render(grid, cam, sc["medium"], sc["light"], spp, 100 + i, sc["render"], out=out)
+        else:
+            step(100 + i)
+    torch.cuda.synchronize()
+    build_ms, render_ms, tet_steps, infos = [], [], [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        if args.render_only:
+            _, st = tv.render(grid, cam, sc["medium"], sc["light"], spp, 1000 + i, sc["render"], out=out)
+            info = grid.info()
+        else:
+            g, st = step(1000 + i)
+            info = g.info()
+        build_ms.append(info["ms"])
+        render_ms.append(st["ms"])
+        tet_steps.append(st["tet_steps"])
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    samples = cam["width"] * cam["height"] * spp
+    value = samples / (ms_per_step / 1e3) / 1e6
+    mean_render_ms = float(np.mean(render_ms))
+    mean_steps = float(np.mean(tet_steps))
+    achieved = mean_steps * BYTES_PER_TET_STEP / (mean_render_ms / 1e3) / 1e9
+    img = out.cpu().numpy()
+    res = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256^3 fBm cloud (seed 1, 20% occupancy, sigma_t max 20) -> adaptive LEB grid "
+                               "(1 px target, tau 0.2, depth <= 24) -> 1024x1024, 32 spp, 32 bounces, albedo 0.9, "
+                               "HG g 0.3, sun + env, analytic light transmittance",
+                   "step": "render only" if args.render_only else "leb_build + tet_render",
+                   "num_tets": infos[-1]["num_tets"], "max_depth": infos[-1]["max_depth"],
+                   "build_rounds": infos[-1]["rounds"], "parallelism": "1 GPU"},
+        "tet_steps_per_s": round(mean_steps / (mean_render_ms / 1e3), 1),
+        "render_ms": round(mean_render_ms, 3), "build_ms": round(float(np.mean(build_ms)), 3),
+        "render_only_msamples_per_s": round(samples / (mean_render_ms / 1e3) / 1e6, 3),
+        "tet_steps_per_frame": int(mean_steps),
+        "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated")},
+        "image_mean": float(img.mean()),
+        "roofline": {"bound": "hbm", "kernel": "k_render<TetMedium>", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(),
+                     "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        n_threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        res["cpu_baseline"] = cpu_baseline(sc, d, n_threads)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -101,6 +101,8 @@ typedef struct {
   int32_t samples_per_item;   /* samples one lane takes at a time (0 = all of a pixel) */
   int32_t block_size;         /* threads per block (0 = tuned default) */
   int32_t blocks_per_cu;      /* persistent blocks per compute unit (0 = default) */
+  int32_t event_batch;        /* scatter events wait for this many lanes of a wave (0 = default, 1..64) */
+  int32_t reserved;
 } tet_render_opts;
 
 typedef struct {
@@ -109,7 +111,8 @@ typedef struct {
   int64_t real_collisions;
   int64_t escapes;
   int64_t truncated;       /* paths stopped by max_steps_per_path */
-  double ms;               /* device time of the render kernels */
+  double ms;               /* device time of the whole render call */
+  double trace_ms;         /* device time of the persistent tracing kernel(s) alone */
 } tet_render_stats;
 
 typedef struct {

@@ -25,9 +25,14 @@
  * normals let the direction rule faces out, leaving at most 3): for a face
  * with outward normal n (entries -1, 0, 1) and offset o_f,
  *   den = (n.x d.x + n.y d.y) + n.z d.z,  only den > 0 can be an exit,
- *   t   = (o_f 2^-20 - ((n.x o.x + n.y o.y) + n.z o.z)) / den,
- * all in FP32 in exactly this order; the exit is the smallest t (lowest face
- * index on ties), never less than the current t.
+ *   num = o_f 2^-20 - ((n.x o.x + n.y o.y) + n.z o.z),  t = num / den,
+ * num and den in FP32 in exactly this order; the exit face is the one with
+ * the smallest exact quotient num / den (lowest face index on ties; the
+ * comparison num_f den_g < num_g den_f is exact in FP64), and the exit
+ * distance is the correctly rounded FP32 quotient of that face, never less
+ * than the current t.  (Rounding is monotone, so this distance is also the
+ * minimum of the rounded quotients; only the choice between faces whose
+ * quotients round to the same float is made exactly.)
  *
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
  * seed, counter = (pixel, sample, (bounce << 8) | stream, draw >> 2), word
@@ -244,7 +249,8 @@ typedef struct {
   float scale;
 } medium_t;
 
-/* Exit of cell `cell` along (o, d) from parameter t.  Returns the exit face
+/* Exit of cell `cell` along (o, d) from parameter t (face rule in the file
+ * header).  Returns the exit face
  * (tets: 0..3, voxels: axis 0..2) or -1, with *te the exit parameter and
  * *next the next cell (-1 = leaves the grid). */
 static int cell_exit(const medium_t* m, int64_t cell, const float o[3], const float d[3], float t, float* te,
@@ -252,7 +258,7 @@ static int cell_exit(const medium_t* m, int64_t cell, const float o[3], const fl
   if (m->kind == 0) {
     const ogrid* g = m->g;
     int best = -1;
-    float bt = 0.0f;
+    float bnum = 0.0f, bden = 1.0f;
     for (int f = 0; f < 4; f++) {
       int code = g->codes[4 * cell + f];
       const int32_t* dir = or_dirs[code >> 1];
@@ -261,13 +267,16 @@ static int cell_exit(const medium_t* m, int64_t cell, const float o[3], const fl
       float den = (n0 * d[0] + n1 * d[1]) + n2 * d[2];
       if (!(den > 0.0f)) continue;
       float num = ldexpf((float)g->offsets[4 * cell + f], -OR_LAT_BITS) - ((n0 * o[0] + n1 * o[1]) + n2 * o[2]);
-      float tf = num / den;
-      if (best < 0 || tf < bt) {
+      /* exact comparison of num/den with the best so far: FP64 products of
+       * FP32 values are exact */
+      if (best < 0 || (double)num * (double)bden < (double)bnum * (double)den) {
         best = f;
-        bt = tf;
+        bnum = num;
+        bden = den;
       }
     }
     if (best < 0) return -1;
+    float bt = bnum / bden;
     *te = bt > t ? bt : t;
     uint32_t nb = g->nbr[4 * cell + best];
     *next = nb == OR_BOUNDARY ? -1 : (int64_t)(nb >> 2);

@@ -43,8 +43,11 @@ class Grid:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().tet_grid_free(h)
             self._h = None
+            try:
+                lib().tet_grid_free(h)
+            except Exception:  # interpreter shutdown: the library is already gone
+                pass
 
     @property
     def handle(self):

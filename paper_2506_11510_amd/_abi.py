@@ -52,13 +52,13 @@ class TetRenderOpts(ctypes.Structure):
     _fields_ = [("max_bounces", ctypes.c_int32), ("transmittance", ctypes.c_int32),
                 ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32),
                 ("samples_per_item", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("event_batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class TetRenderStats(ctypes.Structure):
     _fields_ = [("tet_steps", ctypes.c_int64), ("null_collisions", ctypes.c_int64),
                 ("real_collisions", ctypes.c_int64), ("escapes", ctypes.c_int64), ("truncated", ctypes.c_int64),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("trace_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -155,6 +155,6 @@ def make_render_opts(r: dict | None) -> TetRenderOpts:
     o = TetRenderOpts()
     lib().tet_render_opts_defaults(ctypes.byref(o))
     for k, v in (r or {}).items():
-        if hasattr(o, k):
+        if hasattr(o, k) and k != "reserved":
             setattr(o, k, type(getattr(o, k))(v))
     return o

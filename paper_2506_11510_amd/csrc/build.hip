@@ -368,11 +368,15 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
 // ---------------------------------------------------------------- finalize
 __global__ void k_keys(int64_t n, const uint64_t* __restrict__ ids, uint64_t* __restrict__ keys, int* maxd) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t id = ids[i];
-  int d = id_depth(id);
-  keys[i] = id << (60 - d);
-  atomicMax(maxd, d);
+  int d = 0;
+  if (i < n) {
+    uint64_t id = ids[i];
+    d = id_depth(id);
+    keys[i] = id << (60 - d);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
+  if (__lane_id() == 0) atomicMax(maxd, d);
 }
 
 // Root Kuhn tets: vertex 1 = S e_p0, vertex 2 = S (e_p0 + e_p1), over the

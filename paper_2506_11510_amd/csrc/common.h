@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/tetvol.h"
+#include "tetvol.h"
 
 namespace tv {
 
@@ -103,14 +103,25 @@ __device__ inline uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
-// Uniform in [0,1) with 24 bits: counter (pixel, sample, bounce << 8 | stream,
+// 24-bit uniform in [0,1) from a 32-bit word.
+__device__ inline float u01(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// Draw `draw` of a stream: counter (pixel, sample, bounce << 8 | stream,
 // draw >> 2), word draw & 3.
 __device__ inline float uniform01(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t bounce, uint32_t stream,
                                   uint32_t draw) {
   uint4 r = philox10(make_uint4(pixel, sample, (bounce << 8) | stream, draw >> 2), (uint32_t)seed,
                      (uint32_t)(seed >> 32));
   uint32_t w = (draw & 3) == 0 ? r.x : (draw & 3) == 1 ? r.y : (draw & 3) == 2 ? r.z : r.w;
-  return (float)(w >> 8) * 0x1p-24f;
+  return u01(w);
+}
+
+// Words of draws `draw` and `draw + 1` (draw & 3 < 3: one Philox block).
+__device__ inline uint2 uniform01x2(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t bounce, uint32_t stream,
+                                    uint32_t draw) {
+  uint4 r = philox10(make_uint4(pixel, sample, (bounce << 8) | stream, draw >> 2), (uint32_t)seed,
+                     (uint32_t)(seed >> 32));
+  return (draw & 3) == 0 ? make_uint2(r.x, r.y) : ((draw & 3) == 1 ? make_uint2(r.y, r.z) : make_uint2(r.z, r.w));
 }
 
 enum { kStreamCamera = 0, kStreamFlight = 1, kStreamPhase = 2, kStreamLight = 3 };

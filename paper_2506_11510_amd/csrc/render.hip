@@ -2,12 +2,21 @@
 // (paper, "Volumetric Path Tracing": Algorithm 1 and "Path Tracing within
 // Tetrahedral Grids").
 //
-// One persistent kernel: every lane runs a small state machine over its own
-// paths (fetch work -> camera ray, grid entry and point location -> walk
-// steps of the main path -> walk steps of the light (shadow) ray -> ...).
-// Each loop iteration advances every busy lane by one cell, so lanes whose
-// paths have very different lengths stay busy; idle lanes take new work
-// items from a device counter with one atomic per wave (ballot + popcount).
+// Two kernels per pass of samples:
+//   k_raygen  -- one thread per (pixel, sample): camera ray, entry into the
+//                grid, point location and the first free-flight depth,
+//                written as a 32-byte entry record (coherent, no divergence
+//                beyond the point-location search);
+//   k_render  -- persistent: every lane runs a small state machine over its
+//                own paths (fetch work -> load an entry -> walk steps of the
+//                main path -> walk steps of the light (shadow) ray ->
+//                scatter).  Each loop iteration advances every walking lane
+//                by one cell, so lanes whose paths differ in length stay
+//                busy; idle lanes take new work items from a device counter
+//                with one atomic per wave (ballot + popcount).  Scatter
+//                events (light estimate, phase sampling, new free flight:
+//                FP64 transcendentals) are deferred and run for many lanes
+//                at once, so a wave does not pay for them on every step.
 //
 // One walk step reads one 48-byte tet record (face plane offsets, face
 // normals in 6 bits each, 4 neighbour links, extinction, majorant) and
@@ -22,6 +31,7 @@
 // is the regular-grid reference renderer.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -29,27 +39,43 @@
 
 namespace tv {
 
+// Entry of one camera sample into the grid (32 bytes): entry point, tet
+// (kMiss if the ray misses the grid), direction, first free-flight depth.
+struct alignas(16) RayEntry {
+  float px, py, pz;
+  uint32_t cell;
+  float dx, dy, dz;
+  float tau;
+};
+constexpr uint32_t kMiss = 0xFFFFFFFFu;
+
 struct RenderArgs {
-  const TetRec* rec;
-  const uint64_t* keys;
-  int64_t n;
-  int32_t dmax;
-  const float* dens;  // voxel medium
-  int32_t nvox;
-  float scale;
   Frame fr;
   float albedo, g;
   float sun[3], E[3], env[3];
-  int32_t spp, sample_offset, per_item, items_per_pixel, max_bounces, transmittance;
-  int64_t max_steps;
+  int32_t spp;          // samples per pixel of the whole render (divisor)
+  int32_t pass_start;   // first sample index of this pass
+  int32_t pass_spp;     // samples of this pass
+  int32_t per_item, items_per_pixel, max_bounces, transmittance;
+  uint32_t max_steps;
+  int32_t event_batch;  // scatter events wait until this many lanes of a wave need one
   uint64_t seed;
-  uint32_t items;
+  uint32_t items, slots;
   int32_t tiles_x;
+  const RayEntry* entries;
   float* out;
   uint32_t* counter;
   unsigned long long* stats;
   int accumulate;
 };
+
+// pixel of a slot: 8x8 tiles in row-major tile order
+__device__ inline bool slot_pixel(uint32_t slot, int32_t tiles_x, int32_t w, int32_t h, int32_t& px, int32_t& py) {
+  uint32_t tile = slot >> 6, q = slot & 63u;
+  px = (int32_t)((tile % (uint32_t)tiles_x) * 8 + (q & 7u));
+  py = (int32_t)((tile / (uint32_t)tiles_x) * 8 + (q >> 3));
+  return px < w && py < h;
+}
 
 struct Step {
   float te, sigma, majorant;
@@ -141,37 +167,41 @@ struct TetMedium {
   int64_t n;
   int dmax;
   __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
+  // Exit of the tet along (o, d) from t: faces with n.d > 0 are candidates;
+  // the exit face has the smallest exact quotient num / den (compared by
+  // exact FP64 cross products, lowest face on ties); one FP32 division gives
+  // the exit distance.  Branchless, so the whole record is loaded at once.
   __device__ inline Step step(uint32_t cell, float3 o, float3 d, float t) const {
     const float4* q = (const float4*)(rec + cell);
-    float4 offs = q[0];
-    uint4 nb = *(const uint4*)(q + 1);
-    float4 w = q[2];
-    uint32_t normals = __float_as_uint(w.x);
-    const float off[4] = {offs.x, offs.y, offs.z, offs.w};
-    int best = -1;
-    float bt = 0.0f;
+    const float4 r0 = q[0], r1 = q[1], r2 = q[2];
+    const uint32_t normals = __float_as_uint(r2.x);
+    const float off[4] = {r0.x, r0.y, r0.z, r0.w};
+    const uint32_t link[4] = {__float_as_uint(r1.x), __float_as_uint(r1.y), __float_as_uint(r1.z),
+                              __float_as_uint(r1.w)};
+    bool any = false;
+    float bnum = 0.0f, bden = 1.0f;
+    uint32_t blink = kBoundary;
 #pragma unroll
     for (int f = 0; f < 4; f++) {
       uint32_t c = (normals >> (6 * f)) & 63u;
       float nx = (float)((int)(c & 3u) - 1), ny = (float)((int)((c >> 2) & 3u) - 1),
             nz = (float)((int)((c >> 4) & 3u) - 1);
       float den = (nx * d.x + ny * d.y) + nz * d.z;
-      if (den > 0.0f) {
-        float num = off[f] - ((nx * o.x + ny * o.y) + nz * o.z);
-        float tf = num / den;
-        if (best < 0 || tf < bt) {
-          best = f;
-          bt = tf;
-        }
-      }
+      float num = off[f] - ((nx * o.x + ny * o.y) + nz * o.z);
+      bool cand = den > 0.0f;
+      bool better = cand && (!any || (double)num * (double)bden < (double)bnum * (double)den);
+      bnum = better ? num : bnum;
+      bden = better ? den : bden;
+      blink = better ? link[f] : blink;
+      any = any || cand;
     }
     Step s;
-    s.sigma = w.y;
-    s.majorant = w.z;
-    s.ok = best >= 0;
+    float bt = bnum / bden;
+    s.sigma = r2.y;
+    s.majorant = r2.z;
+    s.ok = any;
     s.te = bt > t ? bt : t;
-    uint32_t link = best == 0 ? nb.x : (best == 1 ? nb.y : (best == 2 ? nb.z : nb.w));
-    s.next = (!s.ok || link == kBoundary) ? -1 : (int32_t)(link >> 2);
+    s.next = (!any || blink == kBoundary) ? -1 : (int32_t)(blink >> 2);
     return s;
   }
 };
@@ -267,21 +297,53 @@ __device__ inline bool enter_cube(float3 o, float3 d, float3& p) {
   return true;
 }
 
-// ---------------------------------------------------------------- kernel
-enum { M_FETCH = 0, M_START = 1, M_TRACK = 2, M_SHADOW = 3, M_DONE = 4 };
+// ---------------------------------------------------------------- kernels
+template <class Med>
+__global__ __launch_bounds__(256) void k_raygen(RenderArgs A, Med med, RayEntry* __restrict__ entries) {
+  uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (uint64_t)A.slots * (uint64_t)A.pass_spp) return;
+  uint32_t slot = (uint32_t)(e / (uint32_t)A.pass_spp);
+  uint32_t s = (uint32_t)(A.pass_start + (int32_t)(e % (uint32_t)A.pass_spp));
+  int32_t px, py;
+  if (!slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) return;
+  uint32_t pix = (uint32_t)(py * A.fr.w + px);
+  uint2 u = uniform01x2(A.seed, pix, s, 0, kStreamCamera, 0);
+  float u0 = u01(u.x), u1 = u01(u.y);
+  float sx = ((2.0f * (((float)px + u0) / (float)A.fr.w)) - 1.0f) * A.fr.tan_x;
+  float sy = (1.0f - 2.0f * (((float)py + u1) / (float)A.fr.h)) * A.fr.tan_y;
+  float3 o = make_float3(A.fr.pos[0], A.fr.pos[1], A.fr.pos[2]);
+  float3 d = normalize3(make_float3((A.fr.f[0] + sx * A.fr.r[0]) + sy * A.fr.u[0],
+                                    (A.fr.f[1] + sx * A.fr.r[1]) + sy * A.fr.u[1],
+                                    (A.fr.f[2] + sx * A.fr.r[2]) + sy * A.fr.u[2]));
+  float3 p = o;
+  int64_t c = -1;
+  if (enter_cube(o, d, p)) c = med.locate(p);
+  RayEntry r;
+  r.px = p.x;
+  r.py = p.y;
+  r.pz = p.z;
+  r.cell = c < 0 ? kMiss : (uint32_t)c;
+  r.dx = d.x;
+  r.dy = d.y;
+  r.dz = d.z;
+  r.tau = c < 0 ? 0.0f : exp_tau(uniform01(A.seed, pix, s, 0, kStreamFlight, 0));
+  entries[e] = r;
+}
+
+enum { M_FETCH = 0, M_START = 1, M_TRACK = 2, M_SHADOW = 3, M_SCATTER = 4, M_DONE = 5 };
 
 template <class Med>
 __global__ __launch_bounds__(256) void k_render(RenderArgs A, Med med) {
   const int lane = __lane_id();
   int mode = M_FETCH;
-  uint32_t pix = 0;
+  uint32_t pix = 0, slot = 0;
   int32_t s = 0, s_end = 0;
-  float3 o = make_float3(0, 0, 0), d = o, dsave = o, beta = o, L = o, acc = o;
-  float t = 0.0f, tau = 0.0f, od = 0.0f, tr = 1.0f;
-  uint32_t cell = 0, cell_x = 0, bounce = 0, jf = 0, jn = 0;
-  int64_t steps = 0;
-  unsigned long long c_steps = 0;
-  uint32_t c_null = 0, c_real = 0, c_esc = 0, c_trunc = 0;
+  float3 o = make_float3(0, 0, 0), d = o, dsave = o, L = o, acc = o;
+  float beta = 1.0f, t = 0.0f, tau = 0.0f, od = 0.0f;
+  uint32_t cell = 0, cell_x = 0, bounce = 0, jf = 0, jn = 0, steps = 0;
+  // per-wave counters (uniform) and the per-lane null-collision count
+  unsigned long long c_steps = 0, c_real = 0, c_esc = 0, c_trunc = 0;
+  uint32_t n_null = 0;
   const float3 sun = make_float3(A.sun[0], A.sun[1], A.sun[2]);
 
   for (;;) {
@@ -298,14 +360,13 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs A, Med med) {
         if (item >= A.items) {
           mode = M_DONE;
         } else {
-          uint32_t slot = item / (uint32_t)A.items_per_pixel, chunk = item % (uint32_t)A.items_per_pixel;
-          uint32_t tile = slot >> 6, w = slot & 63u;
-          int32_t px = (int32_t)((tile % (uint32_t)A.tiles_x) * 8 + (w & 7u));
-          int32_t py = (int32_t)((tile / (uint32_t)A.tiles_x) * 8 + (w >> 3));
-          if (px < A.fr.w && py < A.fr.h) {
+          slot = item / (uint32_t)A.items_per_pixel;
+          uint32_t chunk = item % (uint32_t)A.items_per_pixel;
+          int32_t px, py;
+          if (slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
             pix = (uint32_t)(py * A.fr.w + px);
-            s = A.sample_offset + (int32_t)chunk * A.per_item;
-            s_end = min(s + A.per_item, A.sample_offset + A.spp);
+            s = A.pass_start + (int32_t)chunk * A.per_item;
+            s_end = min(s + A.per_item, A.pass_start + A.pass_spp);
             acc = make_float3(0, 0, 0);
             mode = M_START;
           }
@@ -315,159 +376,148 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs A, Med med) {
     if (__ballot(mode != M_DONE) == 0) break;
 
     bool finish = false;
-    // ---- new sample: camera ray, entry into the grid, point location
+    // ---- new sample: its precomputed entry into the grid
     if (mode == M_START) {
-      int32_t px = (int32_t)(pix % (uint32_t)A.fr.w), py = (int32_t)(pix / (uint32_t)A.fr.w);
-      float u0 = uniform01(A.seed, pix, (uint32_t)s, 0, kStreamCamera, 0);
-      float u1 = uniform01(A.seed, pix, (uint32_t)s, 0, kStreamCamera, 1);
-      float sx = ((2.0f * (((float)px + u0) / (float)A.fr.w)) - 1.0f) * A.fr.tan_x;
-      float sy = (1.0f - 2.0f * (((float)py + u1) / (float)A.fr.h)) * A.fr.tan_y;
-      o = make_float3(A.fr.pos[0], A.fr.pos[1], A.fr.pos[2]);
-      d = normalize3(make_float3((A.fr.f[0] + sx * A.fr.r[0]) + sy * A.fr.u[0],
-                                 (A.fr.f[1] + sx * A.fr.r[1]) + sy * A.fr.u[1],
-                                 (A.fr.f[2] + sx * A.fr.r[2]) + sy * A.fr.u[2]));
-      float3 p;
-      int64_t c = -1;
-      if (enter_cube(o, d, p)) c = med.locate(p);
-      if (c < 0) {
+      const float4* q = (const float4*)(A.entries + (size_t)slot * (uint32_t)A.pass_spp + (uint32_t)(s - A.pass_start));
+      float4 a = q[0], b = q[1];
+      uint32_t c = __float_as_uint(a.w);
+      if (c == kMiss) {
         L = make_float3(A.env[0], A.env[1], A.env[2]);
         finish = true;
       } else {
-        cell = (uint32_t)c;
-        o = p;
+        o = make_float3(a.x, a.y, a.z);
+        d = make_float3(b.x, b.y, b.z);
+        tau = b.w;
+        cell = c;
         t = 0.0f;
-        beta = make_float3(1.0f, 1.0f, 1.0f);
+        beta = 1.0f;
         L = make_float3(0, 0, 0);
         bounce = 0;
-        jf = 0;
+        jf = 1;  // flight draw 0 of bounce 0 made the entry's depth
         jn = 0;
         steps = 0;
-        tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, 0, kStreamFlight, jf++));
         mode = M_TRACK;
       }
     }
     // ---- one walk step (main path or light ray)
-    if (mode == M_TRACK || mode == M_SHADOW) {
-      bool shadow_done = false;
-      if (steps >= A.max_steps) {
-        c_trunc++;
-        finish = true;
-      } else {
-        Step st = med.step(cell, o, d, t);
-        steps++;
-        c_steps++;
-        if (mode == M_TRACK) {
-          if (!st.ok) {
-            L.x = L.x + beta.x * A.env[0];
-            L.y = L.y + beta.y * A.env[1];
-            L.z = L.z + beta.z * A.env[2];
-            c_esc++;
-            finish = true;
-          } else {
-            float sg = st.sigma, sb = st.majorant;
-            bool collided = false;
-            float tc = 0.0f;
-            if (sb > 0.0f) {
-              float dtau = sb * (st.te - t);
-              while (tau < dtau) {
-                tc = t + tau / sb;
-                bool real = true;
-                if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
-                if (real) {
-                  collided = true;
-                  break;
-                }
-                c_null++;
-                t = tc;
-                tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
-                dtau = sb * (st.te - t);
+    bool walking = mode == M_TRACK || mode == M_SHADOW;
+    bool escaped = false, collided = false, trunc = walking && steps >= A.max_steps;
+    c_steps += (unsigned long long)__popcll(__ballot(walking && !trunc));
+    if (trunc) {
+      finish = true;
+    } else if (walking) {
+      Step st = med.step(cell, o, d, t);
+      steps++;
+      if (mode == M_TRACK) {
+        if (!st.ok) {
+          escaped = true;
+        } else {
+          float sg = st.sigma, sb = st.majorant;
+          float tc = 0.0f;
+          if (sb > 0.0f) {
+            float dtau = sb * (st.te - t);
+            while (tau < dtau) {
+              tc = t + tau / sb;
+              bool real = true;
+              if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
+              if (real) {
+                collided = true;
+                break;
               }
-              if (!collided) tau = tau - dtau;
+              n_null++;
+              t = tc;
+              tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
+              dtau = sb * (st.te - t);
             }
-            if (collided) {
-              c_real++;
-              float3 x = make_float3(o.x + tc * d.x, o.y + tc * d.y, o.z + tc * d.z);
-              bounce++;
-              jf = 0;
-              jn = 0;
-              beta.x = beta.x * A.albedo;
-              beta.y = beta.y * A.albedo;
-              beta.z = beta.z * A.albedo;
-              dsave = d;
-              o = x;
-              d = sun;
-              t = 0.0f;
-              cell_x = cell;
-              od = 0.0f;
-              tr = 1.0f;
-              if (A.transmittance != 0) tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
-              mode = M_SHADOW;
-            } else {
-              t = st.te;
-              if (st.next < 0) {
-                L.x = L.x + beta.x * A.env[0];
-                L.y = L.y + beta.y * A.env[1];
-                L.z = L.z + beta.z * A.env[2];
-                c_esc++;
-                finish = true;
-              } else {
-                cell = (uint32_t)st.next;
-              }
-            }
+            if (!collided) tau = tau - dtau;
           }
-        } else {  // light ray
-          if (!st.ok) {
-            shadow_done = true;
+          if (collided) {
+            float3 x = make_float3(o.x + tc * d.x, o.y + tc * d.y, o.z + tc * d.z);
+            bounce++;
+            jf = 0;
+            jn = 0;
+            beta = beta * A.albedo;
+            dsave = d;
+            o = x;
+            d = sun;
+            t = 0.0f;
+            cell_x = cell;
+            od = A.transmittance == 0 ? 0.0f : 1.0f;
+            if (A.transmittance != 0) tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+            mode = M_SHADOW;
           } else {
-            float sg = st.sigma, sb = st.majorant;
-            if (A.transmittance == 0) {
-              od = od + sg * (st.te - t);
-            } else if (sb > 0.0f) {
-              float dtau = sb * (st.te - t);
-              while (tau < dtau) {
-                t = t + tau / sb;
-                if (A.transmittance == 1) {
-                  tr = tr * (1.0f - sg / sb);
-                } else {
-                  bool real = true;
-                  if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++) < sg / sb;
-                  if (real) {
-                    tr = 0.0f;
-                    shadow_done = true;
-                    break;
-                  }
-                }
-                tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
-                dtau = sb * (st.te - t);
-              }
-              if (!shadow_done) tau = tau - dtau;
-            }
-            if (A.transmittance == 1 && tr == 0.0f) shadow_done = true;
-            if (!shadow_done) {
-              t = st.te;
-              if (st.next < 0) shadow_done = true;
-              else cell = (uint32_t)st.next;
-            }
+            t = st.te;
+            if (st.next < 0) escaped = true;
+            else cell = (uint32_t)st.next;
           }
         }
-      }
-      if (shadow_done) {
-        float Tr = A.transmittance == 0 ? (float)exp(-(double)od) : tr;
-        float mu = (dsave.x * sun.x + dsave.y * sun.y) + dsave.z * sun.z;
-        float ph = hg_pdf(A.g, mu);
-        L.x = L.x + ((beta.x * ph) * A.E[0]) * Tr;
-        L.y = L.y + ((beta.y * ph) * A.E[1]) * Tr;
-        L.z = L.z + ((beta.z * ph) * A.E[2]) * Tr;
-        if ((int32_t)bounce >= A.max_bounces) {
+        if (escaped) {  // left the grid: the environment
+          L.x = L.x + beta * A.env[0];
+          L.y = L.y + beta * A.env[1];
+          L.z = L.z + beta * A.env[2];
           finish = true;
-        } else {
-          float v1 = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamPhase, 0);
-          float v2 = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamPhase, 1);
-          d = hg_scatter(dsave, A.g, v1, v2);
-          t = 0.0f;
-          cell = cell_x;
-          tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
-          mode = M_TRACK;
+        }
+      } else {  // light ray: od holds the optical depth (analytic) or the transmittance
+        bool done = !st.ok;
+        if (st.ok) {
+          float sg = st.sigma, sb = st.majorant;
+          if (A.transmittance == 0) {
+            od = od + sg * (st.te - t);
+          } else if (sb > 0.0f) {
+            float dtau = sb * (st.te - t);
+            while (tau < dtau) {
+              t = t + tau / sb;
+              if (A.transmittance == 1) {
+                od = od * (1.0f - sg / sb);
+              } else {
+                bool real = true;
+                if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++) < sg / sb;
+                if (real) {
+                  od = 0.0f;
+                  done = true;
+                  break;
+                }
+              }
+              tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+              dtau = sb * (st.te - t);
+            }
+            if (!done) tau = tau - dtau;
+          }
+          if (A.transmittance == 1 && od == 0.0f) done = true;
+          if (!done) {
+            t = st.te;
+            if (st.next < 0) done = true;
+            else cell = (uint32_t)st.next;
+          }
+        }
+        if (done) mode = M_SCATTER;
+      }
+    }
+    c_trunc += (unsigned long long)__popcll(__ballot(trunc));
+    c_esc += (unsigned long long)__popcll(__ballot(escaped));
+    c_real += (unsigned long long)__popcll(__ballot(collided));
+    // ---- scatter events, run for many lanes at once
+    unsigned long long sm = __ballot(mode == M_SCATTER);
+    if (sm) {
+      unsigned long long busy = __ballot(mode == M_TRACK || mode == M_SHADOW || mode == M_START);
+      if (__popcll(sm) >= A.event_batch || busy == 0) {
+        if (mode == M_SCATTER) {
+          float Tr = A.transmittance == 0 ? (float)exp(-(double)od) : od;
+          float mu = (dsave.x * sun.x + dsave.y * sun.y) + dsave.z * sun.z;
+          float ph = hg_pdf(A.g, mu);
+          L.x = L.x + ((beta * ph) * A.E[0]) * Tr;
+          L.y = L.y + ((beta * ph) * A.E[1]) * Tr;
+          L.z = L.z + ((beta * ph) * A.E[2]) * Tr;
+          if ((int32_t)bounce >= A.max_bounces) {
+            finish = true;
+          } else {
+            uint2 v = uniform01x2(A.seed, pix, (uint32_t)s, bounce, kStreamPhase, 0);
+            d = hg_scatter(dsave, A.g, u01(v.x), u01(v.y));
+            t = 0.0f;
+            cell = cell_x;
+            tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
+            mode = M_TRACK;
+          }
         }
       }
     }
@@ -494,14 +544,15 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs A, Med med) {
       }
     }
   }
-  // ---- counters: wave reduction, one atomic per wave and counter
-  unsigned long long v[5] = {c_steps, c_null, c_real, c_esc, c_trunc};
+  unsigned long long nn = n_null;
 #pragma unroll
-  for (int q = 0; q < 5; q++) {
-    unsigned long long x = v[q];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0 && x) atomicAdd(A.stats + q, x);
+  for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+  if (lane == 0) {
+    if (c_steps) atomicAdd(A.stats + 0, c_steps);
+    if (nn) atomicAdd(A.stats + 1, nn);
+    if (c_real) atomicAdd(A.stats + 2, c_real);
+    if (c_esc) atomicAdd(A.stats + 3, c_esc);
+    if (c_trunc) atomicAdd(A.stats + 4, c_trunc);
   }
 }
 
@@ -529,6 +580,80 @@ __global__ void k_locate(TetMedium med, const float* __restrict__ pts, int64_t c
 }
 
 // ---------------------------------------------------------------- host
+static int cu_count() {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                 hipSuccess && n > 0)
+      cached = n;
+    else
+      return 256;
+  }
+  return cached;
+}
+
+constexpr int64_t kMaxEntriesPerPass = 1ll << 25;  // 1 GiB of entry records
+
+template <class Med>
+static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, int32_t spp, int64_t npix,
+                      char* sc, RayEntry* entries, int64_t pass_cap, hipStream_t st, float* ms_total,
+                      float* ms_trace) {
+  int bs = o.block_size ? o.block_size : 256;
+  int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
+  hipEvent_t e0, e1, t0, t1;
+  TV_HIP(hipEventCreate(&e0));
+  TV_HIP(hipEventCreate(&e1));
+  TV_HIP(hipEventCreate(&t0));
+  TV_HIP(hipEventCreate(&t1));
+  struct Ev {
+    hipEvent_t a, b, c, d;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      (void)hipEventDestroy(c);
+      (void)hipEventDestroy(d);
+    }
+  } ev{e0, e1, t0, t1};
+  *ms_total = 0.0f;
+  *ms_trace = 0.0f;
+  TV_HIP(hipEventRecord(e0, st));
+  if (A.accumulate)
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3);
+  for (int32_t done = 0; done < spp; done += (int32_t)pass_cap) {
+    A.pass_start = A.pass_start + (done ? (int32_t)pass_cap : 0);
+    A.pass_spp = (int32_t)std::min<int64_t>(pass_cap, spp - done);
+    int32_t per = std::min(A.per_item, A.pass_spp);
+    int32_t ipp = (A.pass_spp + per - 1) / per;
+    RenderArgs P = A;
+    P.per_item = per;
+    P.items_per_pixel = ipp;
+    P.items = A.slots * (uint32_t)ipp;
+    P.entries = entries;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 4);
+    uint64_t ne = (uint64_t)A.slots * (uint64_t)P.pass_spp;
+    hipLaunchKernelGGL(k_raygen<Med>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, P, med, entries);
+    int64_t grid = (int64_t)cu_count() * bpc;
+    int64_t need = ((int64_t)P.items + bs - 1) / bs;
+    grid = std::max<int64_t>(1, std::min(grid, need));
+    TV_HIP(hipEventRecord(t0, st));
+    hipLaunchKernelGGL(k_render<Med>, dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+    TV_HIP(hipGetLastError());
+    TV_HIP(hipEventRecord(t1, st));
+    TV_HIP(hipEventSynchronize(t1));
+    float ms = 0.0f;
+    TV_HIP(hipEventElapsedTime(&ms, t0, t1));
+    *ms_trace += ms;
+  }
+  if (A.accumulate)
+    hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3,
+                       (float)spp);
+  TV_HIP(hipEventRecord(e1, st));
+  TV_HIP(hipEventSynchronize(e1));
+  TV_HIP(hipEventElapsedTime(ms_total, e0, e1));
+  return TET_OK;
+}
+
 static int render_common(int kind, const tet_grid* g, const tet_density* dens, const tet_camera* cam,
                          const tet_medium* medm, const tet_light* light, int32_t spp, uint64_t seed,
                          const tet_render_opts* opts_in, float* out_rgb, int32_t on_device, hipStream_t st,
@@ -543,15 +668,17 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   else tet_render_opts_defaults(&o);
   if (o.max_bounces < 1 || o.transmittance < 0 || o.transmittance > 2 || o.max_steps_per_path < 1 ||
       o.sample_offset < 0 || o.samples_per_item < 0 || o.block_size < 0 || o.block_size > 1024 ||
-      (o.block_size % 64) != 0 || o.blocks_per_cu < 0)
+      (o.block_size % 64) != 0 || o.blocks_per_cu < 0 || o.event_batch < 0 || o.event_batch > 64)
     return fail(TET_ERR_INVALID_ARG, "render: bad options");
+  if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
   int64_t npix = (int64_t)cam->width * cam->height;
-  int per_item = (o.samples_per_item <= 0 || o.samples_per_item > spp) ? spp : o.samples_per_item;
-  int ipp = (spp + per_item - 1) / per_item;
   int tiles_x = (cam->width + 7) / 8, tiles_y = (cam->height + 7) / 8;
-  int64_t items = (int64_t)tiles_x * tiles_y * 64 * ipp;
-  if (items >= (1ll << 32) || npix > (1ll << 31) - 1)
-    return fail(TET_ERR_INVALID_ARG, "render: image too large");
+  int64_t slots = (int64_t)tiles_x * tiles_y * 64;
+  if (slots >= (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: image too large");
+  int64_t pass_cap = std::max<int64_t>(1, std::min<int64_t>(spp, kMaxEntriesPerPass / slots));
+  int per_item = (o.samples_per_item <= 0 || o.samples_per_item > pass_cap) ? (int)pass_cap : o.samples_per_item;
+  if (slots * ((pass_cap + per_item - 1) / per_item) >= (1ll << 32))
+    return fail(TET_ERR_INVALID_ARG, "render: too many work items");
 
   RenderArgs A;
   memset(&A, 0, sizeof(A));
@@ -564,20 +691,21 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     A.env[i] = light->env_radiance[i];
   }
   A.spp = spp;
-  A.sample_offset = o.sample_offset;
+  A.pass_start = o.sample_offset;
   A.per_item = per_item;
-  A.items_per_pixel = ipp;
   A.max_bounces = o.max_bounces;
   A.transmittance = o.transmittance;
-  A.max_steps = o.max_steps_per_path;
+  A.max_steps = (uint32_t)std::min<int64_t>(o.max_steps_per_path, 0x7FFFFFFF);
+  A.event_batch = o.event_batch ? o.event_batch : 16;
   A.seed = seed;
-  A.items = (uint32_t)items;
+  A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
-  A.accumulate = ipp > 1;
+  A.accumulate = (pass_cap < spp) || (per_item < pass_cap);
 
-  // scratch: counter + 5 stats + image when the output is on the host
+  // scratch: counters, entry records of one pass, image when the output is on the host
   size_t img_bytes = (size_t)npix * 3 * sizeof(float);
-  size_t scratch = 64 + (on_device ? 0 : img_bytes);
+  size_t ent_bytes = (size_t)slots * (size_t)pass_cap * sizeof(RayEntry);
+  size_t scratch = 256 + ent_bytes + (on_device ? 0 : img_bytes);
   char* sc = (char*)dev_alloc(scratch);
   if (!sc) return fail(TET_ERR_OUT_OF_MEMORY, "render: scratch");
   struct Free {
@@ -585,51 +713,25 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     ~Free() { dev_free(p); }
   } fr_{sc};
   A.counter = (uint32_t*)sc;
-  A.stats = (unsigned long long*)(sc + 16);
-  A.out = on_device ? out_rgb : (float*)(sc + 64);
+  A.stats = (unsigned long long*)(sc + 64);
+  RayEntry* entries = (RayEntry*)(sc + 256);
+  A.out = on_device ? out_rgb : (float*)(sc + 256 + ent_bytes);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
 
-  hipDeviceProp_t prop;
-  int dev = 0;
-  TV_HIP(hipGetDevice(&dev));
-  TV_HIP(hipGetDeviceProperties(&prop, dev));
-  int bs = o.block_size ? o.block_size : 256;
-  int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
-  int64_t grid = (int64_t)prop.multiProcessorCount * bpc;
-  int64_t need = (items + bs - 1) / bs;
-  if (grid > need) grid = need;
-  if (grid < 1) grid = 1;
-
-  hipEvent_t e0, e1;
-  TV_HIP(hipEventCreate(&e0));
-  TV_HIP(hipEventCreate(&e1));
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 16);
-  if (A.accumulate)
-    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3);
-  TV_HIP(hipEventRecord(e0, st));
+  float ms = 0.0f, ms_trace = 0.0f;
+  int rc;
   if (kind == 0) {
     TetMedium m{g->rec, g->keys, g->n, g->max_depth};
-    A.rec = g->rec;
-    A.keys = g->keys;
-    A.n = g->n;
-    A.dmax = g->max_depth;
-    hipLaunchKernelGGL(k_render<TetMedium>, dim3((unsigned)grid), dim3(bs), 0, st, A, m);
+    rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
   } else {
     VoxelMedium m{dens->data, dens->n, dens->density_scale};
-    hipLaunchKernelGGL(k_render<VoxelMedium>, dim3((unsigned)grid), dim3(bs), 0, st, A, m);
+    rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
   }
-  TV_HIP(hipGetLastError());
-  TV_HIP(hipEventRecord(e1, st));
-  if (A.accumulate)
-    hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3,
-                       (float)spp);
+  if (rc) return rc;
   unsigned long long hs[5] = {0, 0, 0, 0, 0};
   TV_HIP(hipMemcpyAsync(hs, A.stats, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (!on_device) TV_HIP(hipMemcpyAsync(out_rgb, A.out, img_bytes, hipMemcpyDeviceToHost, st));
   TV_HIP(hipStreamSynchronize(st));
-  float ms = 0.0f;
-  TV_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (stats) {
     stats->tet_steps = (int64_t)hs[0];
     stats->null_collisions = (int64_t)hs[1];
@@ -637,6 +739,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     stats->escapes = (int64_t)hs[3];
     stats->truncated = (int64_t)hs[4];
     stats->ms = ms;
+    stats->trace_ms = ms_trace;
   }
   return TET_OK;
 }

@@ -107,7 +107,7 @@ def scene(name: str, **over) -> dict:
                  camera=dict(pos=[0.5, 0.45, -0.9], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=45.0,
                              width=1024, height=1024),
                  medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
-                 build=dict(want_mode=0, uniform_depth=0, max_depth=24, majorant_mode=0, variation_tau=0.05,
+                 build=dict(want_mode=0, uniform_depth=0, max_depth=24, majorant_mode=0, variation_tau=0.2,
                             target_px=1.0, density_scale=1.0, max_tets=1 << 26),
                  render=dict(spp=32, max_bounces=32, transmittance=0, max_steps_per_path=1 << 20))
     elif name == "plume":
