@@ -99,10 +99,10 @@ typedef struct {
   int64_t max_steps_per_path; /* exit evaluations per path (all walks) */
   int32_t sample_offset;      /* render samples [offset, offset + spp) */
   int32_t samples_per_item;   /* samples one lane takes at a time (0 = all of a pixel) */
-  int32_t block_size;         /* threads per block (0 = tuned default) */
+  int32_t block_size;         /* threads per block: 64, 128, 192 or 256 (0 = default) */
   int32_t blocks_per_cu;      /* persistent blocks per compute unit (0 = default) */
-  int32_t event_batch;        /* scatter events wait for this many lanes of a wave (0 = default, 1..64) */
-  int32_t reserved;
+  int32_t waves_per_simd;     /* register budget of the tracing kernel: 4, 5, 6 or 8 waves (0 = default 6) */
+  int32_t record_layout;      /* tet records walked: 32 (compact), 48, or 0 = compact when the grid has them */
 } tet_render_opts;
 
 typedef struct {

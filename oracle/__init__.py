@@ -111,6 +111,12 @@ def lib():
         L.oracle_uniform.restype = ctypes.c_float
         L.oracle_hg_sample_mu.argtypes = [ctypes.c_float, ctypes.c_float]
         L.oracle_hg_sample_mu.restype = ctypes.c_float
+        L.oracle_neglog1m.argtypes = [ctypes.c_float]
+        L.oracle_neglog1m.restype = ctypes.c_float
+        L.oracle_expneg.argtypes = [ctypes.c_float]
+        L.oracle_expneg.restype = ctypes.c_float
+        L.oracle_sincos2pi.argtypes = [ctypes.c_float, vp, vp]
+        L.oracle_sincos2pi.restype = None
         L.oracle_hg_eval.argtypes = [ctypes.c_float, ctypes.c_float]
         L.oracle_hg_eval.restype = ctypes.c_float
         L.oracle_hg_direction.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
@@ -321,6 +327,20 @@ def uniform(seed, pixel, sample, bounce, stream, draw) -> float:
 
 def hg_sample_mu(g, u) -> float:
     return float(lib().oracle_hg_sample_mu(g, u))
+
+
+def neglog1m(u) -> float:
+    return float(lib().oracle_neglog1m(u))
+
+
+def expneg(x) -> float:
+    return float(lib().oracle_expneg(x))
+
+
+def sincos2pi(u):
+    c, s = ctypes.c_float(), ctypes.c_float()
+    lib().oracle_sincos2pi(u, ctypes.byref(c), ctypes.byref(s))
+    return c.value, s.value
 
 
 def hg_eval(g, mu) -> float:

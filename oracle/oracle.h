@@ -118,6 +118,9 @@ void  oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_
 float oracle_uniform(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t bounce,
                      uint32_t stream, uint32_t draw);
 float oracle_hg_sample_mu(float g, float u);
+float oracle_neglog1m(float u);
+float oracle_expneg(float x);
+void  oracle_sincos2pi(float u, float* c, float* s);
 float oracle_hg_eval(float g, float mu);
 void  oracle_hg_direction(const float d[3], float g, float u1, float u2, float out[3]);
 void  oracle_camera_ray(const ocam* cam, int32_t px, int32_t py, float u0, float u1,

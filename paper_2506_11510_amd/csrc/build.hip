@@ -487,7 +487,8 @@ __device__ inline bool face_normal(const int64_t v[4][3], int f, int un[3], int6
 
 __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
                            const uint64_t* __restrict__ keys, int dmax, Pyramid P, float scale, int majorant_mode,
-                           TetRec* __restrict__ rec, int* __restrict__ err) {
+                           TetRec* __restrict__ rec, TetRec32* __restrict__ rec32, int* __restrict__ err) {
+  int32_t ioff[4] = {0, 0, 0, 0};
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   uint64_t pv[4] = {verts[4 * t], verts[4 * t + 1], verts[4 * t + 2], verts[4 * t + 3]};
@@ -508,15 +509,21 @@ __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const ui
   double mean = s / c;
   r.sigma = (float)((double)scale * mean);
   r.majorant = majorant_mode == 1 ? (float)((double)scale * (double)mx) : r.sigma;
-  r.normals = 0;
+  r.codes = 0;
   r.pad = 0;
 #pragma unroll 1
   for (int f = 0; f < 4; f++) {
     int un[3];
     int64_t off;
-    if (!face_normal(v, f, un, off)) atomicOr(err, 2);
+    int code = -1;
+    if (face_normal(v, f, un, off)) code = dir_code(un);
+    if (code < 0) {
+      atomicOr(err, 2);
+      code = 0;
+    }
     r.off[f] = ldexpf((float)off, -kLatBits);
-    r.normals |= (uint32_t)((un[0] + 1) | ((un[1] + 1) << 2) | ((un[2] + 1) << 4)) << (6 * f);
+    r.codes |= (uint32_t)code << (8 * f);
+    ioff[f] = (int32_t)off;
     // boundary face: its three vertices share a coordinate equal to 0 or S
     int idx[3], q = 0;
     for (int j = 0; j < 4; j++)
@@ -576,6 +583,21 @@ __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const ui
     }
   }
   rec[t] = r;
+  if (rec32) {
+    TetRec32 c;
+    uint64_t lo = ((uint64_t)(ioff[0] & 0x7FFFFF)) | ((uint64_t)(ioff[1] & 0x7FFFFF) << 23) |
+                  ((uint64_t)(ioff[2] & 0x3FFFF) << 46);
+    uint64_t hi = ((uint64_t)(ioff[2] & 0x7FFFFF) >> 18) | ((uint64_t)(ioff[3] & 0x7FFFFF) << 5);
+    c.w[0] = (uint32_t)lo;
+    c.w[1] = (uint32_t)(lo >> 32);
+    c.w[2] = (uint32_t)hi;
+    c.w[3] = __float_as_uint(r.sigma);
+    for (int f = 0; f < 4; f++) {
+      uint32_t l = r.nbr[f] == kBoundary ? kLink27Boundary : (r.nbr[f] >> 2);
+      c.w[4 + f] = l | (((r.codes >> (8 * f)) & 31u) << 27);
+    }
+    rec32[t] = c;
+  }
 }
 
 // ---------------------------------------------------------------- host
@@ -808,7 +830,9 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   g->keys = (uint64_t*)dev_alloc(cur * 8);
   g->verts = (uint64_t*)dev_alloc(cur * 32);
   g->rec = (TetRec*)dev_alloc(cur * sizeof(TetRec));
-  if (!g->ids || !g->keys || !g->verts || !g->rec) {
+  bool compact = o.majorant_mode == 0 && cur <= kMaxTets32;
+  g->rec32 = compact ? (TetRec32*)dev_alloc(cur * sizeof(TetRec32)) : nullptr;
+  if (!g->ids || !g->keys || !g->verts || !g->rec || (compact && !g->rec32)) {
     tet_grid_free(g);
     return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: grid arrays");
   }
@@ -825,7 +849,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   }
   g->max_depth = flag;
   hipLaunchKernelGGL(k_finalize, dim3(nblocks(cur, 128)), dim3(128), 0, st, cur, g->ids, g->verts, g->keys,
-                     g->max_depth, P, dens->density_scale, o.majorant_mode, g->rec, d_flag + 2);
+                     g->max_depth, P, dens->density_scale, o.majorant_mode, g->rec, g->rec32, d_flag + 2);
   int ferr = 0;
   he = hipMemcpyAsync(&ferr, d_flag + 2, 4, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipEventRecord(e1, st);

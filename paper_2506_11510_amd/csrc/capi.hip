@@ -286,6 +286,7 @@ void tet_grid_free(tet_grid* g) {
   dev_free(g->keys);
   dev_free(g->verts);
   dev_free(g->rec);
+  dev_free(g->rec32);
   delete g;
 }
 

@@ -22,12 +22,54 @@ constexpr int kMaxLevels = 13;          // pyramid levels for n <= 4096
 struct alignas(16) TetRec {
   float off[4];      // face plane offsets n_f . v in world units
   uint32_t nbr[4];   // (index << 2) | back face, or kBoundary
-  uint32_t normals;  // 6 bits per face: (nx+1) | (ny+1) << 2 | (nz+1) << 4
+  uint32_t codes;    // byte f: orientation code 2 N + s of face f (outward normal = (-1)^s dir_N)
   float sigma;       // extinction
   float majorant;    // >= sigma
   uint32_t pad;
 };
 static_assert(sizeof(TetRec) == 48, "record size");
+
+// Compact traversal record, 32 bytes (two 16-byte loads, never straddling a
+// 64-byte sector); the same values as TetRec for grids of < 2^27 tets with
+// tight majorants:
+//   w[0..2]: the 4 plane offsets n_f . v in lattice units as 23-bit two's
+//            complement integers, packed little-endian at bits 0, 23, 46, 69
+//            (world offset = offset * 2^-20, exact in FP32);
+//   w[3]:    extinction (FP32 bits);
+//   w[4+f]:  neighbour index across face f (27 bits; kLink27Boundary on the
+//            boundary) | face f's orientation code << 27.
+struct alignas(32) TetRec32 {
+  uint32_t w[8];
+};
+static_assert(sizeof(TetRec32) == 32, "compact record size");
+constexpr uint32_t kLink27Boundary = (1u << 27) - 1;
+constexpr int64_t kMaxTets32 = (1ll << 27) - 1;
+
+// The 9 plane directions of these grids' faces; a face's outward normal is
+// +dir_N or -dir_N, its orientation code 2 N + (0 or 1).
+//   0 (1,0,0)  1 (0,1,0)  2 (0,0,1)  3 (1,1,0)  4 (1,-1,0)
+//   5 (1,0,1)  6 (1,0,-1) 7 (0,1,1)  8 (0,1,-1)
+__host__ __device__ inline int dir_code(const int un[3]) {
+  int s = 0, v[3] = {un[0], un[1], un[2]};
+  int first = v[0] != 0 ? v[0] : (v[1] != 0 ? v[1] : v[2]);
+  if (first < 0) {
+    s = 1;
+    v[0] = -v[0];
+    v[1] = -v[1];
+    v[2] = -v[2];
+  }
+  int N = -1;
+  if (v[0] == 1 && v[1] == 0 && v[2] == 0) N = 0;
+  else if (v[0] == 0 && v[1] == 1 && v[2] == 0) N = 1;
+  else if (v[0] == 0 && v[1] == 0 && v[2] == 1) N = 2;
+  else if (v[0] == 1 && v[1] == 1 && v[2] == 0) N = 3;
+  else if (v[0] == 1 && v[1] == -1 && v[2] == 0) N = 4;
+  else if (v[0] == 1 && v[1] == 0 && v[2] == 1) N = 5;
+  else if (v[0] == 1 && v[1] == 0 && v[2] == -1) N = 6;
+  else if (v[0] == 0 && v[1] == 1 && v[2] == 1) N = 7;
+  else if (v[0] == 0 && v[1] == 1 && v[2] == -1) N = 8;
+  return N < 0 ? -1 : 2 * N + s;
+}
 
 // Density pyramid: level 0 is the input volume; levels 1..L hold per cell
 // min, max (FP32) and the FP64 sum of its 8 children combined as
@@ -126,29 +168,74 @@ __device__ inline uint2 uniform01x2(uint64_t seed, uint32_t pixel, uint32_t samp
 
 enum { kStreamCamera = 0, kStreamFlight = 1, kStreamPhase = 2, kStreamLight = 3 };
 
-__device__ inline float exp_tau(float u) { return (float)(-log((double)(1.0f - u))); }
+// ---- FP32 elementary functions (explicit algorithms, fixed operation order)
+// -ln(1 - u): 1 - u = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+// s = (m - 1) / (m + 1), series to s^9; ln(1 - u) = e ln2 + ln m.
+__device__ inline float exp_tau(float u) {
+  float y = 1.0f - u;
+  uint32_t b = __float_as_uint(y);
+  int e = (int)((b >> 23) & 0xFFu) - 127;
+  float m = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
+  if (m > 1.41421354f) {
+    m = m * 0.5f;
+    e = e + 1;
+  }
+  float f = m - 1.0f;
+  float sv = f / (2.0f + f);
+  float z = sv * sv;
+  float lnm = 2.0f * sv + sv * z * (0.666666667f + z * (0.4f + z * (0.285714286f + z * 0.222222222f)));
+  float lny = (float)e * 0.693147182f + lnm;
+  return 0.0f - lny;
+}
+
+// e^-x for x >= 0: x = k ln2 + r (Cody-Waite, ln2 = 16-bit head + tail),
+// degree-7 Taylor polynomial of e^-r, times 2^-k.
+__device__ inline float exp_neg(float x) {
+  if (!(x < 104.0f)) return 0.0f;
+  int k = (int)(x * 1.44269504f + 0.5f);
+  float r = (x - (float)k * 0.693145752f) - (float)k * 1.42860677e-06f;
+  float y = 0.0f - r;
+  float p = 1.0f + y * (1.0f + y * (0.5f + y * (0.166666667f + y * (0.0416666667f + y * (0.00833333333f +
+            y * (0.00138888889f + y * 0.000198412698f))))));
+  return ldexpf(p, -k);
+}
+
+// (cos, sin)(2 pi u), u in [0,1): quadrant q = round(4u), theta = 2 pi (u -
+// q/4), Taylor polynomials to degree 12 / 11, rotated by q.
+__device__ inline void sincos_2pi(float u, float& c, float& s) {
+  int q = (int)(u * 4.0f + 0.5f);
+  float w = u - (float)q * 0.25f;
+  float th = w * 6.28318531f;
+  float z = th * th;
+  float sn = th * (1.0f + z * (-0.166666667f + z * (0.00833333333f + z * (-0.000198412698f +
+             z * (2.75573192e-06f + z * -2.50521084e-08f)))));
+  float cs = 1.0f + z * (-0.5f + z * (0.0416666667f + z * (-0.00138888889f + z * (2.48015873e-05f +
+             z * (-2.75573192e-07f + z * 2.08767570e-09f)))));
+  int r = q & 3;
+  c = r == 0 ? cs : (r == 1 ? 0.0f - sn : (r == 2 ? 0.0f - cs : sn));
+  s = r == 0 ? sn : (r == 1 ? cs : (r == 2 ? 0.0f - sn : 0.0f - cs));
+}
 
 // Henyey-Greenstein density of the cosine between successive propagation
-// directions, FP64 rounded once.
+// directions, FP32.
 __device__ inline float hg_pdf(float g, float mu) {
-  double gg = (double)g, m = (double)mu;
-  double g2 = gg * gg;
-  double den = (1.0 + g2) - (2.0 * gg) * m;
-  return (float)((1.0 - g2) / (((4.0 * 3.14159265358979323846) * den) * sqrt(den)));
+  float g2 = g * g;
+  float den = (1.0f + g2) - (2.0f * g) * mu;
+  return (1.0f - g2) / ((12.5663706f * den) * sqrtf(den));
 }
 
 // Inverse HG cumulative distribution (isotropic limit 2u - 1 for |g| < 1e-3).
 __device__ inline float hg_mu(float g, float u) {
-  double gg = (double)g, uu = (double)u, mu;
-  if (fabs(gg) < 1e-3) {
-    mu = 2.0 * uu - 1.0;
+  float mu;
+  if (fabsf(g) < 1e-3f) {
+    mu = 2.0f * u - 1.0f;
   } else {
-    double g2 = gg * gg;
-    double s = (1.0 - g2) / ((1.0 - gg) + (2.0 * gg) * uu);
-    mu = ((1.0 + g2) - s * s) / (2.0 * gg);
+    float g2 = g * g;
+    float sv = (1.0f - g2) / ((1.0f - g) + (2.0f * g) * u);
+    mu = ((1.0f + g2) - sv * sv) / (2.0f * g);
   }
-  mu = mu < -1.0 ? -1.0 : (mu > 1.0 ? 1.0 : mu);
-  return (float)mu;
+  mu = mu < -1.0f ? -1.0f : (mu > 1.0f ? 1.0f : mu);
+  return mu;
 }
 
 __device__ inline float3 normalize3(float3 v) {
@@ -163,8 +250,8 @@ __device__ inline float3 hg_scatter(float3 d, float g, float u1, float u2) {
   float q = 1.0f - mu * mu;
   q = q < 0.0f ? 0.0f : q;
   float st = sqrtf(q);
-  double phi = (2.0 * 3.14159265358979323846) * (double)u2;
-  float cp = (float)cos(phi), sp = (float)sin(phi);
+  float cp, sp;
+  sincos_2pi(u2, cp, sp);
   float sign = copysignf(1.0f, d.z);
   float a = -1.0f / (sign + d.z);
   float b = (d.x * d.y) * a;
@@ -206,5 +293,6 @@ struct tet_grid {
   uint64_t* ids;    // heap ids, depth-first order
   uint64_t* keys;   // depth-first keys (sorted ascending)
   uint64_t* verts;  // 4 packed lattice vertices per tet
-  tv::TetRec* rec;  // traversal records
+  tv::TetRec* rec;      // traversal records
+  tv::TetRec32* rec32;  // compact records (NULL when the grid cannot use them)
 };

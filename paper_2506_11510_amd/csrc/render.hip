@@ -13,15 +13,19 @@
 //                scatter).  Each loop iteration advances every walking lane
 //                by one cell, so lanes whose paths differ in length stay
 //                busy; idle lanes take new work items from a device counter
-//                with one atomic per wave (ballot + popcount).  Scatter
-//                events (light estimate, phase sampling, new free flight:
-//                FP64 transcendentals) are deferred and run for many lanes
-//                at once, so a wave does not pay for them on every step.
+//                with one atomic per wave (ballot + popcount).  All rare
+//                events (collision, light estimate and phase sampling,
+//                escape, end of sample, new work) sit in one section the
+//                wave enters only when some lane needs it; the common
+//                iteration is a bare walk step.
 //
 // One walk step reads one 48-byte tet record (face plane offsets, face
-// normals in 6 bits each, 4 neighbour links, extinction, majorant) and
-// evaluates only faces whose outward normal faces the ray (n.d > 0, at most
-// 3), in FP32 in a fixed order; the free flight is delta tracking against the
+// orientation codes, 4 neighbour links, extinction, majorant) and evaluates
+// only faces whose outward normal faces the ray (n.d > 0, at most 3).  The
+// dot products of the segment's origin and direction with the 9 possible
+// face directions are computed once per segment into a per-lane LDS table,
+// so a face costs one LDS read pair and a sign flip; every value is rounded
+// exactly as the direct FP32 dot product would be.  The free flight is delta tracking against the
 // per-tet majorant with an optical depth carried across cells; real
 // collisions scatter by Henyey-Greenstein after a next-event estimate of the
 // directional light (transmittance by walking the light ray to the grid
@@ -58,9 +62,9 @@ struct RenderArgs {
   int32_t pass_spp;     // samples of this pass
   int32_t per_item, items_per_pixel, max_bounces, transmittance;
   uint32_t max_steps;
-  int32_t event_batch;  // scatter events wait until this many lanes of a wave need one
   uint64_t seed;
   uint32_t items, slots;
+  uint32_t range_size;  // work items per XCD range (8 contiguous ranges)
   int32_t tiles_x;
   const RayEntry* entries;
   float* out;
@@ -167,14 +171,16 @@ struct TetMedium {
   int64_t n;
   int dmax;
   __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
-  // Exit of the tet along (o, d) from t: faces with n.d > 0 are candidates;
-  // the exit face has the smallest exact quotient num / den (compared by
-  // exact FP64 cross products, lowest face on ties); one FP32 division gives
-  // the exit distance.  Branchless, so the whole record is loaded at once.
-  __device__ inline Step step(uint32_t cell, float3 o, float3 d, float t) const {
+  // Exit of the tet along the segment whose direction-dot table is `tab`
+  // (tab[N] = dir_N . d, tab[9 + N] = dir_N . o) from t: faces with
+  // n.d > 0 are candidates; the exit face has the smallest exact quotient
+  // num / den (exact FP64 cross products, lowest face on ties); one FP32
+  // division gives the exit distance.  Branchless, so the whole record is
+  // loaded at once.
+  __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
     const float4* q = (const float4*)(rec + cell);
     const float4 r0 = q[0], r1 = q[1], r2 = q[2];
-    const uint32_t normals = __float_as_uint(r2.x);
+    const uint32_t codes = __float_as_uint(r2.x);
     const float off[4] = {r0.x, r0.y, r0.z, r0.w};
     const uint32_t link[4] = {__float_as_uint(r1.x), __float_as_uint(r1.y), __float_as_uint(r1.z),
                               __float_as_uint(r1.w)};
@@ -183,11 +189,11 @@ struct TetMedium {
     uint32_t blink = kBoundary;
 #pragma unroll
     for (int f = 0; f < 4; f++) {
-      uint32_t c = (normals >> (6 * f)) & 63u;
-      float nx = (float)((int)(c & 3u) - 1), ny = (float)((int)((c >> 2) & 3u) - 1),
-            nz = (float)((int)((c >> 4) & 3u) - 1);
-      float den = (nx * d.x + ny * d.y) + nz * d.z;
-      float num = off[f] - ((nx * o.x + ny * o.y) + nz * o.z);
+      uint32_t c = (codes >> (8 * f)) & 0xFFu;
+      uint32_t sg = c << 31;
+      float den = __uint_as_float(__float_as_uint(tab[c >> 1]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(tab[9 + (c >> 1)]) ^ sg);
+      float num = off[f] - dot;
       bool cand = den > 0.0f;
       bool better = cand && (!any || (double)num * (double)bden < (double)bnum * (double)den);
       bnum = better ? num : bnum;
@@ -202,6 +208,49 @@ struct TetMedium {
     s.ok = any;
     s.te = bt > t ? bt : t;
     s.next = (!any || blink == kBoundary) ? -1 : (int32_t)(blink >> 2);
+    return s;
+  }
+};
+
+// Same walk on the compact 32-byte records (bitwise the same values).
+struct TetMedium32 {
+  const TetRec32* __restrict__ rec;
+  const uint64_t* __restrict__ keys;
+  int64_t n;
+  int dmax;
+  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
+  __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
+    const uint4* q = (const uint4*)(rec + cell);
+    const uint4 a = q[0], b = q[1];
+    uint32_t o1 = (uint32_t)((((uint64_t)a.y << 32) | a.x) >> 23);
+    uint32_t o2 = (uint32_t)((((uint64_t)a.z << 32) | a.y) >> 14);
+    const int32_t ioff[4] = {((int32_t)(a.x << 9)) >> 9, ((int32_t)(o1 << 9)) >> 9, ((int32_t)(o2 << 9)) >> 9,
+                             ((int32_t)(a.z << 4)) >> 9};
+    const uint32_t lw[4] = {b.x, b.y, b.z, b.w};
+    bool any = false;
+    float bnum = 0.0f, bden = 1.0f;
+    uint32_t blink = kLink27Boundary;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      uint32_t c = lw[f] >> 27;
+      uint32_t sg = c << 31;
+      float den = __uint_as_float(__float_as_uint(tab[c >> 1]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(tab[9 + (c >> 1)]) ^ sg);
+      float num = (float)ioff[f] * 0x1p-20f - dot;
+      bool cand = den > 0.0f;
+      bool better = cand && (!any || (double)num * (double)bden < (double)bnum * (double)den);
+      bnum = better ? num : bnum;
+      bden = better ? den : bden;
+      blink = better ? (lw[f] & kLink27Boundary) : blink;
+      any = any || cand;
+    }
+    Step s;
+    float bt = bnum / bden;
+    s.sigma = __uint_as_float(a.w);
+    s.majorant = s.sigma;
+    s.ok = any;
+    s.te = bt > t ? bt : t;
+    s.next = (!any || blink == kLink27Boundary) ? -1 : (int32_t)blink;
     return s;
   }
 };
@@ -221,7 +270,7 @@ struct VoxelMedium {
     }
     return idx[0] + n * (idx[1] + (int64_t)n * idx[2]);
   }
-  __device__ inline Step step(uint32_t cell, float3 o, float3 d, float t) const {
+  __device__ inline Step step(uint32_t cell, float3 o, float3 d, const float*, float t) const {
     int32_t idx[3] = {(int32_t)(cell % (uint32_t)n), (int32_t)((cell / (uint32_t)n) % (uint32_t)n),
                       (int32_t)(cell / ((uint32_t)n * (uint32_t)n))};
     const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
@@ -330,10 +379,40 @@ __global__ __launch_bounds__(256) void k_raygen(RenderArgs A, Med med, RayEntry*
   entries[e] = r;
 }
 
-enum { M_FETCH = 0, M_START = 1, M_TRACK = 2, M_SHADOW = 3, M_SCATTER = 4, M_DONE = 5 };
+enum { M_TRACK = 0, M_SHADOW = 1, M_COLLIDE = 2, M_SCATTER = 3, M_ESCAPE = 4, M_FINISH = 5, M_FETCH = 6,
+       M_START = 7, M_DONE = 8 };
 
-template <class Med>
-__global__ __launch_bounds__(256) void k_render(RenderArgs A, Med med) {
+constexpr int kTabStride = 19;  // floats per lane in the LDS dot table (odd: no bank conflicts)
+
+// Dot products of the 9 face directions with the segment's direction d and
+// origin o, each rounded as (n.x a.x + n.y a.y) + n.z a.z would be (its
+// zero terms are exact).
+__device__ inline void set_segment(float* tab, float3 o, float3 d) {
+  tab[0] = d.x;
+  tab[1] = d.y;
+  tab[2] = d.z;
+  tab[3] = d.x + d.y;
+  tab[4] = d.x - d.y;
+  tab[5] = d.x + d.z;
+  tab[6] = d.x - d.z;
+  tab[7] = d.y + d.z;
+  tab[8] = d.y - d.z;
+  tab[9] = o.x;
+  tab[10] = o.y;
+  tab[11] = o.z;
+  tab[12] = o.x + o.y;
+  tab[13] = o.x - o.y;
+  tab[14] = o.x + o.z;
+  tab[15] = o.x - o.z;
+  tab[16] = o.y + o.z;
+  tab[17] = o.y - o.z;
+}
+
+// W: occupancy target in waves per SIMD (the register budget follows).
+template <class Med, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_render(RenderArgs A, Med med) {
+  __shared__ float s_tab[256 * kTabStride];
+  float* tab = s_tab + threadIdx.x * kTabStride;
   const int lane = __lane_id();
   int mode = M_FETCH;
   uint32_t pix = 0, slot = 0;
@@ -341,218 +420,225 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs A, Med med) {
   float3 o = make_float3(0, 0, 0), d = o, dsave = o, L = o, acc = o;
   float beta = 1.0f, t = 0.0f, tau = 0.0f, od = 0.0f;
   uint32_t cell = 0, cell_x = 0, bounce = 0, jf = 0, jn = 0, steps = 0;
-  // per-wave counters (uniform) and the per-lane null-collision count
-  unsigned long long c_steps = 0, c_real = 0, c_esc = 0, c_trunc = 0;
-  uint32_t n_null = 0;
+  uint32_t n_steps = 0, n_null = 0, n_real = 0, n_esc = 0, n_trunc = 0;
+  int range = blockIdx.x & 7, tried = 0;  // wave-uniform work range state
   const float3 sun = make_float3(A.sun[0], A.sun[1], A.sun[2]);
 
   for (;;) {
-    // ---- idle lanes take work items (one atomic per wave)
-    bool need = mode == M_FETCH;
-    unsigned long long m = __ballot(need);
-    if (m) {
-      int leader = __ffsll((long long)m) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(A.counter, (uint32_t)__popcll(m));
-      base = __shfl(base, leader);
-      if (need) {
-        uint32_t item = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (item >= A.items) {
-          mode = M_DONE;
-        } else {
-          slot = item / (uint32_t)A.items_per_pixel;
-          uint32_t chunk = item % (uint32_t)A.items_per_pixel;
-          int32_t px, py;
-          if (slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
-            pix = (uint32_t)(py * A.fr.w + px);
-            s = A.pass_start + (int32_t)chunk * A.per_item;
-            s_end = min(s + A.per_item, A.pass_start + A.pass_spp);
-            acc = make_float3(0, 0, 0);
-            mode = M_START;
-          }
-        }
-      }
-    }
-    if (__ballot(mode != M_DONE) == 0) break;
-
-    bool finish = false;
-    // ---- new sample: its precomputed entry into the grid
-    if (mode == M_START) {
-      const float4* q = (const float4*)(A.entries + (size_t)slot * (uint32_t)A.pass_spp + (uint32_t)(s - A.pass_start));
-      float4 a = q[0], b = q[1];
-      uint32_t c = __float_as_uint(a.w);
-      if (c == kMiss) {
-        L = make_float3(A.env[0], A.env[1], A.env[2]);
-        finish = true;
-      } else {
-        o = make_float3(a.x, a.y, a.z);
-        d = make_float3(b.x, b.y, b.z);
-        tau = b.w;
-        cell = c;
-        t = 0.0f;
-        beta = 1.0f;
-        L = make_float3(0, 0, 0);
-        bounce = 0;
-        jf = 1;  // flight draw 0 of bounce 0 made the entry's depth
+    // ================= events: run only when some lane is not walking
+    if (__ballot(mode > M_SHADOW)) {
+      if (mode == M_COLLIDE) {  // real collision at t: start the light ray
+        n_real++;
+        float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+        bounce++;
+        jf = 0;
         jn = 0;
-        steps = 0;
-        mode = M_TRACK;
+        beta = beta * A.albedo;
+        dsave = d;
+        o = x;
+        d = sun;
+        t = 0.0f;
+        cell_x = cell;
+        od = A.transmittance == 0 ? 0.0f : 1.0f;
+        if (A.transmittance != 0) tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+        set_segment(tab, o, d);
+        mode = M_SHADOW;
       }
-    }
-    // ---- one walk step (main path or light ray)
-    bool walking = mode == M_TRACK || mode == M_SHADOW;
-    bool escaped = false, collided = false, trunc = walking && steps >= A.max_steps;
-    c_steps += (unsigned long long)__popcll(__ballot(walking && !trunc));
-    if (trunc) {
-      finish = true;
-    } else if (walking) {
-      Step st = med.step(cell, o, d, t);
-      steps++;
-      if (mode == M_TRACK) {
-        if (!st.ok) {
-          escaped = true;
+      if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
+        float Tr = A.transmittance == 0 ? exp_neg(od) : od;
+        float mu = (dsave.x * sun.x + dsave.y * sun.y) + dsave.z * sun.z;
+        float ph = hg_pdf(A.g, mu);
+        L.x = L.x + ((beta * ph) * A.E[0]) * Tr;
+        L.y = L.y + ((beta * ph) * A.E[1]) * Tr;
+        L.z = L.z + ((beta * ph) * A.E[2]) * Tr;
+        if ((int32_t)bounce >= A.max_bounces) {
+          mode = M_FINISH;
         } else {
-          float sg = st.sigma, sb = st.majorant;
-          float tc = 0.0f;
-          if (sb > 0.0f) {
-            float dtau = sb * (st.te - t);
-            while (tau < dtau) {
-              tc = t + tau / sb;
-              bool real = true;
-              if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
-              if (real) {
-                collided = true;
-                break;
-              }
-              n_null++;
-              t = tc;
-              tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
-              dtau = sb * (st.te - t);
-            }
-            if (!collided) tau = tau - dtau;
-          }
-          if (collided) {
-            float3 x = make_float3(o.x + tc * d.x, o.y + tc * d.y, o.z + tc * d.z);
-            bounce++;
-            jf = 0;
-            jn = 0;
-            beta = beta * A.albedo;
-            dsave = d;
-            o = x;
-            d = sun;
-            t = 0.0f;
-            cell_x = cell;
-            od = A.transmittance == 0 ? 0.0f : 1.0f;
-            if (A.transmittance != 0) tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
-            mode = M_SHADOW;
+          uint2 v = uniform01x2(A.seed, pix, (uint32_t)s, bounce, kStreamPhase, 0);
+          d = hg_scatter(dsave, A.g, u01(v.x), u01(v.y));
+          t = 0.0f;
+          cell = cell_x;
+          tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
+          set_segment(tab, o, d);
+          mode = M_TRACK;
+        }
+      }
+      if (mode == M_ESCAPE) {  // left the grid: the environment
+        n_esc++;
+        L.x = L.x + beta * A.env[0];
+        L.y = L.y + beta * A.env[1];
+        L.z = L.z + beta * A.env[2];
+        mode = M_FINISH;
+      }
+      if (mode == M_FINISH) {  // sample done: accumulate; next sample or next item
+        acc.x = acc.x + L.x;
+        acc.y = acc.y + L.y;
+        acc.z = acc.z + L.z;
+        n_steps += steps;
+        steps = 0;
+        s++;
+        if (s < s_end) {
+          mode = M_START;
+        } else {
+          float* px = A.out + 3 * (size_t)pix;
+          if (A.accumulate) {
+            atomicAdd(px, acc.x);
+            atomicAdd(px + 1, acc.y);
+            atomicAdd(px + 2, acc.z);
           } else {
-            t = st.te;
-            if (st.next < 0) escaped = true;
-            else cell = (uint32_t)st.next;
+            px[0] = acc.x / (float)A.spp;
+            px[1] = acc.y / (float)A.spp;
+            px[2] = acc.z / (float)A.spp;
+          }
+          mode = M_FETCH;
+        }
+      }
+      // idle lanes take work items, one atomic per wave: first from this
+      // block's XCD range (blocks are dealt to the 8 XCDs round-robin, so
+      // an XCD's L2 sees one band of the image), then from the others
+      bool need = mode == M_FETCH;
+      unsigned long long m = __ballot(need);
+      if (m) {
+        if (tried >= 8) {
+          if (need) mode = M_DONE;
+        } else {
+          int leader = __ffsll((long long)m) - 1;
+          uint32_t base = 0;
+          if (lane == leader) base = atomicAdd(A.counter + range, (uint32_t)__popcll(m));
+          base = __shfl(base, leader);
+          uint32_t r0 = (uint32_t)range * A.range_size;
+          uint32_t rend = min(r0 + A.range_size, A.items);
+          uint32_t item = r0 + base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+          if (base + (uint32_t)__popcll(m) >= rend - min(r0, rend)) {  // range drained: move on
+            range = (range + 1) & 7;
+            tried++;
+          }
+          if (need && item < rend) {
+            slot = item / (uint32_t)A.items_per_pixel;
+            uint32_t chunk = item % (uint32_t)A.items_per_pixel;
+            int32_t px, py;
+            if (slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
+              pix = (uint32_t)(py * A.fr.w + px);
+              s = A.pass_start + (int32_t)chunk * A.per_item;
+              s_end = min(s + A.per_item, A.pass_start + A.pass_spp);
+              acc = make_float3(0, 0, 0);
+              mode = M_START;
+            }
           }
         }
-        if (escaped) {  // left the grid: the environment
-          L.x = L.x + beta * A.env[0];
-          L.y = L.y + beta * A.env[1];
-          L.z = L.z + beta * A.env[2];
-          finish = true;
+      }
+      if (mode == M_START) {  // new sample: its precomputed entry into the grid
+        const float4* q =
+            (const float4*)(A.entries + (size_t)slot * (uint32_t)A.pass_spp + (uint32_t)(s - A.pass_start));
+        float4 a = q[0], b = q[1];
+        uint32_t c = __float_as_uint(a.w);
+        steps = 0;
+        if (c == kMiss) {
+          L = make_float3(A.env[0], A.env[1], A.env[2]);
+          mode = M_FINISH;
+        } else {
+          o = make_float3(a.x, a.y, a.z);
+          d = make_float3(b.x, b.y, b.z);
+          tau = b.w;
+          cell = c;
+          t = 0.0f;
+          beta = 1.0f;
+          L = make_float3(0, 0, 0);
+          bounce = 0;
+          jf = 1;  // flight draw 0 of bounce 0 made the entry's depth
+          jn = 0;
+          set_segment(tab, o, d);
+          mode = M_TRACK;
         }
-      } else {  // light ray: od holds the optical depth (analytic) or the transmittance
-        bool done = !st.ok;
-        if (st.ok) {
-          float sg = st.sigma, sb = st.majorant;
-          if (A.transmittance == 0) {
-            od = od + sg * (st.te - t);
-          } else if (sb > 0.0f) {
-            float dtau = sb * (st.te - t);
-            while (tau < dtau) {
-              t = t + tau / sb;
-              if (A.transmittance == 1) {
-                od = od * (1.0f - sg / sb);
-              } else {
+      }
+      if (__ballot(mode != M_DONE) == 0) break;
+    }
+    // ================= one walk step of the main path or of the light ray
+    if (mode <= M_SHADOW) {
+      if (steps >= A.max_steps) {
+        n_trunc++;
+        mode = M_FINISH;  // truncated path keeps what it has gathered
+      } else {
+        Step st = med.step(cell, o, d, tab, t);
+        steps++;
+        float sg = st.sigma, sb = st.majorant;
+        if (mode == M_TRACK) {
+          if (!st.ok) {
+            mode = M_ESCAPE;
+          } else {
+            bool collided = false;
+            float tc = 0.0f;
+            if (sb > 0.0f) {
+              float dtau = sb * (st.te - t);
+              while (tau < dtau) {
+                tc = t + tau / sb;
                 bool real = true;
-                if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++) < sg / sb;
+                if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
                 if (real) {
-                  od = 0.0f;
-                  done = true;
+                  collided = true;
                   break;
                 }
+                n_null++;
+                t = tc;
+                tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
+                dtau = sb * (st.te - t);
               }
-              tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
-              dtau = sb * (st.te - t);
+              if (!collided) tau = tau - dtau;
             }
-            if (!done) tau = tau - dtau;
+            if (collided) {
+              t = tc;
+              mode = M_COLLIDE;
+            } else {
+              t = st.te;
+              if (st.next < 0) mode = M_ESCAPE;
+              else cell = (uint32_t)st.next;
+            }
           }
-          if (A.transmittance == 1 && od == 0.0f) done = true;
-          if (!done) {
-            t = st.te;
-            if (st.next < 0) done = true;
-            else cell = (uint32_t)st.next;
+        } else {  // light ray: od holds the optical depth (analytic) or the transmittance
+          bool done = !st.ok;
+          if (st.ok) {
+            if (A.transmittance == 0) {
+              od = od + sg * (st.te - t);
+            } else if (sb > 0.0f) {
+              float dtau = sb * (st.te - t);
+              while (tau < dtau) {
+                t = t + tau / sb;
+                if (A.transmittance == 1) {
+                  od = od * (1.0f - sg / sb);
+                } else {
+                  bool real = true;
+                  if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++) < sg / sb;
+                  if (real) {
+                    od = 0.0f;
+                    done = true;
+                    break;
+                  }
+                }
+                tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+                dtau = sb * (st.te - t);
+              }
+              if (!done) tau = tau - dtau;
+            }
+            if (A.transmittance == 1 && od == 0.0f) done = true;
+            if (!done) {
+              t = st.te;
+              if (st.next < 0) done = true;
+              else cell = (uint32_t)st.next;
+            }
           }
+          if (done) mode = M_SCATTER;
         }
-        if (done) mode = M_SCATTER;
-      }
-    }
-    c_trunc += (unsigned long long)__popcll(__ballot(trunc));
-    c_esc += (unsigned long long)__popcll(__ballot(escaped));
-    c_real += (unsigned long long)__popcll(__ballot(collided));
-    // ---- scatter events, run for many lanes at once
-    unsigned long long sm = __ballot(mode == M_SCATTER);
-    if (sm) {
-      unsigned long long busy = __ballot(mode == M_TRACK || mode == M_SHADOW || mode == M_START);
-      if (__popcll(sm) >= A.event_batch || busy == 0) {
-        if (mode == M_SCATTER) {
-          float Tr = A.transmittance == 0 ? (float)exp(-(double)od) : od;
-          float mu = (dsave.x * sun.x + dsave.y * sun.y) + dsave.z * sun.z;
-          float ph = hg_pdf(A.g, mu);
-          L.x = L.x + ((beta * ph) * A.E[0]) * Tr;
-          L.y = L.y + ((beta * ph) * A.E[1]) * Tr;
-          L.z = L.z + ((beta * ph) * A.E[2]) * Tr;
-          if ((int32_t)bounce >= A.max_bounces) {
-            finish = true;
-          } else {
-            uint2 v = uniform01x2(A.seed, pix, (uint32_t)s, bounce, kStreamPhase, 0);
-            d = hg_scatter(dsave, A.g, u01(v.x), u01(v.y));
-            t = 0.0f;
-            cell = cell_x;
-            tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
-            mode = M_TRACK;
-          }
-        }
-      }
-    }
-    // ---- sample finished: accumulate, next sample or next work item
-    if (finish) {
-      acc.x = acc.x + L.x;
-      acc.y = acc.y + L.y;
-      acc.z = acc.z + L.z;
-      s++;
-      if (s < s_end) {
-        mode = M_START;
-      } else {
-        float* px = A.out + 3 * (size_t)pix;
-        if (A.accumulate) {
-          atomicAdd(px, acc.x);
-          atomicAdd(px + 1, acc.y);
-          atomicAdd(px + 2, acc.z);
-        } else {
-          px[0] = acc.x / (float)A.spp;
-          px[1] = acc.y / (float)A.spp;
-          px[2] = acc.z / (float)A.spp;
-        }
-        mode = M_FETCH;
       }
     }
   }
-  unsigned long long nn = n_null;
+  // ---- counters: wave reductions, one atomic per wave and counter
+  unsigned long long v[5] = {n_steps, n_null, n_real, n_esc, n_trunc};
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
-  if (lane == 0) {
-    if (c_steps) atomicAdd(A.stats + 0, c_steps);
-    if (nn) atomicAdd(A.stats + 1, nn);
-    if (c_real) atomicAdd(A.stats + 2, c_real);
-    if (c_esc) atomicAdd(A.stats + 3, c_esc);
-    if (c_trunc) atomicAdd(A.stats + 4, c_trunc);
+  for (int q = 0; q < 5; q++) {
+    unsigned long long x = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0 && x) atomicAdd(A.stats + q, x);
   }
 }
 
@@ -630,14 +716,21 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     P.items_per_pixel = ipp;
     P.items = A.slots * (uint32_t)ipp;
     P.entries = entries;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 4);
+    P.range_size = (P.items + 7) / 8;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 8);
     uint64_t ne = (uint64_t)A.slots * (uint64_t)P.pass_spp;
     hipLaunchKernelGGL(k_raygen<Med>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, P, med, entries);
     int64_t grid = (int64_t)cu_count() * bpc;
     int64_t need = ((int64_t)P.items + bs - 1) / bs;
     grid = std::max<int64_t>(1, std::min(grid, need));
     TV_HIP(hipEventRecord(t0, st));
-    hipLaunchKernelGGL(k_render<Med>, dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+    switch (o.waves_per_simd) {
+      case 4: hipLaunchKernelGGL((k_render<Med, 4>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      case 5: hipLaunchKernelGGL((k_render<Med, 5>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      case 6: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      case 8: hipLaunchKernelGGL((k_render<Med, 8>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      default: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+    }
     TV_HIP(hipGetLastError());
     TV_HIP(hipEventRecord(t1, st));
     TV_HIP(hipEventSynchronize(t1));
@@ -667,8 +760,11 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (opts_in) o = *opts_in;
   else tet_render_opts_defaults(&o);
   if (o.max_bounces < 1 || o.transmittance < 0 || o.transmittance > 2 || o.max_steps_per_path < 1 ||
-      o.sample_offset < 0 || o.samples_per_item < 0 || o.block_size < 0 || o.block_size > 1024 ||
-      (o.block_size % 64) != 0 || o.blocks_per_cu < 0 || o.event_batch < 0 || o.event_batch > 64)
+      o.sample_offset < 0 || o.samples_per_item < 0 || o.block_size < 0 || o.block_size > 256 ||
+      (o.block_size % 64) != 0 || o.blocks_per_cu < 0 ||
+      (o.waves_per_simd != 0 && o.waves_per_simd != 4 && o.waves_per_simd != 5 && o.waves_per_simd != 6 &&
+       o.waves_per_simd != 8) ||
+      (o.record_layout != 0 && o.record_layout != 32 && o.record_layout != 48))
     return fail(TET_ERR_INVALID_ARG, "render: bad options");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
   int64_t npix = (int64_t)cam->width * cam->height;
@@ -696,7 +792,6 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.max_bounces = o.max_bounces;
   A.transmittance = o.transmittance;
   A.max_steps = (uint32_t)std::min<int64_t>(o.max_steps_per_path, 0x7FFFFFFF);
-  A.event_batch = o.event_batch ? o.event_batch : 16;
   A.seed = seed;
   A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
@@ -713,14 +808,18 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     ~Free() { dev_free(p); }
   } fr_{sc};
   A.counter = (uint32_t*)sc;
-  A.stats = (unsigned long long*)(sc + 64);
+  A.stats = (unsigned long long*)(sc + 64);  // counters: 8 work ranges in sc[0..32)
   RayEntry* entries = (RayEntry*)(sc + 256);
   A.out = on_device ? out_rgb : (float*)(sc + 256 + ent_bytes);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
 
   float ms = 0.0f, ms_trace = 0.0f;
   int rc;
-  if (kind == 0) {
+  if (kind == 0 && g->rec32 && o.record_layout != 48) {
+    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth};
+    rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
+  } else if (kind == 0) {
+    if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
     TetMedium m{g->rec, g->keys, g->n, g->max_depth};
     rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
   } else {

@@ -92,12 +92,14 @@ def render_both(tv, g, o, sc, cam, spp, seed, ropts):
     return img.cpu().numpy(), st, ref, rst
 
 
-def test_render_tiny_parity(tv, tiny_density):
-    say("case render tiny 64x64 16spp")
+@pytest.mark.parametrize("layout,waves", [(32, 8), (48, 8), (32, 5), (48, 4)])
+def test_render_tiny_parity(tv, tiny_density, layout, waves):
+    say(f"case render tiny 64x64 16spp, {layout}-byte records, {waves} waves")
     sc = TINY
     g = gpu_build(tv, tiny_density, 64, sc["camera"], sc["build"])
     o = oracle.leb_build(tiny_density, 64, sc["camera"], sc["build"])
-    img, st, ref, rst = render_both(tv, g, o, sc, sc["camera"], 16, 1234, sc["render"])
+    r = dict(sc["render"], record_layout=layout, waves_per_simd=waves)
+    img, st, ref, rst = render_both(tv, g, o, sc, sc["camera"], 16, 1234, r)
     assert_image_parity(img, ref, "tiny")
     assert st["real_collisions"] > 0 and st["escapes"] > 0
     # identical paths take identical numbers of steps (up to rare last-ulp

@@ -46,6 +46,30 @@ def test_uniforms_are_uniform_and_keyed():
     assert a != oracle.uniform(7, 3, 4, 0, 1, 1) and a != oracle.uniform(8, 3, 4, 0, 1, 0)
 
 
+# ---------------------------------------------------------------- FP32 elementary functions
+def test_elementary_functions_against_fp64():
+    """The FP32 -ln(1-u), e^-x and (cos, sin)(2 pi u) algorithms stay within a
+    few FP32 ulps of the FP64 library functions over their whole domain."""
+    rng = np.random.default_rng(4)
+    u = np.concatenate([np.arange(0, 2 ** 24, 4099) / 2 ** 24, (2 ** 24 - np.arange(1, 200)) / 2 ** 24,
+                        np.arange(1, 200) / 2 ** 24]).astype(np.float32)
+    got = np.array([oracle.neglog1m(x) for x in u])
+    ref = -np.log1p(-u.astype(np.float64))
+    assert np.all(np.abs(got - ref) <= 4e-7 * np.maximum(ref, 1e-30) + 1e-45)
+    assert oracle.neglog1m(0.0) == 0.0
+    x = np.concatenate([rng.uniform(0, 90, 5000), rng.uniform(0, 1e-3, 500), [0.0, 1e-30, 0.3465, 87.0]])
+    x = x.astype(np.float32)
+    got = np.array([oracle.expneg(v) for v in x])
+    ref = np.exp(-x.astype(np.float64))
+    assert np.all(np.abs(got - ref) <= 4e-7 * ref + 1e-44)
+    assert oracle.expneg(0.0) == 1.0 and oracle.expneg(200.0) == 0.0
+    uu = np.concatenate([rng.random(5000), np.arange(0, 1, 1 / 64)]).astype(np.float32)
+    cs = np.array([oracle.sincos2pi(v) for v in uu])
+    a = 2 * np.pi * uu.astype(np.float64)
+    assert np.max(np.abs(cs[:, 0] - np.cos(a))) < 3e-7 and np.max(np.abs(cs[:, 1] - np.sin(a))) < 3e-7
+    assert np.allclose(cs[:, 0] ** 2 + cs[:, 1] ** 2, 1.0, atol=6e-7)
+
+
 # ---------------------------------------------------------------- phase function
 @pytest.mark.parametrize("g", [-0.7, -0.2, 0.0, 0.3, 0.6, 0.9])
 def test_hg_density_and_sampling(g):
