@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Msamples/s + tet-steps/s at 1024² 32spp; NRC vs plain speedup at equal RMSE"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_TET_STEP = 32  # algorithmic bytes per walk step (compact tet record)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_cloud1024_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_cloud1024_traffic.txt")
+COPY_BYTES = 1 << 30  # plain device copy used to calibrate the traffic counters
 KERNEL_SOURCES = ["paper_2506_11510_amd/csrc/render.hip", "paper_2506_11510_amd/csrc/common.h"]
 
 
@@ -35,17 +36,87 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per render launch from the committed rocprofv3 counter runs,
-    or None when the kernel source changed since they were taken."""
+def read_kv(path):
+    out = {}
     try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+        with open(path) as f:
+            for line in f:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    out[k.strip()] = v.strip()
+    except OSError:
+        pass
+    return out
+
+
+def measured_traffic():
+    """HBM bytes per tracing-kernel launch from the committed rocprofv3
+    counter runs, or None when the kernel source changed since."""
+    t = read_kv(TRAFFIC_FILE)
+    if t.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in t:
         return None
-    if t.get("source_hash") != kernel_source_hash():
-        return None
-    return t.get("traffic_bytes_per_launch")
+    return float(t["traffic_bytes_per_launch"])
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(p)))
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir, out_path, command):
+    """Traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE runs (KiB
+    per dispatch), each scaled by the factor that maps the same counter on
+    a plain 1 GiB device copy to its true size."""
+    def per_kernel(rows, counter):
+        trace, copies = [], []
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if "k_render<tv::TetMedium32" in r["Kernel_Name"]:
+                trace.append(v)
+            elif "copyBuffer" in r["Kernel_Name"]:
+                copies.append(v)
+        return trace, copies
+    ft, fc = per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    wt, wc = per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    f_kib, w_kib = sum(ft) / len(ft), sum(wt) / len(wt)
+    f_fac = (COPY_BYTES / 1024) / max(fc)
+    w_fac = (COPY_BYTES / 1024) / max(wc)
+    traffic = (f_kib * f_fac + w_kib * w_fac) * 1024
+    with open(out_path, "w") as f:
+        f.write("# HBM traffic of the tracing kernel k_render<TetMedium32> on the 1024^2 x 32 spp cloud frame\n")
+        f.write(f"# command: {command}\n")
+        f.write("# counters are KiB per dispatch; the copy factors map a plain 1 GiB device copy to 1 GiB\n")
+        f.write(f"source_hash = {kernel_source_hash()}\n")
+        f.write(f"dispatches = {len(ft)}\n")
+        f.write(f"fetch_kib_per_launch = {f_kib:.1f}\n")
+        f.write(f"write_kib_per_launch = {w_kib:.1f}\n")
+        f.write(f"copy_fetch_kib = {max(fc):.1f}\n")
+        f.write(f"copy_write_kib = {max(wc):.1f}\n")
+        f.write(f"copy_fetch_factor = {f_fac:.4f}\n")
+        f.write(f"copy_write_factor = {w_fac:.4f}\n")
+        f.write(f"traffic_bytes_per_launch = {traffic:.6g}\n")
+    print(open(out_path).read())
+
+
+def summarize_trace(trace_dir, out_path, command):
+    """Short kernel table from a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    rows = list(csv.DictReader(open(paths[0])))
+    with open(out_path, "w") as f:
+        f.write(f"# rocprofv3 kernel statistics\n# command: {command}\n")
+        f.write(f"{'calls':>6} {'avg_us':>12} {'total_ms':>10} {'pct':>6}  kernel\n")
+        for r in rows[:16]:
+            f.write(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>12.1f} {float(r['TotalDurationNs']) / 1e6:>10.2f} "
+                    f"{float(r['Percentage']):>6.2f}  {r['Name'][:110]}\n")
+    print(open(out_path).read())
 
 
 def cpu_model() -> str:
@@ -69,7 +140,7 @@ def cpu_baseline(sc, d, n_threads: int) -> dict:
     g = oracle.leb_build(d, sc["n"], cam, sc["build"])
     t_build = time.perf_counter() - t0
     W, H = cam["width"], cam["height"]
-    stride = 1021
+    stride = 3
     pix = np.arange(0, W * H, stride, dtype=np.int32)
     t0 = time.perf_counter()
     _, st = g.render(cam, sc["medium"], sc["light"], sc["render"]["spp"], 2024, sc["render"], pixels=pix,
@@ -94,7 +165,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--render-only", action="store_true", help="time only the render (grid built once)")
+    ap.add_argument("--calibrate-copy", action="store_true", help="end with a plain 1 GiB device copy")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"))
+    ap.add_argument("--command", default="")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, args.command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the method's hot path is "
               "single-GPU here; sharding across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
@@ -107,9 +188,9 @@ def main():
     import paper_2506_11510_amd as tv
 
     sc = synthetic.scene("cloud")
-    # launch configuration of the tracing kernel (work items of 8 samples,
-    # compact 32-byte records, 6 waves per SIMD)
-    sc["render"] = dict(sc["render"], samples_per_item=8, record_layout=32, waves_per_simd=6)
+    # launch configuration of the tracing kernel (one sample per work item,
+    # batches of 64 items per wave, compact 32-byte records, 6 waves per SIMD)
+    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=6)
     cam, spp = sc["camera"], sc["render"]["spp"]
     d = sc["density_fn"]()
     dev = torch.from_numpy(d).cuda()
@@ -174,12 +255,19 @@ def main():
         "tet_steps_per_frame": int(mean_steps),
         "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated")},
         "image_mean": float(img.mean()),
-        "roofline": {"bound": "hbm", "kernel": "k_render<TetMedium>", "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_render<TetMedium32, 6>", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP)},
         "cpu_baseline": None,
     }
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         n_threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         res["cpu_baseline"] = cpu_baseline(sc, d, n_threads)

@@ -65,6 +65,7 @@ struct RenderArgs {
   uint64_t seed;
   uint32_t items, slots;
   uint32_t range_size;  // work items per XCD range (8 contiguous ranges)
+  uint32_t batch;       // work items a wave takes per atomic
   int32_t tiles_x;
   const RayEntry* entries;
   float* out;
@@ -422,6 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   uint32_t cell = 0, cell_x = 0, bounce = 0, jf = 0, jn = 0, steps = 0;
   uint32_t n_steps = 0, n_null = 0, n_real = 0, n_esc = 0, n_trunc = 0;
   int range = blockIdx.x & 7, tried = 0;  // wave-uniform work range state
+  uint32_t bnext = 0, bend = 0;          // wave-uniform batch of work items
   const float3 sun = make_float3(A.sun[0], A.sun[1], A.sun[2]);
 
   for (;;) {
@@ -493,27 +495,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           mode = M_FETCH;
         }
       }
-      // idle lanes take work items, one atomic per wave: first from this
-      // block's XCD range (blocks are dealt to the 8 XCDs round-robin, so
-      // an XCD's L2 sees one band of the image), then from the others
+      // idle lanes take consecutive work items from the wave's batch; a wave
+      // refills its batch with one atomic, first from this block's XCD range
+      // (blocks are dealt to the 8 XCDs round-robin, so an XCD's L2 serves
+      // one band of the image), then from the others.  Consecutive items are
+      // samples of one pixel, so lanes walking side by side share records.
       bool need = mode == M_FETCH;
       unsigned long long m = __ballot(need);
       if (m) {
-        if (tried >= 8) {
-          if (need) mode = M_DONE;
-        } else {
-          int leader = __ffsll((long long)m) - 1;
+        if (bnext >= bend && tried < 8) {
           uint32_t base = 0;
-          if (lane == leader) base = atomicAdd(A.counter + range, (uint32_t)__popcll(m));
-          base = __shfl(base, leader);
+          if (lane == 0) base = atomicAdd(A.counter + range, A.batch);
+          base = __shfl(base, 0);
           uint32_t r0 = (uint32_t)range * A.range_size;
           uint32_t rend = min(r0 + A.range_size, A.items);
-          uint32_t item = r0 + base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-          if (base + (uint32_t)__popcll(m) >= rend - min(r0, rend)) {  // range drained: move on
+          if (r0 >= rend || base >= rend - r0) {  // range drained: move on
             range = (range + 1) & 7;
             tried++;
+          } else {
+            bnext = r0 + base;
+            bend = min(bnext + A.batch, rend);
           }
-          if (need && item < rend) {
+        }
+        if (bnext < bend) {
+          uint32_t item = bnext + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+          if (need && item < bend) {
             slot = item / (uint32_t)A.items_per_pixel;
             uint32_t chunk = item % (uint32_t)A.items_per_pixel;
             int32_t px, py;
@@ -523,8 +529,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
               s_end = min(s + A.per_item, A.pass_start + A.pass_spp);
               acc = make_float3(0, 0, 0);
               mode = M_START;
+            } else {
+              mode = M_FETCH;  // padding slot of an edge tile: take another item
             }
           }
+          bnext = min(bnext + (uint32_t)__popcll(m), bend);
+        } else if (tried >= 8) {
+          if (need) mode = M_DONE;
         }
       }
       if (mode == M_START) {  // new sample: its precomputed entry into the grid
@@ -764,7 +775,8 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
       (o.block_size % 64) != 0 || o.blocks_per_cu < 0 ||
       (o.waves_per_simd != 0 && o.waves_per_simd != 4 && o.waves_per_simd != 5 && o.waves_per_simd != 6 &&
        o.waves_per_simd != 8) ||
-      (o.record_layout != 0 && o.record_layout != 32 && o.record_layout != 48))
+      (o.record_layout != 0 && o.record_layout != 32 && o.record_layout != 48) || o.batch_items < 0 ||
+      o.batch_items > (1 << 20))
     return fail(TET_ERR_INVALID_ARG, "render: bad options");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
   int64_t npix = (int64_t)cam->width * cam->height;
@@ -795,6 +807,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.seed = seed;
   A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
+  A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
   A.accumulate = (pass_cap < spp) || (per_item < pass_cap);
 
   // scratch: counters, entry records of one pass, image when the output is on the host
