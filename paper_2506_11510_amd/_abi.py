@@ -53,7 +53,7 @@ class TetRenderOpts(ctypes.Structure):
                 ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32),
                 ("samples_per_item", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("record_layout", ctypes.c_int32), ("batch_items", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("record_layout", ctypes.c_int32), ("batch_items", ctypes.c_int32), ("event_wait", ctypes.c_int32)]
 
 
 class TetRenderStats(ctypes.Structure):

@@ -66,6 +66,7 @@ struct RenderArgs {
   uint32_t items, slots;
   uint32_t range_size;  // work items per XCD range (8 contiguous ranges)
   uint32_t batch;       // work items a wave takes per atomic
+  int32_t event_wait;   // lanes waiting for an event before the wave handles events
   int32_t tiles_x;
   const RayEntry* entries;
   float* out;
@@ -167,6 +168,7 @@ __device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_
 }
 
 struct TetMedium {
+  static constexpr float kOriginScale = 1.0f;
   const TetRec* __restrict__ rec;
   const uint64_t* __restrict__ keys;
   int64_t n;
@@ -213,8 +215,14 @@ struct TetMedium {
   }
 };
 
-// Same walk on the compact 32-byte records (bitwise the same values).
+// Same walk on the compact 32-byte records (bitwise the same values).  The
+// LDS table holds origin dots scaled by 2^20 (exact), so the integer
+// offsets need no scaling: num * 2^20 = offset - dot * 2^20 exactly, the
+// quotient comparisons are scale-free, and one final multiply by 2^-20
+// (exact) gives the exit distance.  The running best starts at the
+// quotient 1/0 = +inf, which every candidate beats.
 struct TetMedium32 {
+  static constexpr float kOriginScale = 0x1p20f;  // origin dots stored times 2^20
   const TetRec32* __restrict__ rec;
   const uint64_t* __restrict__ keys;
   int64_t n;
@@ -228,25 +236,23 @@ struct TetMedium32 {
     const int32_t ioff[4] = {((int32_t)(a.x << 9)) >> 9, ((int32_t)(o1 << 9)) >> 9, ((int32_t)(o2 << 9)) >> 9,
                              ((int32_t)(a.z << 4)) >> 9};
     const uint32_t lw[4] = {b.x, b.y, b.z, b.w};
-    bool any = false;
-    float bnum = 0.0f, bden = 1.0f;
+    float bnum = 1.0f, bden = 0.0f;
     uint32_t blink = kLink27Boundary;
 #pragma unroll
     for (int f = 0; f < 4; f++) {
-      uint32_t c = lw[f] >> 27;
-      uint32_t sg = c << 31;
-      float den = __uint_as_float(__float_as_uint(tab[c >> 1]) ^ sg);
-      float dot = __uint_as_float(__float_as_uint(tab[9 + (c >> 1)]) ^ sg);
-      float num = (float)ioff[f] * 0x1p-20f - dot;
-      bool cand = den > 0.0f;
-      bool better = cand && (!any || (double)num * (double)bden < (double)bnum * (double)den);
+      const float* e = tab + (lw[f] >> 28);
+      uint32_t sg = (lw[f] >> 27) << 31;
+      float den = __uint_as_float(__float_as_uint(e[0]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(e[9]) ^ sg);
+      float num = (float)ioff[f] - dot;
+      bool better = den > 0.0f && (double)num * (double)bden < (double)bnum * (double)den;
       bnum = better ? num : bnum;
       bden = better ? den : bden;
       blink = better ? (lw[f] & kLink27Boundary) : blink;
-      any = any || cand;
     }
     Step s;
-    float bt = bnum / bden;
+    bool any = bden > 0.0f;
+    float bt = (bnum / bden) * 0x1p-20f;
     s.sigma = __uint_as_float(a.w);
     s.majorant = s.sigma;
     s.ok = any;
@@ -258,6 +264,7 @@ struct TetMedium32 {
 
 // ---------------------------------------------------------------- voxel medium
 struct VoxelMedium {
+  static constexpr float kOriginScale = 1.0f;
   const float* __restrict__ dens;
   int32_t n;
   float scale;
@@ -388,7 +395,8 @@ constexpr int kTabStride = 19;  // floats per lane in the LDS dot table (odd: no
 // Dot products of the 9 face directions with the segment's direction d and
 // origin o, each rounded as (n.x a.x + n.y a.y) + n.z a.z would be (its
 // zero terms are exact).
-__device__ inline void set_segment(float* tab, float3 o, float3 d) {
+__device__ inline void set_segment(float* tab, float3 o, float3 d, float oscale) {
+  o = make_float3(o.x * oscale, o.y * oscale, o.z * oscale);
   tab[0] = d.x;
   tab[1] = d.y;
   tab[2] = d.z;
@@ -427,8 +435,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   const float3 sun = make_float3(A.sun[0], A.sun[1], A.sun[2]);
 
   for (;;) {
-    // ================= events: run only when some lane is not walking
-    if (__ballot(mode > M_SHADOW)) {
+    // ================= events: run when enough lanes wait for one, or when
+    // no lane is walking (waiting lanes idle meanwhile)
+    unsigned long long waiting = __ballot(mode > M_SHADOW);
+    if (waiting && (__popcll(waiting) >= A.event_wait || __popcll(waiting) == 64 ||
+                    __ballot(mode <= M_SHADOW) == 0)) {
       if (mode == M_COLLIDE) {  // real collision at t: start the light ray
         n_real++;
         float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
@@ -443,7 +454,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         cell_x = cell;
         od = A.transmittance == 0 ? 0.0f : 1.0f;
         if (A.transmittance != 0) tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
-        set_segment(tab, o, d);
+        set_segment(tab, o, d, Med::kOriginScale);
         mode = M_SHADOW;
       }
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
@@ -461,7 +472,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           t = 0.0f;
           cell = cell_x;
           tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
-          set_segment(tab, o, d);
+          set_segment(tab, o, d, Med::kOriginScale);
           mode = M_TRACK;
         }
       }
@@ -558,7 +569,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           bounce = 0;
           jf = 1;  // flight draw 0 of bounce 0 made the entry's depth
           jn = 0;
-          set_segment(tab, o, d);
+          set_segment(tab, o, d, Med::kOriginScale);
           mode = M_TRACK;
         }
       }
@@ -737,10 +748,10 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     TV_HIP(hipEventRecord(t0, st));
     switch (o.waves_per_simd) {
       case 4: hipLaunchKernelGGL((k_render<Med, 4>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
-      case 5: hipLaunchKernelGGL((k_render<Med, 5>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
       case 6: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
       case 8: hipLaunchKernelGGL((k_render<Med, 8>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
-      default: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      case 6: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      default: hipLaunchKernelGGL((k_render<Med, 5>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
     }
     TV_HIP(hipGetLastError());
     TV_HIP(hipEventRecord(t1, st));
@@ -776,7 +787,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
       (o.waves_per_simd != 0 && o.waves_per_simd != 4 && o.waves_per_simd != 5 && o.waves_per_simd != 6 &&
        o.waves_per_simd != 8) ||
       (o.record_layout != 0 && o.record_layout != 32 && o.record_layout != 48) || o.batch_items < 0 ||
-      o.batch_items > (1 << 20))
+      o.batch_items > (1 << 20) || o.event_wait < 0 || o.event_wait > 64)
     return fail(TET_ERR_INVALID_ARG, "render: bad options");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
   int64_t npix = (int64_t)cam->width * cam->height;
@@ -808,6 +819,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
   A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
+  A.event_wait = o.event_wait ? o.event_wait : 16;
   A.accumulate = (pass_cap < spp) || (per_item < pass_cap);
 
   // scratch: counters, entry records of one pass, image when the output is on the host
