@@ -750,7 +750,6 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
       case 4: hipLaunchKernelGGL((k_render<Med, 4>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
       case 6: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
       case 8: hipLaunchKernelGGL((k_render<Med, 8>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
-      case 6: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
       default: hipLaunchKernelGGL((k_render<Med, 5>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
     }
     TV_HIP(hipGetLastError());
