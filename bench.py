@@ -190,9 +190,9 @@ def main():
     sc = synthetic.scene("cloud")
     # launch configuration of the tracing kernel: one sample per work item,
     # batches of 64 items per wave, compact 32-byte records, 5 waves per SIMD,
-    # events handled once 16 lanes of a wave wait for one
+    # events handled once 48 lanes of a wave wait for one
     sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
-                        event_wait=16)
+                        event_wait=48)
     cam, spp = sc["camera"], sc["render"]["spp"]
     d = sc["density_fn"]()
     dev = torch.from_numpy(d).cuda()

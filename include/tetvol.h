@@ -104,7 +104,7 @@ typedef struct {
   int32_t waves_per_simd;     /* register budget of the tracing kernel: 4, 5, 6 or 8 waves (0 = default 5) */
   int32_t record_layout;      /* tet records walked: 32 (compact), 48, or 0 = compact when the grid has them */
   int32_t batch_items;        /* work items a wave takes at a time (0 = default 64) */
-  int32_t event_wait;         /* lanes of a wave that wait for an event before events run (0 = default 16) */
+  int32_t event_wait;         /* lanes of a wave that wait for an event before events run (0 = default 48) */
 } tet_render_opts;
 
 typedef struct {

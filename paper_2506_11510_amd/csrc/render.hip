@@ -818,7 +818,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
   A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
-  A.event_wait = o.event_wait ? o.event_wait : 16;
+  A.event_wait = o.event_wait ? o.event_wait : 48;
   A.accumulate = (pass_cap < spp) || (per_item < pass_cap);
 
   // scratch: counters, entry records of one pass, image when the output is on the host
