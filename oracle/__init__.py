@@ -124,9 +124,22 @@ def lib():
         L.oracle_camera_ray.argtypes = [ctypes.POINTER(OCam), ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                         ctypes.c_float, vp, vp]
         L.oracle_camera_ray.restype = None
-        L.oracle_nrc_encode.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
-        L.oracle_mlp_forward.argtypes = [vp, ctypes.c_int64, vp, vp]
-        L.oracle_mlp_backward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.oracle_bf16_round.argtypes = [ctypes.c_float]
+        L.oracle_bf16_round.restype = ctypes.c_float
+        L.oracle_nrc_encode.argtypes = [ctypes.c_int64, vp, vp, vp, ctypes.c_float, vp]
+        L.oracle_mlp_forward.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int32]
+        L.oracle_mlp_backward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int32]
+        L.oracle_nrc_eval_point.argtypes = [vp, ctypes.c_int32, ctypes.c_float, vp, vp, ctypes.c_float, vp]
+        L.oracle_nrc_eval_point.restype = None
+        L.oracle_nrc_render.argtypes = [vp, ctypes.POINTER(OCam), ctypes.POINTER(OMedium), ctypes.POINTER(OLight),
+                                        ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ORenderOpts), vp,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_float, vp, ctypes.c_int64, vp,
+                                        ctypes.POINTER(ORenderStats), ctypes.c_int32]
+        L.oracle_train_pixel.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64]
+        L.oracle_train_pixel.restype = ctypes.c_int32
+        L.oracle_nrc_collect.argtypes = [vp, ctypes.POINTER(OCam), ctypes.POINTER(OMedium), ctypes.POINTER(OLight),
+                                         ctypes.c_uint64, ctypes.POINTER(ORenderOpts), ctypes.c_int32,
+                                         ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32]
         L.oracle_nrc_loss_grad.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
         L.oracle_adam_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -250,6 +263,55 @@ class Grid:
         return out, st.as_dict()
 
 
+    def nrc_render(self, camera: dict, medium: dict, light: dict, spp: int, seed: int, params, render=None,
+                   truncate_bounce: int = 2, sigma_ref: float = 1.0, bf16: bool = True, pixels=None,
+                   threads: int = 1):
+        """Truncated render with the radiance cache `params` (17,603
+        values): every path stops at real vertex `truncate_bounce` and adds
+        the throughput reaching it times the cache's estimate."""
+        cam = make_cam(camera)
+        ro = make_render_opts(render or {})
+        st = ORenderStats()
+        params = np.ascontiguousarray(params, np.float64)
+        assert params.size == N_PARAMS
+        if pixels is not None:
+            pixels = np.ascontiguousarray(pixels, np.int32)
+            out = np.empty((len(pixels), 3), np.float32)
+            npx = len(pixels)
+        else:
+            out = np.empty((cam.height, cam.width, 3), np.float32)
+            npx = 0
+        _check(lib().oracle_nrc_render(self._h, ctypes.byref(cam), ctypes.byref(make_medium(medium)),
+                                       ctypes.byref(make_light(light)), int(spp), int(seed), ctypes.byref(ro),
+                                       _vp(params), int(bool(bf16)), int(truncate_bounce), float(sigma_ref),
+                                       _vp(pixels), npx, _vp(out), ctypes.byref(st), int(threads)),
+               "oracle_nrc_render")
+        return out, st.as_dict()
+
+    def nrc_collect(self, camera: dict, medium: dict, light: dict, frame_seed: int, n_paths: int,
+                    max_vertices: int = 4, render=None, threads: int = 1) -> dict:
+        """Training records of one frame (see oracle_nrc_collect): pos,
+        dir, sigma, target, tag, plus each path's pixel and radiance."""
+        cam = make_cam(camera)
+        ro = make_render_opts(render or {})
+        cap = max(1, n_paths * max_vertices)
+        r = dict(pos=np.empty((cap, 3), np.float32), dir=np.empty((cap, 3), np.float32),
+                 sigma=np.empty(cap, np.float32), target=np.empty((cap, 3), np.float32), tag=np.empty(cap, np.int32),
+                 path_pixel=np.empty(max(1, n_paths), np.int32), path_L=np.empty((max(1, n_paths), 3), np.float32))
+        cnt = ctypes.c_int64()
+        _check(lib().oracle_nrc_collect(self._h, ctypes.byref(cam), ctypes.byref(make_medium(medium)),
+                                        ctypes.byref(make_light(light)), int(frame_seed), ctypes.byref(ro),
+                                        int(n_paths), int(max_vertices), _vp(r["pos"]), _vp(r["dir"]),
+                                        _vp(r["sigma"]), _vp(r["target"]), _vp(r["tag"]), ctypes.byref(cnt),
+                                        _vp(r["path_pixel"]), _vp(r["path_L"]), int(threads)), "oracle_nrc_collect")
+        c = cnt.value
+        for k in ("pos", "dir", "sigma", "target", "tag"):
+            r[k] = r[k][:c]
+        r["path_pixel"] = r["path_pixel"][:n_paths]
+        r["path_L"] = r["path_L"][:n_paths]
+        return r
+
+
 def leb_build(density: np.ndarray, n: int, camera: dict, build: dict) -> Grid:
     density = np.ascontiguousarray(density, np.float32)
     assert density.size == n ** 3
@@ -361,31 +423,54 @@ def camera_ray(camera: dict, px, py, u0, u1):
     return o, d
 
 
-def nrc_encode(pos, dirs, sigma_norm) -> np.ndarray:
+def bf16_round(x) -> np.ndarray:
+    """bfloat16 rounding (nearest, ties to even) of FP32 values, as FP32."""
+    x = np.ascontiguousarray(x, np.float32).reshape(-1)
+    f = lib().oracle_bf16_round
+    return np.array([f(float(v)) for v in x], np.float32)
+
+
+def nrc_encode(pos, dirs, sigma, sigma_ref: float) -> np.ndarray:
     pos = np.ascontiguousarray(pos, np.float32).reshape(-1, 3)
     dirs = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
-    sn = np.ascontiguousarray(sigma_norm, np.float32).reshape(-1)
+    sg = np.ascontiguousarray(sigma, np.float32).reshape(-1)
     out = np.empty((len(pos), N_FEATS), np.float32)
-    _check(lib().oracle_nrc_encode(len(pos), _vp(pos), _vp(dirs), _vp(sn), _vp(out)), "oracle_nrc_encode")
+    _check(lib().oracle_nrc_encode(len(pos), _vp(pos), _vp(dirs), _vp(sg), float(sigma_ref), _vp(out)),
+           "oracle_nrc_encode")
     return out
 
 
-def mlp_forward(params, x) -> np.ndarray:
+def mlp_forward(params, x, bf16: bool = False) -> np.ndarray:
     params = np.ascontiguousarray(params, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, N_FEATS)
     y = np.empty((len(x), 3), np.float64)
-    _check(lib().oracle_mlp_forward(_vp(params), len(x), _vp(x), _vp(y)), "oracle_mlp_forward")
+    _check(lib().oracle_mlp_forward(_vp(params), len(x), _vp(x), _vp(y), int(bool(bf16))), "oracle_mlp_forward")
     return y
 
 
-def mlp_backward(params, x, dy):
+def mlp_backward(params, x, dy, bf16: bool = False):
     params = np.ascontiguousarray(params, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, N_FEATS)
     dy = np.ascontiguousarray(dy, np.float64).reshape(-1, 3)
     y = np.empty((len(x), 3), np.float64)
     g = np.empty(N_PARAMS, np.float64)
-    _check(lib().oracle_mlp_backward(_vp(params), len(x), _vp(x), _vp(dy), _vp(y), _vp(g)), "oracle_mlp_backward")
+    _check(lib().oracle_mlp_backward(_vp(params), len(x), _vp(x), _vp(dy), _vp(y), _vp(g), int(bool(bf16))),
+           "oracle_mlp_backward")
     return y, g
+
+
+def nrc_eval_point(params, p, d, sigma, sigma_ref, bf16: bool = True) -> np.ndarray:
+    params = np.ascontiguousarray(params, np.float64)
+    p = np.ascontiguousarray(p, np.float32)
+    d = np.ascontiguousarray(d, np.float32)
+    out = np.empty(3, np.float32)
+    lib().oracle_nrc_eval_point(_vp(params), int(bool(bf16)), float(sigma_ref), _vp(p), _vp(d), float(sigma),
+                                _vp(out))
+    return out
+
+
+def train_pixel(frame_seed: int, j: int, npix: int) -> int:
+    return int(lib().oracle_train_pixel(int(frame_seed), int(j), int(npix)))
 
 
 def nrc_loss_grad(y, target):

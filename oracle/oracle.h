@@ -127,18 +127,33 @@ void  oracle_camera_ray(const ocam* cam, int32_t px, int32_t py, float u0, float
                         float o[3], float d[3]);
 
 /* MLP radiance cache (not in the paper): 76 -> 64 x4 (ReLU) -> 3 (linear).
- * params layout (17,603 floats): for each layer l: W_l row-major
- * [out][in] then b_l[out]. */
-int  oracle_nrc_encode(int64_t count, const float* pos, const float* dir, const float* sigma_norm,
+ * params layout (17,603 values): for each layer l: W_l row-major
+ * [out][in] then b_l[out].  bf16 != 0 rounds every matrix-product operand
+ * to bfloat16 (see mlp.c). */
+float oracle_bf16_round(float x);
+int  oracle_nrc_encode(int64_t count, const float* pos, const float* dir, const float* sigma, float sigma_ref,
                        float* feats /* count x 76 */);
 int  oracle_mlp_forward(const double* params, int64_t count, const double* x /* count x 76 */,
-                        double* y /* count x 3 */);
+                        double* y /* count x 3 */, int32_t bf16);
 int  oracle_mlp_backward(const double* params, int64_t count, const double* x,
-                         const double* dy /* count x 3 */, double* y, double* grads);
+                         const double* dy /* count x 3 */, double* y, double* grads, int32_t bf16);
 int  oracle_nrc_loss_grad(int64_t count, const double* y, const double* target, double* loss,
                           double* dy);
 int  oracle_adam_step(int64_t n, double* params, const double* grads, double* m, double* v,
                       int64_t step, double lr, double beta1, double beta2, double eps);
+void oracle_nrc_eval_point(const double* params, int32_t bf16, float sigma_ref, const float p[3],
+                           const float d[3], float sigma, float out[3]);
+/* Truncated render with the cache, training pixel choice and training
+ * records (transport.c). */
+int  oracle_nrc_render(const ogrid* g, const ocam* cam, const omedium* med, const olight* light, int32_t spp,
+                       uint64_t seed, const orender_opts* opts, const double* params, int32_t bf16,
+                       int32_t truncate_bounce, float sigma_ref, const int32_t* pixels, int64_t n_pixels,
+                       float* out_rgb, orender_stats* stats, int32_t threads);
+int32_t oracle_train_pixel(uint64_t frame_seed, uint32_t j, int64_t npix);
+int  oracle_nrc_collect(const ogrid* g, const ocam* cam, const omedium* med, const olight* light,
+                        uint64_t frame_seed, const orender_opts* opts, int32_t n_paths, int32_t max_vertices,
+                        float* pos, float* dir, float* sigma, float* target, int32_t* tag, int64_t* count,
+                        int32_t* path_pixel, float* path_L, int32_t threads);
 
 #ifdef __cplusplus
 }

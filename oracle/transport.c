@@ -438,9 +438,26 @@ static float shadow(const medium_t* m, int64_t cell, const float x[3], const flo
   return tr;
 }
 
+/* Radiance cache hooks of a path (NULL: the plain estimator).
+ *   truncate > 0: at real vertex `truncate` the path adds the cache's
+ *     estimate times the throughput reaching the vertex (before the albedo)
+ *     and stops; there is no light estimate at that vertex (the cache covers
+ *     it).
+ *   rec != NULL: vertices 1..max_rec are recorded, 11 floats each: the
+ *     vertex x (3), the incoming direction d (3), the cell's extinction, the
+ *     throughput reaching the vertex, and L gathered before it (3);
+ *     *n_rec = number recorded. */
+typedef struct {
+  int32_t truncate;
+  const double* params;
+  int32_t bf16;
+  float sigma_ref;
+  int32_t max_rec;
+} nrc_hook;
+
 static void trace_path(const medium_t* m, const frame32* fr, const omedium* med, const olight* lt,
                        const orender_opts* op, uint64_t seed, int32_t px, int32_t py, uint32_t sample, float L[3],
-                       orender_stats* st) {
+                       orender_stats* st, const nrc_hook* hk, float* rec, int32_t* n_rec) {
   rng_t rng;
   memset(&rng, 0, sizeof(rng));
   rng.seed = seed;
@@ -505,6 +522,23 @@ static void trace_path(const medium_t* m, const frame32* fr, const omedium* med,
       for (int i = 0; i < 3; i++) x[i] = o[i] + tc * d[i];
       rng.bounce++;
       memset(rng.draws, 0, sizeof(rng.draws));
+      if (hk && hk->truncate == (int32_t)rng.bounce) {
+        float r[3];
+        oracle_nrc_eval_point(hk->params, hk->bf16, hk->sigma_ref, x, d, cell_sigma(m, cell), r);
+        for (int c = 0; c < 3; c++) L[c] = L[c] + beta[c] * r[c];
+        return;
+      }
+      if (rec && (int32_t)rng.bounce <= hk->max_rec) {
+        float* q = rec + 11 * (rng.bounce - 1);
+        for (int i = 0; i < 3; i++) {
+          q[i] = x[i];
+          q[3 + i] = d[i];
+          q[8 + i] = L[i];
+        }
+        q[6] = cell_sigma(m, cell);
+        q[7] = beta[0];
+        *n_rec = (int32_t)rng.bounce;
+      }
       for (int c = 0; c < 3; c++) beta[c] = beta[c] * med->albedo;
       float tr = shadow(m, cell, x, lt->sun_dir, op->transmittance, &rng, &b);
       if (tr < 0.0f) {
@@ -550,7 +584,7 @@ static int check_render_args(const ocam* cam, const omedium* med, const olight* 
 
 static int render_common(const medium_t* m, const ocam* cam, const omedium* med, const olight* lt, int32_t spp,
                          uint64_t seed, const orender_opts* op, const int32_t* pixels, int64_t n_pixels,
-                         float* out, orender_stats* stats, int32_t threads) {
+                         float* out, orender_stats* stats, int32_t threads, const nrc_hook* hk) {
   int rc = check_render_args(cam, med, lt, spp, op, pixels, pixels ? n_pixels : 0, out);
   if (rc) return rc;
   frame32 fr;
@@ -570,7 +604,8 @@ static int render_common(const medium_t* m, const ocam* cam, const omedium* med,
     float acc[3] = {0.0f, 0.0f, 0.0f};
     for (int32_t s = 0; s < spp; s++) {
       float L[3];
-      trace_path(m, &fr, med, lt, op, seed, px, py, (uint32_t)(op->sample_offset + s), L, &st);
+      trace_path(m, &fr, med, lt, op, seed, px, py, (uint32_t)(op->sample_offset + s), L, &st, hk, NULL,
+                 NULL);
       for (int c = 0; c < 3; c++) acc[c] = acc[c] + L[c];
     }
     for (int c = 0; c < 3; c++) out[3 * i + c] = acc[c] / (float)spp;
@@ -595,7 +630,7 @@ int oracle_tet_render(const ogrid* g, const ocam* cam, const omedium* med, const
                       float* out_rgb, orender_stats* stats, int32_t threads) {
   if (!g) return -1;
   medium_t m = {0, g, NULL, 0, 1.0f};
-  return render_common(&m, cam, med, light, spp, seed, opts, pixels, n_pixels, out_rgb, stats, threads);
+  return render_common(&m, cam, med, light, spp, seed, opts, pixels, n_pixels, out_rgb, stats, threads, NULL);
 }
 
 int oracle_dda_render(const float* density, int32_t n, float density_scale, const ocam* cam, const omedium* med,
@@ -604,7 +639,7 @@ int oracle_dda_render(const float* density, int32_t n, float density_scale, cons
                       int32_t threads) {
   if (!density || n < 1 || (n & (n - 1))) return -1;
   medium_t m = {1, NULL, density, n, density_scale};
-  return render_common(&m, cam, med, light, spp, seed, opts, pixels, n_pixels, out_rgb, stats, threads);
+  return render_common(&m, cam, med, light, spp, seed, opts, pixels, n_pixels, out_rgb, stats, threads, NULL);
 }
 
 int oracle_walk(const ogrid* g, const float o[3], const float d[3], int64_t start, int32_t max_out, int64_t* tets,
@@ -628,5 +663,96 @@ int oracle_walk(const ogrid* g, const float o[3], const float d[3], int64_t star
     cell = next;
   }
   *n_out = k;
+  return 0;
+}
+
+/* ---------------- radiance cache (not in the paper) ----------------
+ * Truncated render: every path stops at real vertex truncate_bounce, adding
+ * the throughput reaching it times the cache's estimate there. */
+int oracle_nrc_render(const ogrid* g, const ocam* cam, const omedium* med, const olight* light, int32_t spp,
+                      uint64_t seed, const orender_opts* opts, const double* params, int32_t bf16,
+                      int32_t truncate_bounce, float sigma_ref, const int32_t* pixels, int64_t n_pixels,
+                      float* out_rgb, orender_stats* stats, int32_t threads) {
+  if (!g || !params || truncate_bounce < 1 || !(sigma_ref > 0.0f)) return -1;
+  medium_t m = {0, g, NULL, 0, 1.0f};
+  nrc_hook hk = {truncate_bounce, params, bf16, sigma_ref, 0};
+  return render_common(&m, cam, med, light, spp, seed, opts, pixels, n_pixels, out_rgb, stats, threads, &hk);
+}
+
+/* Pixel of training path j: a 24-bit uniform integer w (from the draw of
+ * stream 4 with counter pixel = j, sample 0, bounce 0) scaled to the image,
+ * floor(w * npix / 2^24). */
+int32_t oracle_train_pixel(uint64_t frame_seed, uint32_t j, int64_t npix) {
+  float u = oracle_uniform(frame_seed, j, 0, 0, 4, 0);
+  uint64_t w = (uint64_t)(u * 16777216.0f);
+  return (int32_t)((w * (uint64_t)npix) >> 24);
+}
+
+/* Training records of one frame: path j (0 <= j < n_paths) is the plain
+ * estimator's sample j of pixel oracle_train_pixel(frame_seed, j) with seed
+ * frame_seed, never truncated.  Its vertices k = 1..max_vertices with a
+ * positive throughput give one record each, in (path, vertex) order: the
+ * vertex, the incoming direction, the cell's extinction and the target
+ * (L_final - L_before_k) / beta_k (FP32, per channel), where beta_k is the
+ * throughput reaching vertex k (before its albedo) and L_before_k the
+ * radiance gathered before it; tag = 16 j + (k - 1).  Arrays hold
+ * n_paths * max_vertices records; path_pixel and path_L (n_paths and
+ * 3 n_paths, may be NULL) receive each path's pixel and final radiance. */
+int oracle_nrc_collect(const ogrid* g, const ocam* cam, const omedium* med, const olight* light, uint64_t frame_seed,
+                       const orender_opts* opts, int32_t n_paths, int32_t max_vertices, float* pos, float* dir,
+                       float* sigma, float* target, int32_t* tag, int64_t* count, int32_t* path_pixel, float* path_L,
+                       int32_t threads) {
+  if (!g || n_paths < 0 || n_paths > (1 << 26) || max_vertices < 1 || max_vertices > 16 || !pos || !dir || !sigma ||
+      !target || !tag || !count)
+    return -1;
+  int rc = check_render_args(cam, med, light, 1, opts, NULL, 0, target);
+  if (rc) return rc;
+  medium_t m = {0, g, NULL, 0, 1.0f};
+  frame32 fr;
+  make_frame(cam, &fr);
+  int64_t npix = (int64_t)cam->width * cam->height;
+  float* rec = (float*)malloc(sizeof(float) * 11 * (size_t)max_vertices * (size_t)(n_paths ? n_paths : 1));
+  int32_t* nv = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_paths ? n_paths : 1));
+  float* Lf = (float*)malloc(sizeof(float) * 3 * (size_t)(n_paths ? n_paths : 1));
+  if (!rec || !nv || !Lf) {
+    free(rec);
+    free(nv);
+    free(Lf);
+    return -2;
+  }
+  nrc_hook hk = {0, NULL, 0, 0.0f, max_vertices};
+  int nt = threads > 1 ? threads : 1;
+  (void)nt;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+  for (int32_t j = 0; j < n_paths; j++) {
+    int32_t pix = oracle_train_pixel(frame_seed, (uint32_t)j, npix);
+    orender_stats st;
+    memset(&st, 0, sizeof(st));
+    nv[j] = 0;
+    trace_path(&m, &fr, med, light, opts, frame_seed, (int32_t)(pix % cam->width), (int32_t)(pix / cam->width),
+               (uint32_t)j, Lf + 3 * (size_t)j, &st, &hk, rec + 11 * (size_t)max_vertices * (size_t)j, nv + j);
+    if (path_pixel) path_pixel[j] = pix;
+  }
+  int64_t c = 0;
+  for (int32_t j = 0; j < n_paths; j++) {
+    for (int32_t k = 0; k < nv[j]; k++) {
+      const float* q = rec + 11 * ((size_t)max_vertices * (size_t)j + (size_t)k);
+      if (!(q[7] > 0.0f)) continue;
+      for (int i = 0; i < 3; i++) {
+        pos[3 * c + i] = q[i];
+        dir[3 * c + i] = q[3 + i];
+        target[3 * c + i] = (Lf[3 * j + i] - q[8 + i]) / q[7];
+      }
+      sigma[c] = q[6];
+      tag[c] = 16 * j + k;
+      c++;
+    }
+    if (path_L)
+      for (int i = 0; i < 3; i++) path_L[3 * j + i] = Lf[3 * j + i];
+  }
+  *count = c;
+  free(rec);
+  free(nv);
+  free(Lf);
   return 0;
 }
