@@ -44,7 +44,7 @@ typedef enum {
 } tet_status;
 
 typedef struct tet_grid tet_grid; /* device-resident grid, library-owned */
-typedef struct tet_nrc tet_nrc;   /* radiance-cache state, library-owned */
+typedef struct tet_nrc tet_nrc;   /* radiance cache (network and optimiser state), library-owned */
 
 /* Dense density volume: n^3 FP32 values, voxel (i,j,k) at index
  * i + n (j + n k), covering [i/n,(i+1)/n) x ... of the unit cube (the
@@ -105,6 +105,8 @@ typedef struct {
   int32_t record_layout;      /* tet records walked: 32 (compact), 48, or 0 = compact when the grid has them */
   int32_t batch_items;        /* work items a wave takes at a time (0 = default 64) */
   int32_t event_wait;         /* lanes of a wave that wait for an event before events run (0 = default 48) */
+  const tet_nrc* nrc;         /* radiance cache: NULL = plain estimator; else paths stop at the cache's
+                                 truncate_bounce-th real vertex and add throughput x cache (tet grids only) */
 } tet_render_opts;
 
 typedef struct {
@@ -115,6 +117,7 @@ typedef struct {
   int64_t truncated;       /* paths stopped by max_steps_per_path */
   double ms;               /* device time of the whole render call */
   double trace_ms;         /* device time of the persistent tracing kernel(s) alone */
+  double cache_ms;         /* device time of the radiance-cache queries (0 without a cache) */
 } tet_render_stats;
 
 typedef struct {
@@ -174,6 +177,95 @@ int dda_render(const tet_density* density, const tet_camera* camera, const tet_m
                int32_t on_device, void* hip_stream, tet_render_stats* stats);
 
 void tet_grid_free(tet_grid* grid);
+
+/* ---------------------------------------------------------------- radiance cache
+ * A learned radiance cache (an addition to the paper's method, after
+ * Mueller et al. 2021, "Real-time Neural Radiance Caching for Path
+ * Tracing").  A small MLP maps a path vertex -- its position p, the
+ * incoming direction d and the extinction sigma of the cell holding it --
+ * to the radiance the rest of the path brings back per unit of throughput
+ * reaching the vertex (before the vertex's albedo).  Rendering with a cache
+ * (tet_render_opts.nrc) stops every path at real vertex truncate_bounce
+ * and adds throughput x max(cache, 0) there; that vertex gets no light
+ * estimate of its own (the cache covers it).  The cache learns online from
+ * untruncated training paths of the scene (tet_nrc_train_frame).
+ *
+ * Network: 76 features -> 64 -> 64 -> 64 -> 64 -> 3, ReLU after hidden
+ * layers, linear output; 17,603 parameters, stored layer by layer as W
+ * (row-major [out][in]) then b.  Features: for axis a = x, y, z and
+ * k = 0..11, sin(2^k pi p_a) at 24 a + 2 k and cos(2^k pi p_a) at
+ * 24 a + 2 k + 1; then d (72..74) and log(1 + sigma) / log(1 + sigma_ref)
+ * (75).  Products run on the matrix cores in BF16 with FP32 accumulation:
+ * the weights, each layer's input and the back-propagated errors are
+ * rounded to bfloat16 (nearest, ties to even); biases, bias gradients,
+ * loss and Adam stay FP32, on FP32 master weights.  Loss: relative L2,
+ * 1/(3B) sum (y - t)^2 / (y^2 + 0.01) with the denominator held constant.
+ * Optimiser: Adam with bias correction.
+ *
+ * Training paths of a frame: path j < train_paths is the plain estimator's
+ * sample j (Philox key frame_seed) of pixel floor(w (W H) / 2^24), w = the
+ * upper 24 bits of word 0 of Philox(counter (j, 0, 4, 0)).  Each of its
+ * real vertices k <= train_vertices with a positive throughput beta_k gives
+ * a record (p, d, sigma, target = (L_final - L_before_k) / beta_k), in
+ * (path, vertex) order. */
+
+typedef struct {
+  int32_t truncate_bounce;  /* real vertex at which rendering queries the cache, >= 1 (default 2) */
+  int32_t train_paths;      /* training paths per frame, 1..2^24 (default 16384) */
+  int32_t train_vertices;   /* vertices recorded per training path, 1..16 (default 4) */
+  int32_t train_steps;      /* Adam steps per frame; the frame's records split in equal consecutive
+                               batches (default 4) */
+  float lr, beta1, beta2, eps; /* Adam (defaults 1e-3, 0.9, 0.99, 1e-8) */
+  float sigma_ref;          /* extinction normaliser of the features, > 0; 0 = the largest extinction of
+                               the first grid trained on (default 0) */
+  int32_t reserved;
+  uint64_t seed;            /* weight initialisation (He-uniform weights, zero biases) */
+} tet_nrc_opts;
+
+typedef struct {
+  int64_t records;  /* training records of the frame */
+  double loss;      /* mean over the frame's Adam steps of the batch loss before the step */
+  double ms;        /* device time of the call */
+  double trace_ms;  /* of which tracing the training paths */
+} tet_nrc_stats;
+
+void tet_nrc_opts_defaults(tet_nrc_opts* o);
+/* New cache on the current device; *out receives the handle. */
+int tet_nrc_create(const tet_nrc_opts* opts /* NULL = defaults */, tet_nrc** out);
+void tet_nrc_free(tet_nrc* nrc);
+/* Options in force (sigma_ref resolved once set) and Adam steps taken. */
+int tet_nrc_info(const tet_nrc* nrc, tet_nrc_opts* opts, int64_t* adam_steps);
+/* FP32 master parameters out / in (17,603 values, layout above); import
+ * also resets the Adam moments and step count. */
+int tet_nrc_export(const tet_nrc* nrc, float* params, int32_t on_device, void* hip_stream);
+int tet_nrc_import(tet_nrc* nrc, const float* params, int32_t on_device, void* hip_stream);
+/* Network outputs (unclamped) at `count` points: pos, dir count x 3,
+ * sigma count (raw extinction), y count x 3; all on one side.  Needs
+ * sigma_ref set. */
+int tet_nrc_infer(const tet_nrc* nrc, int64_t count, const float* pos, const float* dir, const float* sigma,
+                  float* y, int32_t on_device, void* hip_stream);
+/* Gradient of sum_n dy_n . y_n over the parameters for explicit features
+ * (count x 76 FP32) and output gradients dy (count x 3), with y; the cache
+ * is not changed.  count <= 2^20.  grads: 17,603 values. */
+int tet_nrc_forward_backward(const tet_nrc* nrc, int32_t count, const float* feats, const float* dy, float* y,
+                             float* grads, int32_t on_device, void* hip_stream);
+/* One Adam step on the relative-L2 loss of `count` records (count <= 2^20);
+ * *loss (host, nullable) receives the batch loss before the step. */
+int tet_nrc_train_batch(tet_nrc* nrc, int32_t count, const float* pos, const float* dir, const float* sigma,
+                        const float* target, float* loss, int32_t on_device, void* hip_stream);
+/* The training records of one frame (see above), without training:
+ * capacity records at most (TET_ERR_CAPACITY beyond it, with *count set to
+ * the number needed); tag = 16 j + (k - 1).  opts (nullable) gives
+ * max_bounces, transmittance and max_steps_per_path of the paths. */
+int tet_nrc_collect(const tet_nrc* nrc, const tet_grid* grid, const tet_camera* camera, const tet_medium* medium,
+                    const tet_light* light, uint64_t frame_seed, const tet_render_opts* opts, float* pos, float* dir,
+                    float* sigma, float* target, int32_t* tag, int64_t capacity, int64_t* count, int32_t on_device,
+                    void* hip_stream);
+/* Online training for one frame: trace the frame's training paths, then
+ * train_steps Adam steps over their records. */
+int tet_nrc_train_frame(tet_nrc* nrc, const tet_grid* grid, const tet_camera* camera, const tet_medium* medium,
+                        const tet_light* light, uint64_t frame_seed, const tet_render_opts* opts, void* hip_stream,
+                        tet_nrc_stats* stats /* nullable */);
 
 /* Frees device memory cached by the library between calls. */
 void tet_release_cache(void);

@@ -142,8 +142,127 @@ def dda_render(density, n: int, density_scale: float, camera: dict, medium: dict
     return out, st.as_dict()
 
 
+N_PARAMS = 17603  # radiance-cache parameters (76 -> 64 x 4 -> 3, with biases)
+
+
+def _dev(a, dtype, shape):
+    """A contiguous CUDA float32/int32 tensor of `shape` from a tensor or array."""
+    import torch
+    t = torch.as_tensor(a, dtype=dtype)
+    if not t.is_cuda:
+        t = t.cuda()
+    return t.contiguous().reshape(shape)
+
+
+class Nrc:
+    """Learned radiance cache (include/tetvol.h, tet_nrc_*): a handle to the
+    network, its FP32 master weights and Adam state on the device."""
+
+    def __init__(self, opts: dict | None = None):
+        o = _abi.make_nrc_opts(opts)
+        h = ctypes.c_void_p()
+        check(lib().tet_nrc_create(ctypes.byref(o), ctypes.byref(h)), "tet_nrc_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            try:
+                lib().tet_nrc_free(h)
+            except Exception:
+                pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        o = _abi.TetNrcOpts()
+        steps = ctypes.c_int64()
+        check(lib().tet_nrc_info(self._h, ctypes.byref(o), ctypes.byref(steps)), "tet_nrc_info")
+        return {**o.as_dict(), "adam_steps": steps.value}
+
+    def export(self) -> np.ndarray:
+        p = np.empty(N_PARAMS, np.float32)
+        check(lib().tet_nrc_export(self._h, p.ctypes.data, 0, _stream()), "tet_nrc_export")
+        return p
+
+    def load(self, params) -> None:
+        """Sets the master weights (17,603 FP32) and resets Adam."""
+        p = np.ascontiguousarray(params, np.float32).reshape(-1)
+        assert p.size == N_PARAMS
+        check(lib().tet_nrc_import(self._h, p.ctypes.data, 0, _stream()), "tet_nrc_import")
+
+    def infer(self, pos, dirs, sigma):
+        """Network outputs (unclamped) at points: CUDA tensors in and out."""
+        import torch
+        pos = _dev(pos, torch.float32, (-1, 3))
+        n = pos.shape[0]
+        dirs = _dev(dirs, torch.float32, (n, 3))
+        sigma = _dev(sigma, torch.float32, (n,))
+        y = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+        check(lib().tet_nrc_infer(self._h, n, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(dirs.data_ptr()),
+                                  ctypes.c_void_p(sigma.data_ptr()), ctypes.c_void_p(y.data_ptr()), 1, _stream()),
+              "tet_nrc_infer")
+        return y
+
+    def forward_backward(self, feats, dy):
+        """(y, grads) for explicit features (B x 76) and output gradients."""
+        import torch
+        feats = _dev(feats, torch.float32, (-1, 76))
+        n = feats.shape[0]
+        dy = _dev(dy, torch.float32, (n, 3))
+        y = torch.empty((n, 3), dtype=torch.float32, device=feats.device)
+        g = torch.empty(N_PARAMS, dtype=torch.float32, device=feats.device)
+        check(lib().tet_nrc_forward_backward(self._h, n, ctypes.c_void_p(feats.data_ptr()),
+                                             ctypes.c_void_p(dy.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                             ctypes.c_void_p(g.data_ptr()), 1, _stream()), "tet_nrc_forward_backward")
+        return y, g
+
+    def train_batch(self, pos, dirs, sigma, target) -> float:
+        """One Adam step on explicit records; returns the loss before it."""
+        import torch
+        pos = _dev(pos, torch.float32, (-1, 3))
+        n = pos.shape[0]
+        dirs = _dev(dirs, torch.float32, (n, 3))
+        sigma = _dev(sigma, torch.float32, (n,))
+        target = _dev(target, torch.float32, (n, 3))
+        loss = ctypes.c_float()
+        check(lib().tet_nrc_train_batch(self._h, n, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(dirs.data_ptr()),
+                                        ctypes.c_void_p(sigma.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                        ctypes.byref(loss), 1, _stream()), "tet_nrc_train_batch")
+        return loss.value
+
+    def collect(self, grid: Grid, camera: dict, medium: dict, light: dict, frame_seed: int,
+                render: dict | None = None) -> dict:
+        """The frame's training records (host arrays): pos, dir, sigma,
+        target, tag."""
+        info = self.info()
+        cap = info["train_paths"] * info["train_vertices"]
+        r = dict(pos=np.empty((cap, 3), np.float32), dir=np.empty((cap, 3), np.float32),
+                 sigma=np.empty(cap, np.float32), target=np.empty((cap, 3), np.float32), tag=np.empty(cap, np.int32))
+        cnt = ctypes.c_int64()
+        check(lib().tet_nrc_collect(self._h, grid.handle, ctypes.byref(_abi.make_camera(camera)),
+                                    ctypes.byref(_abi.make_medium(medium)), ctypes.byref(_abi.make_light(light)),
+                                    int(frame_seed), ctypes.byref(_abi.make_render_opts(render)),
+                                    r["pos"].ctypes.data, r["dir"].ctypes.data, r["sigma"].ctypes.data,
+                                    r["target"].ctypes.data, r["tag"].ctypes.data, cap, ctypes.byref(cnt), 0,
+                                    _stream()), "tet_nrc_collect")
+        return {k: v[:cnt.value] for k, v in r.items()}
+
+    def train_frame(self, grid: Grid, camera: dict, medium: dict, light: dict, frame_seed: int,
+                    render: dict | None = None) -> dict:
+        st = _abi.TetNrcStats()
+        check(lib().tet_nrc_train_frame(self._h, grid.handle, ctypes.byref(_abi.make_camera(camera)),
+                                        ctypes.byref(_abi.make_medium(medium)), ctypes.byref(_abi.make_light(light)),
+                                        int(frame_seed), ctypes.byref(_abi.make_render_opts(render)), _stream(),
+                                        ctypes.byref(st)), "tet_nrc_train_frame")
+        return st.as_dict()
+
+
 def release_cache():
     lib().tet_release_cache()
 
 
-__all__ = ["Grid", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]
+__all__ = ["Grid", "Nrc", "N_PARAMS", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]

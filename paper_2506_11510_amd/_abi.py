@@ -53,13 +53,32 @@ class TetRenderOpts(ctypes.Structure):
                 ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32),
                 ("samples_per_item", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("record_layout", ctypes.c_int32), ("batch_items", ctypes.c_int32), ("event_wait", ctypes.c_int32)]
+                ("record_layout", ctypes.c_int32), ("batch_items", ctypes.c_int32), ("event_wait", ctypes.c_int32),
+                ("nrc", ctypes.c_void_p)]
 
 
 class TetRenderStats(ctypes.Structure):
     _fields_ = [("tet_steps", ctypes.c_int64), ("null_collisions", ctypes.c_int64),
                 ("real_collisions", ctypes.c_int64), ("escapes", ctypes.c_int64), ("truncated", ctypes.c_int64),
-                ("ms", ctypes.c_double), ("trace_ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("trace_ms", ctypes.c_double), ("cache_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TetNrcOpts(ctypes.Structure):
+    _fields_ = [("truncate_bounce", ctypes.c_int32), ("train_paths", ctypes.c_int32),
+                ("train_vertices", ctypes.c_int32), ("train_steps", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("sigma_ref", ctypes.c_float), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class TetNrcStats(ctypes.Structure):
+    _fields_ = [("records", ctypes.c_int64), ("loss", ctypes.c_double), ("ms", ctypes.c_double),
+                ("trace_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +111,22 @@ SIGNATURES = {
                                   ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32, VP,
                                   ctypes.POINTER(TetRenderStats)]),
     "tet_grid_free": (None, [VP]),
+    "tet_nrc_opts_defaults": (None, [ctypes.POINTER(TetNrcOpts)]),
+    "tet_nrc_create": (ctypes.c_int, [ctypes.POINTER(TetNrcOpts), ctypes.POINTER(VP)]),
+    "tet_nrc_free": (None, [VP]),
+    "tet_nrc_info": (ctypes.c_int, [VP, ctypes.POINTER(TetNrcOpts), ctypes.POINTER(ctypes.c_int64)]),
+    "tet_nrc_export": (ctypes.c_int, [VP, VP, ctypes.c_int32, VP]),
+    "tet_nrc_import": (ctypes.c_int, [VP, VP, ctypes.c_int32, VP]),
+    "tet_nrc_infer": (ctypes.c_int, [VP, ctypes.c_int64, VP, VP, VP, VP, ctypes.c_int32, VP]),
+    "tet_nrc_forward_backward": (ctypes.c_int, [VP, ctypes.c_int32, VP, VP, VP, VP, ctypes.c_int32, VP]),
+    "tet_nrc_train_batch": (ctypes.c_int, [VP, ctypes.c_int32, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),
+    "tet_nrc_collect": (ctypes.c_int, [VP, VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium),
+                                       ctypes.POINTER(TetLight), ctypes.c_uint64, ctypes.POINTER(TetRenderOpts),
+                                       VP, VP, VP, VP, VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.c_int32, VP]),
+    "tet_nrc_train_frame": (ctypes.c_int, [VP, VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium),
+                                           ctypes.POINTER(TetLight), ctypes.c_uint64, ctypes.POINTER(TetRenderOpts),
+                                           VP, ctypes.POINTER(TetNrcStats)]),
     "tet_release_cache": (None, []),
     "tet_last_error": (ctypes.c_char_p, []),
 }
@@ -153,9 +188,23 @@ def make_build_opts(b: dict | None) -> TetBuildOpts:
 
 
 def make_render_opts(r: dict | None) -> TetRenderOpts:
+    """Render options from a dict; "nrc" takes a cache object (with a
+    `handle`) or None."""
     o = TetRenderOpts()
     lib().tet_render_opts_defaults(ctypes.byref(o))
     for k, v in (r or {}).items():
-        if hasattr(o, k) and k != "reserved":
+        if k == "nrc":
+            o.nrc = v.handle if v is not None else None
+        elif hasattr(o, k) and k != "reserved":
             setattr(o, k, type(getattr(o, k))(v))
+    return o
+
+
+def make_nrc_opts(d: dict | None) -> TetNrcOpts:
+    o = TetNrcOpts()
+    lib().tet_nrc_opts_defaults(ctypes.byref(o))
+    for k, v in (d or {}).items():
+        if not hasattr(o, k) or k == "reserved":
+            raise KeyError(f"unknown radiance-cache option {k}")
+        setattr(o, k, type(getattr(o, k))(v))
     return o

@@ -9,7 +9,7 @@
 #include <string>
 #include <unordered_map>
 
-#include "common.h"
+#include "nrc.h"
 
 namespace tv {
 
@@ -301,6 +301,75 @@ void tet_release_cache(void) {
     it = g_free.erase(it);
   }
   (void)hipSetDevice(cur);
+}
+
+void tet_nrc_opts_defaults(tet_nrc_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->truncate_bounce = 2;
+  o->train_paths = 16384;
+  o->train_vertices = 4;
+  o->train_steps = 4;
+  o->lr = 1e-3f;
+  o->beta1 = 0.9f;
+  o->beta2 = 0.99f;
+  o->eps = 1e-8f;
+  o->sigma_ref = 0.0f;
+  o->seed = 0x5EEDull;
+}
+
+int tet_nrc_create(const tet_nrc_opts* opts, tet_nrc** out) { TV_GUARD(nrc_create(opts, out)); }
+
+void tet_nrc_free(tet_nrc* nrc) {
+  if (!nrc) return;
+  int cur = 0;
+  bool sw = hipGetDevice(&cur) == hipSuccess && cur != nrc->device && hipSetDevice(nrc->device) == hipSuccess;
+  nrc_free(nrc);
+  if (sw) (void)hipSetDevice(cur);
+}
+
+int tet_nrc_info(const tet_nrc* nrc, tet_nrc_opts* opts, int64_t* adam_steps) {
+  if (!nrc) return fail(TET_ERR_INVALID_ARG, "tet_nrc_info: cache is NULL");
+  if (opts) *opts = nrc->opts;
+  if (adam_steps) *adam_steps = nrc->step;
+  return TET_OK;
+}
+
+int tet_nrc_export(const tet_nrc* nrc, float* params, int32_t on_device, void* hip_stream) {
+  TV_GUARD(nrc_export(nrc, params, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_import(tet_nrc* nrc, const float* params, int32_t on_device, void* hip_stream) {
+  TV_GUARD(nrc_import(nrc, params, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_infer(const tet_nrc* nrc, int64_t count, const float* pos, const float* dir, const float* sigma, float* y,
+                  int32_t on_device, void* hip_stream) {
+  TV_GUARD(nrc_infer(nrc, count, pos, dir, sigma, y, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_forward_backward(const tet_nrc* nrc, int32_t count, const float* feats, const float* dy, float* y,
+                             float* grads, int32_t on_device, void* hip_stream) {
+  TV_GUARD(nrc_forward_backward(nrc, count, feats, dy, y, grads, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_train_batch(tet_nrc* nrc, int32_t count, const float* pos, const float* dir, const float* sigma,
+                        const float* target, float* loss, int32_t on_device, void* hip_stream) {
+  TV_GUARD(nrc_train_batch(nrc, count, pos, dir, sigma, target, loss, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_collect(const tet_nrc* nrc, const tet_grid* grid, const tet_camera* camera, const tet_medium* medium,
+                    const tet_light* light, uint64_t frame_seed, const tet_render_opts* opts, float* pos, float* dir,
+                    float* sigma, float* target, int32_t* tag, int64_t capacity, int64_t* count, int32_t on_device,
+                    void* hip_stream) {
+  TV_GUARD(nrc_collect(nrc, grid, camera, medium, light, frame_seed, opts, pos, dir, sigma, target, tag, capacity,
+                       count, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_train_frame(tet_nrc* nrc, const tet_grid* grid, const tet_camera* camera, const tet_medium* medium,
+                        const tet_light* light, uint64_t frame_seed, const tet_render_opts* opts, void* hip_stream,
+                        tet_nrc_stats* stats) {
+  TV_GUARD(nrc_train_frame(nrc, grid, camera, medium, light, frame_seed, opts, (hipStream_t)hip_stream, stats));
 }
 
 const char* tet_last_error(void) { return g_err.c_str(); }

@@ -39,7 +39,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "common.h"
+#include "nrc.h"
 
 namespace tv {
 
@@ -73,7 +73,23 @@ struct RenderArgs {
   uint32_t* counter;
   unsigned long long* stats;
   int accumulate;
+  // radiance cache
+  int32_t train;         // work items are training paths (pixel from train_pixel, sample = item)
+  uint32_t npix;         // width * height
+  int32_t truncate;      // real vertex where a path queries the cache
+  int32_t rec_vertices;  // vertices recorded per training path
+  float4* qrec;          // queries, over the entry records
+  float4* vrec;          // training-path vertex records
+  float4* path_l;        // training-path radiance and vertex count
+  const tet_nrc* nrc;    // host handle (the query pass), never read on the device
 };
+
+// Pixel of training path j: floor(w npix / 2^24), w = the upper 24 bits of
+// word 0 of Philox(counter (j, 0, 4, 0)).
+__device__ inline uint32_t train_pixel(uint64_t seed, uint32_t j, uint32_t npix) {
+  uint4 r = philox10(make_uint4(j, 0u, 4u, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+  return (uint32_t)(((uint64_t)(r.x >> 8) * npix) >> 24);
+}
 
 // pixel of a slot: 8x8 tiles in row-major tile order
 __device__ inline bool slot_pixel(uint32_t slot, int32_t tiles_x, int32_t w, int32_t h, int32_t& px, int32_t& py) {
@@ -174,6 +190,7 @@ struct TetMedium {
   int64_t n;
   int dmax;
   __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
+  __device__ inline float sigma_at(uint32_t cell) const { return rec[cell].sigma; }
   // Exit of the tet along the segment whose direction-dot table is `tab`
   // (tab[N] = dir_N . d, tab[9 + N] = dir_N . o) from t: faces with
   // n.d > 0 are candidates; the exit face has the smallest exact quotient
@@ -228,6 +245,7 @@ struct TetMedium32 {
   int64_t n;
   int dmax;
   __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
+  __device__ inline float sigma_at(uint32_t cell) const { return __uint_as_float(rec[cell].w[3]); }
   __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
     const uint4* q = (const uint4*)(rec + cell);
     const uint4 a = q[0], b = q[1];
@@ -278,6 +296,7 @@ struct VoxelMedium {
     }
     return idx[0] + n * (idx[1] + (int64_t)n * idx[2]);
   }
+  __device__ inline float sigma_at(uint32_t cell) const { return scale * dens[cell]; }
   __device__ inline Step step(uint32_t cell, float3 o, float3 d, const float*, float t) const {
     int32_t idx[3] = {(int32_t)(cell % (uint32_t)n), (int32_t)((cell / (uint32_t)n) % (uint32_t)n),
                       (int32_t)(cell / ((uint32_t)n * (uint32_t)n))};
@@ -359,11 +378,25 @@ template <class Med>
 __global__ __launch_bounds__(256) void k_raygen(RenderArgs A, Med med, RayEntry* __restrict__ entries) {
   uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (uint64_t)A.slots * (uint64_t)A.pass_spp) return;
-  uint32_t slot = (uint32_t)(e / (uint32_t)A.pass_spp);
-  uint32_t s = (uint32_t)(A.pass_start + (int32_t)(e % (uint32_t)A.pass_spp));
+  uint32_t pix, s;
   int32_t px, py;
-  if (!slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) return;
-  uint32_t pix = (uint32_t)(py * A.fr.w + px);
+  if (A.train) {
+    s = (uint32_t)e;
+    pix = train_pixel(A.seed, s, A.npix);
+    px = (int32_t)(pix % (uint32_t)A.fr.w);
+    py = (int32_t)(pix / (uint32_t)A.fr.w);
+  } else {
+    uint32_t slot = (uint32_t)(e / (uint32_t)A.pass_spp);
+    s = (uint32_t)(A.pass_start + (int32_t)(e % (uint32_t)A.pass_spp));
+    if (!slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
+      RayEntry z;
+      memset(&z, 0, sizeof(z));
+      z.cell = kMiss;
+      entries[e] = z;  // padding slot of an edge tile: never traced, never queried
+      return;
+    }
+    pix = (uint32_t)(py * A.fr.w + px);
+  }
   uint2 u = uniform01x2(A.seed, pix, s, 0, kStreamCamera, 0);
   float u0 = u01(u.x), u1 = u01(u.y);
   float sx = ((2.0f * (((float)px + u0) / (float)A.fr.w)) - 1.0f) * A.fr.tan_x;
@@ -418,13 +451,16 @@ __device__ inline void set_segment(float* tab, float3 o, float3 d, float oscale)
 }
 
 // W: occupancy target in waves per SIMD (the register budget follows).
-template <class Med, int W>
+// NRC: 0 plain estimator; 1 paths stop at real vertex A.truncate and leave
+// a query for the radiance cache in their entry record; 2 training paths
+// (A.train), whose first vertices and final radiance are recorded.
+template <class Med, int W, int NRC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_render(RenderArgs A, Med med) {
   __shared__ float s_tab[256 * kTabStride];
   float* tab = s_tab + threadIdx.x * kTabStride;
   const int lane = __lane_id();
   int mode = M_FETCH;
-  uint32_t pix = 0, slot = 0;
+  uint32_t pix = 0, ent = 0;  // ent: the sample's entry record
   int32_t s = 0, s_end = 0;
   float3 o = make_float3(0, 0, 0), d = o, dsave = o, L = o, acc = o;
   float beta = 1.0f, t = 0.0f, tau = 0.0f, od = 0.0f;
@@ -440,10 +476,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     unsigned long long waiting = __ballot(mode > M_SHADOW);
     if (waiting && (__popcll(waiting) >= A.event_wait || __popcll(waiting) == 64 ||
                     __ballot(mode <= M_SHADOW) == 0)) {
+      if (NRC == 1 && mode == M_COLLIDE && (int32_t)bounce + 1 == A.truncate) {
+        // the cache stands for the rest of the path: leave a query
+        n_real++;
+        bounce++;
+        float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+        A.qrec[2 * (size_t)ent] = make_float4(x.x, x.y, x.z, med.sigma_at(cell));
+        A.qrec[2 * (size_t)ent + 1] = make_float4(d.x, d.y, d.z, beta);
+        mode = M_FINISH;
+      }
       if (mode == M_COLLIDE) {  // real collision at t: start the light ray
         n_real++;
         float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
         bounce++;
+        if (NRC == 2 && (int32_t)bounce <= A.rec_vertices) {
+          float4* q = A.vrec + ((size_t)ent * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
+          q[0] = make_float4(x.x, x.y, x.z, med.sigma_at(cell));
+          q[1] = make_float4(d.x, d.y, d.z, beta);
+          q[2] = make_float4(L.x, L.y, L.z, 0.0f);
+        }
         jf = 0;
         jn = 0;
         beta = beta * A.albedo;
@@ -489,9 +540,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         acc.z = acc.z + L.z;
         n_steps += steps;
         steps = 0;
+        if (NRC == 2) A.path_l[ent] = make_float4(L.x, L.y, L.z, __uint_as_float(bounce));
         s++;
         if (s < s_end) {
+          ent++;
           mode = M_START;
+        } else if (NRC == 2) {
+          mode = M_FETCH;
         } else {
           float* px = A.out + 3 * (size_t)pix;
           if (A.accumulate) {
@@ -531,17 +586,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         if (bnext < bend) {
           uint32_t item = bnext + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
           if (need && item < bend) {
-            slot = item / (uint32_t)A.items_per_pixel;
-            uint32_t chunk = item % (uint32_t)A.items_per_pixel;
-            int32_t px, py;
-            if (slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
-              pix = (uint32_t)(py * A.fr.w + px);
-              s = A.pass_start + (int32_t)chunk * A.per_item;
-              s_end = min(s + A.per_item, A.pass_start + A.pass_spp);
+            if (NRC == 2) {
+              pix = train_pixel(A.seed, item, A.npix);
+              s = (int32_t)item;
+              s_end = s + 1;
+              ent = item;
               acc = make_float3(0, 0, 0);
               mode = M_START;
             } else {
-              mode = M_FETCH;  // padding slot of an edge tile: take another item
+              uint32_t slot = item / (uint32_t)A.items_per_pixel;
+              uint32_t chunk = item % (uint32_t)A.items_per_pixel;
+              int32_t px, py;
+              if (slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
+                pix = (uint32_t)(py * A.fr.w + px);
+                s = A.pass_start + (int32_t)chunk * A.per_item;
+                s_end = min(s + A.per_item, A.pass_start + A.pass_spp);
+                ent = slot * (uint32_t)A.pass_spp + (uint32_t)(s - A.pass_start);
+                acc = make_float3(0, 0, 0);
+                mode = M_START;
+              } else {
+                mode = M_FETCH;  // padding slot of an edge tile: take another item
+              }
             }
           }
           bnext = min(bnext + (uint32_t)__popcll(m), bend);
@@ -550,13 +615,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         }
       }
       if (mode == M_START) {  // new sample: its precomputed entry into the grid
-        const float4* q =
-            (const float4*)(A.entries + (size_t)slot * (uint32_t)A.pass_spp + (uint32_t)(s - A.pass_start));
+        const float4* q = (const float4*)(A.entries + ent);
         float4 a = q[0], b = q[1];
+        if (NRC == 1) ((float*)(A.qrec + 2 * (size_t)ent + 1))[3] = 0.0f;  // no query (yet)
         uint32_t c = __float_as_uint(a.w);
         steps = 0;
         if (c == kMiss) {
           L = make_float3(A.env[0], A.env[1], A.env[2]);
+          bounce = 0;
           mode = M_FINISH;
         } else {
           o = make_float3(a.x, a.y, a.z);
@@ -679,6 +745,28 @@ __global__ void k_scale_f32(float* p, int64_t n, float div) {
   if (i < n) p[i] = p[i] / div;
 }
 
+// Adds each pixel's cache contributions of one pass (its samples in order).
+__global__ void k_nrc_gather(RenderArgs A, const float4* __restrict__ rec) {
+  uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= A.slots) return;
+  int32_t px, py;
+  if (!slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) return;
+  float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+  const float4* q = rec + 2 * (size_t)slot * (uint32_t)A.pass_spp;
+  for (int32_t k = 0; k < A.pass_spp; k++) {
+    if (q[2 * k + 1].w > 0.0f) {
+      float4 c = q[2 * k];
+      cx = cx + c.x;
+      cy = cy + c.y;
+      cz = cz + c.z;
+    }
+  }
+  float* o = A.out + 3 * ((size_t)py * A.fr.w + px);
+  o[0] = o[0] + cx;
+  o[1] = o[1] + cy;
+  o[2] = o[2] + cz;
+}
+
 __global__ void k_locate(TetMedium med, const float* __restrict__ pts, int64_t count, int64_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -703,30 +791,33 @@ static int cu_count() {
 
 constexpr int64_t kMaxEntriesPerPass = 1ll << 25;  // 1 GiB of entry records
 
-template <class Med>
+template <class Med, int NRC>
 static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, int32_t spp, int64_t npix,
                       char* sc, RayEntry* entries, int64_t pass_cap, hipStream_t st, float* ms_total,
-                      float* ms_trace) {
+                      float* ms_trace, float* ms_cache) {
   int bs = o.block_size ? o.block_size : 256;
   int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
-  hipEvent_t e0, e1, t0, t1;
+  hipEvent_t e0, e1, e2, t0, t1;
   TV_HIP(hipEventCreate(&e0));
   TV_HIP(hipEventCreate(&e1));
+  TV_HIP(hipEventCreate(&e2));
   TV_HIP(hipEventCreate(&t0));
   TV_HIP(hipEventCreate(&t1));
   struct Ev {
-    hipEvent_t a, b, c, d;
+    hipEvent_t a, b, c, d, f;
     ~Ev() {
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
       (void)hipEventDestroy(c);
       (void)hipEventDestroy(d);
+      (void)hipEventDestroy(f);
     }
-  } ev{e0, e1, t0, t1};
+  } ev{e0, e1, e2, t0, t1};
   *ms_total = 0.0f;
   *ms_trace = 0.0f;
+  *ms_cache = 0.0f;
   TV_HIP(hipEventRecord(e0, st));
-  if (A.accumulate)
+  if (A.accumulate && NRC != 2)
     hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3);
   for (int32_t done = 0; done < spp; done += (int32_t)pass_cap) {
     A.pass_start = A.pass_start + (done ? (int32_t)pass_cap : 0);
@@ -746,26 +837,61 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     int64_t need = ((int64_t)P.items + bs - 1) / bs;
     grid = std::max<int64_t>(1, std::min(grid, need));
     TV_HIP(hipEventRecord(t0, st));
-    switch (o.waves_per_simd) {
-      case 4: hipLaunchKernelGGL((k_render<Med, 4>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
-      case 6: hipLaunchKernelGGL((k_render<Med, 6>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
-      case 8: hipLaunchKernelGGL((k_render<Med, 8>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
-      default: hipLaunchKernelGGL((k_render<Med, 5>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+    if (NRC != 0) {
+      hipLaunchKernelGGL((k_render<Med, 5, NRC>), dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+    } else {
+      switch (o.waves_per_simd) {
+        case 4: hipLaunchKernelGGL((k_render<Med, 4, 0>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+        case 6: hipLaunchKernelGGL((k_render<Med, 6, 0>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+        case 8: hipLaunchKernelGGL((k_render<Med, 8, 0>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+        default: hipLaunchKernelGGL((k_render<Med, 5, 0>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+      }
     }
     TV_HIP(hipGetLastError());
     TV_HIP(hipEventRecord(t1, st));
-    TV_HIP(hipEventSynchronize(t1));
+    if (NRC == 1) {  // the pass's cache queries, then their sums per pixel
+      if (int rc = nrc_query_pass(A.nrc, (float4*)entries, (int64_t)ne, st)) return rc;
+      hipLaunchKernelGGL(k_nrc_gather, dim3((P.slots + 255) / 256), dim3(256), 0, st, P, (const float4*)entries);
+      TV_HIP(hipGetLastError());
+    }
+    TV_HIP(hipEventRecord(e2, st));
+    TV_HIP(hipEventSynchronize(e2));
     float ms = 0.0f;
     TV_HIP(hipEventElapsedTime(&ms, t0, t1));
     *ms_trace += ms;
+    TV_HIP(hipEventElapsedTime(&ms, t1, e2));
+    *ms_cache += ms;
   }
-  if (A.accumulate)
+  if (A.accumulate && NRC != 2)
     hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3,
                        (float)spp);
   TV_HIP(hipEventRecord(e1, st));
   TV_HIP(hipEventSynchronize(e1));
   TV_HIP(hipEventElapsedTime(ms_total, e0, e1));
   return TET_OK;
+}
+
+static int check_render_opts(const tet_render_opts& o) {
+  if (o.max_bounces < 1 || o.transmittance < 0 || o.transmittance > 2 || o.max_steps_per_path < 1 ||
+      o.sample_offset < 0 || o.samples_per_item < 0 || o.block_size < 0 || o.block_size > 256 ||
+      (o.block_size % 64) != 0 || o.blocks_per_cu < 0 ||
+      (o.waves_per_simd != 0 && o.waves_per_simd != 4 && o.waves_per_simd != 5 && o.waves_per_simd != 6 &&
+       o.waves_per_simd != 8) ||
+      (o.record_layout != 0 && o.record_layout != 32 && o.record_layout != 48) || o.batch_items < 0 ||
+      o.batch_items > (1 << 20) || o.event_wait < 0 || o.event_wait > 64)
+    return fail(TET_ERR_INVALID_ARG, "render: bad options");
+  return TET_OK;
+}
+
+static void set_scene(RenderArgs& A, const tet_camera* cam, const tet_medium* medm, const tet_light* light) {
+  make_frame(*cam, &A.fr);
+  A.albedo = medm->albedo;
+  A.g = medm->g;
+  for (int i = 0; i < 3; i++) {
+    A.sun[i] = light->sun_dir[i];
+    A.E[i] = light->sun_irradiance[i];
+    A.env[i] = light->env_radiance[i];
+  }
 }
 
 static int render_common(int kind, const tet_grid* g, const tet_density* dens, const tet_camera* cam,
@@ -780,14 +906,11 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   tet_render_opts o;
   if (opts_in) o = *opts_in;
   else tet_render_opts_defaults(&o);
-  if (o.max_bounces < 1 || o.transmittance < 0 || o.transmittance > 2 || o.max_steps_per_path < 1 ||
-      o.sample_offset < 0 || o.samples_per_item < 0 || o.block_size < 0 || o.block_size > 256 ||
-      (o.block_size % 64) != 0 || o.blocks_per_cu < 0 ||
-      (o.waves_per_simd != 0 && o.waves_per_simd != 4 && o.waves_per_simd != 5 && o.waves_per_simd != 6 &&
-       o.waves_per_simd != 8) ||
-      (o.record_layout != 0 && o.record_layout != 32 && o.record_layout != 48) || o.batch_items < 0 ||
-      o.batch_items > (1 << 20) || o.event_wait < 0 || o.event_wait > 64)
-    return fail(TET_ERR_INVALID_ARG, "render: bad options");
+  if (int rc = check_render_opts(o)) return rc;
+  const tet_nrc* nrc = o.nrc;
+  if (nrc && kind != 0) return fail(TET_ERR_UNSUPPORTED, "render: the radiance cache needs a tet grid");
+  if (nrc && !(nrc->opts.sigma_ref > 0.0f))
+    return fail(TET_ERR_INVALID_ARG, "render: the radiance cache has no sigma_ref yet (train it or set one)");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
   int64_t npix = (int64_t)cam->width * cam->height;
   int tiles_x = (cam->width + 7) / 8, tiles_y = (cam->height + 7) / 8;
@@ -800,14 +923,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
 
   RenderArgs A;
   memset(&A, 0, sizeof(A));
-  make_frame(*cam, &A.fr);
-  A.albedo = medm->albedo;
-  A.g = medm->g;
-  for (int i = 0; i < 3; i++) {
-    A.sun[i] = light->sun_dir[i];
-    A.E[i] = light->sun_irradiance[i];
-    A.env[i] = light->env_radiance[i];
-  }
+  set_scene(A, cam, medm, light);
   A.spp = spp;
   A.pass_start = o.sample_offset;
   A.per_item = per_item;
@@ -819,7 +935,11 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.tiles_x = tiles_x;
   A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
   A.event_wait = o.event_wait ? o.event_wait : 48;
-  A.accumulate = (pass_cap < spp) || (per_item < pass_cap);
+  A.accumulate = (pass_cap < spp) || (per_item < pass_cap) || nrc != nullptr;
+  if (nrc) {
+    A.nrc = nrc;
+    A.truncate = nrc->opts.truncate_bounce;
+  }
 
   // scratch: counters, entry records of one pass, image when the output is on the host
   size_t img_bytes = (size_t)npix * 3 * sizeof(float);
@@ -837,18 +957,21 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.out = on_device ? out_rgb : (float*)(sc + 256 + ent_bytes);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
 
-  float ms = 0.0f, ms_trace = 0.0f;
+  A.qrec = (float4*)entries;
+  float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
     TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth};
-    rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
+    rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
+             : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
     TetMedium m{g->rec, g->keys, g->n, g->max_depth};
-    rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
+    rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
+             : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else {
     VoxelMedium m{dens->data, dens->n, dens->density_scale};
-    rc = run_passes(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace);
+    rc = run_passes<VoxelMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   }
   if (rc) return rc;
   unsigned long long hs[5] = {0, 0, 0, 0, 0};
@@ -863,7 +986,65 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     stats->truncated = (int64_t)hs[4];
     stats->ms = ms;
     stats->trace_ms = ms_trace;
+    stats->cache_ms = ms_cache;
   }
+  return TET_OK;
+}
+
+int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_medium* medm, const tet_light* light,
+                         uint64_t frame_seed, const tet_render_opts* opts_in, int32_t n_paths, int32_t kv, float4* vrec,
+                         float4* path_l, hipStream_t st, float* ms_out) {
+  if (!g) return fail(TET_ERR_INVALID_ARG, "training paths: grid is NULL");
+  if (int rc = check_camera(cam)) return rc;
+  if (!medm || !light) return fail(TET_ERR_INVALID_ARG, "training paths: NULL medium or light");
+  if (!(medm->g > -1.0f && medm->g < 1.0f) || !(medm->albedo >= 0.0f))
+    return fail(TET_ERR_INVALID_ARG, "training paths: medium needs albedo >= 0 and -1 < g < 1");
+  tet_render_opts o;
+  if (opts_in) o = *opts_in;
+  else tet_render_opts_defaults(&o);
+  if (int rc = check_render_opts(o)) return rc;
+  if (n_paths < 1 || kv < 1) return fail(TET_ERR_INVALID_ARG, "training paths: bad counts");
+  RenderArgs A;
+  memset(&A, 0, sizeof(A));
+  set_scene(A, cam, medm, light);
+  A.spp = 1;
+  A.per_item = 1;
+  A.max_bounces = o.max_bounces;
+  A.transmittance = o.transmittance;
+  A.max_steps = (uint32_t)std::min<int64_t>(o.max_steps_per_path, 0x7FFFFFFF);
+  A.seed = frame_seed;
+  A.slots = (uint32_t)n_paths;
+  A.tiles_x = (cam->width + 7) / 8;
+  A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
+  A.event_wait = o.event_wait ? o.event_wait : 48;
+  A.train = 1;
+  A.npix = (uint32_t)((int64_t)cam->width * cam->height);
+  A.rec_vertices = kv;
+  A.vrec = vrec;
+  A.path_l = path_l;
+  size_t ent_bytes = (size_t)n_paths * sizeof(RayEntry);
+  char* sc = (char*)dev_alloc(256 + ent_bytes);
+  if (!sc) return fail(TET_ERR_OUT_OF_MEMORY, "training paths: scratch");
+  struct Free {
+    void* p;
+    ~Free() { dev_free(p); }
+  } fr_{sc};
+  A.counter = (uint32_t*)sc;
+  A.stats = (unsigned long long*)(sc + 64);
+  RayEntry* entries = (RayEntry*)(sc + 256);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
+  float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
+  int rc;
+  if (g->rec32 && o.record_layout != 48) {
+    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth};
+    rc = run_passes<TetMedium32, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
+  } else {
+    TetMedium m{g->rec, g->keys, g->n, g->max_depth};
+    rc = run_passes<TetMedium, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
+  }
+  if (rc) return rc;
+  TV_HIP(hipStreamSynchronize(st));
+  if (ms_out) *ms_out = ms_trace;
   return TET_OK;
 }
 
