@@ -5,7 +5,10 @@ adaptive conforming tet grid from a 256^3 fBm cloud density resident in HBM
 Prints one JSON line.  `value` is Msamples/s of whole steps (build + render);
 tet-steps/s, render-only and build figures are reported beside it, with the
 render kernel's roofline fraction and the CPU oracle timed on a bounded
-sample of the same workload.
+sample of the same workload.  The radiance-cache leg ("nrc") trains the
+cache online on the same grid and compares, at equal RMSE against a
+1024-spp plain render, the time of truncated renders with the cache (plus
+one training frame each) with the plain renderer's.
 """
 from __future__ import annotations
 
@@ -23,6 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Msamples/s + tet-steps/s at 1024² 32spp; NRC vs plain speedup at equal RMSE"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_TET_STEP = 32  # algorithmic bytes per walk step (compact tet record)
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
+NRC_FLOP_PER_QUERY = 2 * (76 * 64 + 3 * 64 * 64 + 64 * 3)  # multiply-adds of the 76-64-64-64-64-3 network
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_cloud1024_traffic.txt")
 COPY_BYTES = 1 << 30  # plain device copy used to calibrate the traffic counters
 KERNEL_SOURCES = ["paper_2506_11510_amd/csrc/render.hip", "paper_2506_11510_amd/csrc/common.h"]
@@ -157,6 +162,76 @@ def cpu_baseline(sc, d, n_threads: int) -> dict:
             "tet_steps_per_s": st["tet_steps"] / t_render}
 
 
+def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
+    """Online-trained radiance cache vs the plain renderer at equal RMSE.
+
+    RMSE is measured against a 1024-spp plain render; that reference's own
+    noise (the plain 32-spp noise scaled by 32/1024) is subtracted from every
+    mean squared error.  The plain renderer's RMSE at any spp follows from
+    its 32-spp RMSE by 1/sqrt(spp) and its time by spp (no fixed cost, which
+    favours it).  A cache render's time includes one training frame."""
+    import numpy as np
+    cam, med, light = sc["camera"], sc["medium"], sc["light"]
+    ro = sc["render"]
+    ref, _ = tv.render(grid, cam, med, light, 1024, 7777, ro)
+    ref = ref.cpu().numpy().astype(np.float64)
+    a, sa = tv.render(grid, cam, med, light, 32, 1, ro)
+    a = a.cpu().numpy().astype(np.float64)
+    b, sb = tv.render(grid, cam, med, light, 32, 2, ro)
+    b = b.cpu().numpy().astype(np.float64)
+    var32 = float(((a - b) ** 2).mean()) / 2.0  # per-pixel variance of a 32-spp render
+    mse_ref = var32 * 32.0 / 1024.0
+
+    def rmse(img):
+        return float(np.sqrt(max(float(((img - ref) ** 2).mean()) - mse_ref, 0.0)))
+
+    rmse_plain32 = 0.5 * (rmse(a) + rmse(b))
+    ms_plain32 = 0.5 * (sa["ms"] + sb["ms"])
+    nrc = tv.Nrc(dict(lr=lr))
+    p0 = nrc.export()
+    untrained = None
+    losses, train_ms = [], []
+    for f in range(frames):
+        st = nrc.train_frame(grid, cam, med, light, 50000 + f, ro)
+        if f == 0:  # sigma_ref is set by the first frame; measure the untrained weights with it
+            p1 = nrc.export()
+            nrc.load(p0)
+            img, _ = tv.render(grid, cam, med, light, 32, 3, dict(ro, nrc=nrc))
+            untrained = rmse(img.cpu().numpy().astype(np.float64))
+            nrc.load(p1)
+        losses.append(st["loss"])
+        train_ms.append(st["ms"])
+    rows = []
+    for i, spp in enumerate([1, 2, 4, 8, 16, 32, 128]):
+        st_t = nrc.train_frame(grid, cam, med, light, 90000 + i, ro)
+        img, st = tv.render(grid, cam, med, light, spp, 4000 + i, dict(ro, nrc=nrc))
+        e = rmse(img.cpu().numpy().astype(np.float64))
+        t = st["ms"] + st_t["ms"]
+        plain_spp = 32.0 * (rmse_plain32 / e) ** 2 if e > 0 else float("inf")
+        plain_ms = ms_plain32 * plain_spp / 32.0
+        rows.append({"spp": spp, "rmse": round(e, 6), "ms_render": round(st["ms"], 3),
+                     "ms_train_frame": round(st_t["ms"], 3), "tet_steps": st["tet_steps"],
+                     "queries": st["cache_queries"], "query_ms": round(st["cache_ms"], 3),
+                     "plain_spp_equal_rmse": round(plain_spp, 2), "plain_ms_equal_rmse": round(plain_ms, 3),
+                     "speedup": round(plain_ms / t, 3)})
+    best = max(rows[:-1], key=lambda r: r["speedup"])
+    q = rows[5]
+    flops = q["queries"] * NRC_FLOP_PER_QUERY
+    achieved = flops / (q["query_ms"] / 1e3) / 1e12 if q["query_ms"] > 0 else 0.0
+    return {"speedup_equal_rmse": best["speedup"], "at_spp": best["spp"],
+            "plain": {"spp": 32, "rmse": round(rmse_plain32, 6), "ms": round(ms_plain32, 3),
+                      "tet_steps": sa["tet_steps"]},
+            "reference_spp": 1024, "truncate_bounce": nrc.info()["truncate_bounce"],
+            "train_frames": frames, "lr": lr, "train_frame_ms": round(float(np.mean(train_ms)), 3),
+            "loss_first_last": [round(float(np.mean(losses[:5])), 5), round(float(np.mean(losses[-5:])), 5)],
+            "rmse_untrained_32spp": round(untrained, 6), "bias_floor_rmse_128spp": rows[-1]["rmse"],
+            "rows": rows,
+            "query_roofline": {"bound": "mfma", "kernel": "k_nrc_query<1> + k_nrc_gather (32 spp frame)",
+                               "achieved": round(achieved, 3), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 5),
+                               "flop_per_query": NRC_FLOP_PER_QUERY}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +241,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--render-only", action="store_true", help="time only the render (grid built once)")
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a plain 1 GiB device copy")
+    ap.add_argument("--no-nrc", action="store_true", help="skip the radiance-cache leg")
+    ap.add_argument("--nrc-frames", type=int, default=100)
+    ap.add_argument("--nrc-lr", type=float, default=3e-3)
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="")
@@ -257,12 +335,16 @@ def main():
         "tet_steps_per_frame": int(mean_steps),
         "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated")},
         "image_mean": float(img.mean()),
-        "roofline": {"bound": "hbm", "kernel": "k_render<TetMedium32, 5>", "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_render<TetMedium32, 5, 0>", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP)},
         "cpu_baseline": None,
     }
+    if not args.no_nrc:
+        if grid is None:
+            grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+        res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr)
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -118,6 +118,7 @@ typedef struct {
   double ms;               /* device time of the whole render call */
   double trace_ms;         /* device time of the persistent tracing kernel(s) alone */
   double cache_ms;         /* device time of the radiance-cache queries (0 without a cache) */
+  int64_t cache_queries;   /* paths that stopped at the cache */
 } tet_render_stats;
 
 typedef struct {

@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   float3 o = make_float3(0, 0, 0), d = o, dsave = o, L = o, acc = o;
   float beta = 1.0f, t = 0.0f, tau = 0.0f, od = 0.0f;
   uint32_t cell = 0, cell_x = 0, bounce = 0, jf = 0, jn = 0, steps = 0;
-  uint32_t n_steps = 0, n_null = 0, n_real = 0, n_esc = 0, n_trunc = 0;
+  uint32_t n_steps = 0, n_null = 0, n_real = 0, n_esc = 0, n_trunc = 0, n_query = 0;
   int range = blockIdx.x & 7, tried = 0;  // wave-uniform work range state
   uint32_t bnext = 0, bend = 0;          // wave-uniform batch of work items
   const float3 sun = make_float3(A.sun[0], A.sun[1], A.sun[2]);
@@ -483,6 +483,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
         A.qrec[2 * (size_t)ent] = make_float4(x.x, x.y, x.z, med.sigma_at(cell));
         A.qrec[2 * (size_t)ent + 1] = make_float4(d.x, d.y, d.z, beta);
+        n_query++;
         mode = M_FINISH;
       }
       if (mode == M_COLLIDE) {  // real collision at t: start the light ray
@@ -720,9 +721,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     }
   }
   // ---- counters: wave reductions, one atomic per wave and counter
-  unsigned long long v[5] = {n_steps, n_null, n_real, n_esc, n_trunc};
+  unsigned long long v[6] = {n_steps, n_null, n_real, n_esc, n_trunc, n_query};
 #pragma unroll
-  for (int q = 0; q < 5; q++) {
+  for (int q = 0; q < 6; q++) {
     unsigned long long x = v[q];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -974,7 +975,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     rc = run_passes<VoxelMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   }
   if (rc) return rc;
-  unsigned long long hs[5] = {0, 0, 0, 0, 0};
+  unsigned long long hs[6] = {0, 0, 0, 0, 0, 0};
   TV_HIP(hipMemcpyAsync(hs, A.stats, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (!on_device) TV_HIP(hipMemcpyAsync(out_rgb, A.out, img_bytes, hipMemcpyDeviceToHost, st));
   TV_HIP(hipStreamSynchronize(st));
@@ -987,6 +988,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     stats->ms = ms;
     stats->trace_ms = ms_trace;
     stats->cache_ms = ms_cache;
+    stats->cache_queries = (int64_t)hs[5];
   }
   return TET_OK;
 }
