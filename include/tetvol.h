@@ -165,6 +165,33 @@ int tet_render(const tet_grid* grid, const tet_camera* camera, const tet_medium*
                int32_t spp, uint64_t seed, const tet_render_opts* opts /* NULL = defaults */, float* out_rgb,
                int32_t on_device, void* hip_stream, tet_render_stats* stats /* nullable */);
 
+/* Renders n scenes (each its own grid, camera, medium, light, spp and
+ * seed) with one persistent launch of the same path tracer: the scenes'
+ * samples are work items of one queue, so small images fill the GPU
+ * together instead of one after another.  out_rgb[i]: device pointer,
+ * width_i*height_i*3 FP32, as tet_render would write it.  Per-scene
+ * images equal tet_render's up to FP32 summation order.  opts (nullable):
+ * max_bounces, transmittance, max_steps_per_path, sample_offset,
+ * block_size, blocks_per_cu, record_layout and event_wait apply to all
+ * scenes; the radiance cache is not available in batches.  1 <= n <= 4096,
+ * fewer than 2^32 samples in all.  stats (nullable) receives the batch's
+ * totals. */
+int tet_render_batch(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,
+                     const tet_light* lights, const int32_t* spp, const uint64_t* seeds,
+                     const tet_render_opts* opts, float* const* out_rgb, void* hip_stream,
+                     tet_render_stats* stats);
+
+/* The same batch as a reusable frame: tet_batch_create fixes the scenes,
+ * allocates the scratch memory and captures the frame's kernels in a HIP
+ * graph; tet_batch_render replays it with new seeds (n values).  The grids
+ * and output buffers must outlive the handle. */
+typedef struct tet_batch tet_batch;
+int tet_batch_create(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,
+                     const tet_light* lights, const int32_t* spp, const tet_render_opts* opts,
+                     float* const* out_rgb, tet_batch** out);
+int tet_batch_render(tet_batch* batch, const uint64_t* seeds, void* hip_stream, tet_render_stats* stats);
+void tet_batch_free(tet_batch* batch);
+
 /* Point location (the grid-entry step of Algorithm 1): canonical index of
  * the tet containing each point (3 FP32 per point, inside [0,1]^3), or -1.
  * pts and out live on the same side (on_device). */

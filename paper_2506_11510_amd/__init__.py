@@ -142,6 +142,72 @@ def dda_render(density, n: int, density_scale: float, camera: dict, medium: dict
     return out, st.as_dict()
 
 
+class _SceneArrays:
+    """ctypes arrays describing a batch of scenes (kept alive with it)."""
+
+    def __init__(self, grids, cameras, media, lights, spp, outs):
+        import torch
+        n = len(grids)
+        assert n == len(cameras) == len(media) == len(lights) == len(spp)
+        self.n = n
+        self.grids = list(grids)
+        self.grid_ptrs = (ctypes.c_void_p * n)(*[g.handle for g in grids])
+        self.cams = (_abi.TetCamera * n)(*[_abi.make_camera(c) for c in cameras])
+        self.media = (_abi.TetMedium * n)(*[_abi.make_medium(m) for m in media])
+        self.lights = (_abi.TetLight * n)(*[_abi.make_light(l) for l in lights])
+        self.spp = (ctypes.c_int32 * n)(*[int(x) for x in spp])
+        if outs is None:
+            outs = [torch.empty((c["height"], c["width"], 3), dtype=torch.float32, device="cuda") for c in cameras]
+        for o, c in zip(outs, cameras):
+            assert o.is_cuda and o.is_contiguous() and o.numel() == c["width"] * c["height"] * 3
+        self.outs = list(outs)
+        self.out_ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+
+
+def render_batch(grids, cameras, media, lights, spp, seeds, render: dict | None = None, outs=None):
+    """Renders a batch of scenes with one persistent launch; returns (list
+    of (H, W, 3) CUDA tensors, batch stats)."""
+    a = _SceneArrays(grids, cameras, media, lights, spp, outs)
+    sd = (ctypes.c_uint64 * a.n)(*[int(x) for x in seeds])
+    st = _abi.TetRenderStats()
+    check(lib().tet_render_batch(a.n, a.grid_ptrs, a.cams, a.media, a.lights, a.spp, sd,
+                                 ctypes.byref(_abi.make_render_opts(render)), a.out_ptrs, _stream(),
+                                 ctypes.byref(st)), "tet_render_batch")
+    return a.outs, st.as_dict()
+
+
+class Batch:
+    """A batch of scenes captured once as a HIP graph frame; render(seeds)
+    replays it into the same output tensors."""
+
+    def __init__(self, grids, cameras, media, lights, spp, render: dict | None = None, outs=None):
+        self._a = _SceneArrays(grids, cameras, media, lights, spp, outs)
+        h = ctypes.c_void_p()
+        check(lib().tet_batch_create(self._a.n, self._a.grid_ptrs, self._a.cams, self._a.media, self._a.lights,
+                                     self._a.spp, ctypes.byref(_abi.make_render_opts(render)), self._a.out_ptrs,
+                                     ctypes.byref(h)), "tet_batch_create")
+        self._h = h
+
+    @property
+    def outs(self):
+        return self._a.outs
+
+    def render(self, seeds) -> dict:
+        sd = (ctypes.c_uint64 * self._a.n)(*[int(x) for x in seeds])
+        st = _abi.TetRenderStats()
+        check(lib().tet_batch_render(self._h, sd, _stream(), ctypes.byref(st)), "tet_batch_render")
+        return st.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            try:
+                lib().tet_batch_free(h)
+            except Exception:
+                pass
+
+
 N_PARAMS = 17603  # radiance-cache parameters (76 -> 64 x 4 -> 3, with biases)
 
 
@@ -265,4 +331,4 @@ def release_cache():
     lib().tet_release_cache()
 
 
-__all__ = ["Grid", "Nrc", "N_PARAMS", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]
+__all__ = ["Grid", "Nrc", "Batch", "render_batch", "N_PARAMS", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]

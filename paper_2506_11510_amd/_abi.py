@@ -112,6 +112,12 @@ SIGNATURES = {
                                   ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32, VP,
                                   ctypes.POINTER(TetRenderStats)]),
     "tet_grid_free": (None, [VP]),
+    "tet_render_batch": (ctypes.c_int, [ctypes.c_int32, VP, VP, VP, VP, VP, VP, ctypes.POINTER(TetRenderOpts), VP,
+                                        VP, ctypes.POINTER(TetRenderStats)]),
+    "tet_batch_create": (ctypes.c_int, [ctypes.c_int32, VP, VP, VP, VP, VP, ctypes.POINTER(TetRenderOpts), VP,
+                                        ctypes.POINTER(VP)]),
+    "tet_batch_render": (ctypes.c_int, [VP, VP, VP, ctypes.POINTER(TetRenderStats)]),
+    "tet_batch_free": (None, [VP]),
     "tet_nrc_opts_defaults": (None, [ctypes.POINTER(TetNrcOpts)]),
     "tet_nrc_create": (ctypes.c_int, [ctypes.POINTER(TetNrcOpts), ctypes.POINTER(VP)]),
     "tet_nrc_free": (None, [VP]),

@@ -19,6 +19,14 @@ int render_grid(const tet_grid*, const tet_camera*, const tet_medium*, const tet
 int render_voxels(const tet_density*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
                   const tet_render_opts*, float*, int32_t, hipStream_t, tet_render_stats*);
 int locate_points(const tet_grid*, const float*, int64_t, int64_t*, int32_t, hipStream_t);
+int render_batch(int32_t, const tet_grid* const*, const tet_camera*, const tet_medium*, const tet_light*,
+                 const int32_t*, const uint64_t*, const tet_render_opts*, float* const*, hipStream_t,
+                 tet_render_stats*);
+int batch_create(int32_t, const tet_grid* const*, const tet_camera*, const tet_medium*, const tet_light*,
+                 const int32_t*, const tet_render_opts*, float* const*, void**);
+int batch_render(void*, const uint64_t*, hipStream_t, tet_render_stats*);
+void batch_free(void*);
+int batch_device(const void*);
 
 static thread_local std::string g_err;
 
@@ -301,6 +309,31 @@ void tet_release_cache(void) {
     it = g_free.erase(it);
   }
   (void)hipSetDevice(cur);
+}
+
+int tet_render_batch(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,
+                     const tet_light* lights, const int32_t* spp, const uint64_t* seeds,
+                     const tet_render_opts* opts, float* const* out_rgb, void* hip_stream,
+                     tet_render_stats* stats) {
+  TV_GUARD(render_batch(n, grids, cameras, media, lights, spp, seeds, opts, out_rgb, (hipStream_t)hip_stream, stats));
+}
+
+int tet_batch_create(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,
+                     const tet_light* lights, const int32_t* spp, const tet_render_opts* opts,
+                     float* const* out_rgb, tet_batch** out) {
+  TV_GUARD(batch_create(n, grids, cameras, media, lights, spp, opts, out_rgb, (void**)out));
+}
+
+int tet_batch_render(tet_batch* batch, const uint64_t* seeds, void* hip_stream, tet_render_stats* stats) {
+  TV_GUARD(batch_render(batch, seeds, (hipStream_t)hip_stream, stats));
+}
+
+void tet_batch_free(tet_batch* batch) {
+  if (!batch) return;
+  int cur = 0, dev = batch_device(batch);
+  bool sw = hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess;
+  batch_free(batch);
+  if (sw) (void)hipSetDevice(cur);
 }
 
 void tet_nrc_opts_defaults(tet_nrc_opts* o) {

@@ -38,6 +38,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "nrc.h"
 
@@ -52,6 +53,41 @@ struct alignas(16) RayEntry {
   float tau;
 };
 constexpr uint32_t kMiss = 0xFFFFFFFFu;
+
+// One scene of a batch (several grids rendered by one launch sequence).
+// Work items and entry records of all scenes are concatenated; a scene's
+// items start at a multiple of 64, so the 64-item batches waves take never
+// straddle two scenes.
+struct SceneDesc {
+  Frame fr;
+  float albedo, g;
+  float sun[3], E[3], env[3];
+  int32_t spp, tiles_x;
+  uint64_t seed;
+  uint32_t s0;       // first sample index
+  uint32_t items;    // slots x spp (the scene's work items, one sample each)
+  uint32_t item0;    // first work item (multiple of 64)
+  uint32_t pad0;
+  uint64_t entry0;   // first entry record
+  uint64_t pix0;     // first pixel in the concatenated images
+  const void* rec;   // traversal records (TetRec32 or TetRec)
+  const uint64_t* keys;
+  int64_t n;
+  int32_t dmax, pad1;
+  float* out;
+};
+
+// Largest k < n with key(k) <= v (key ascending, key(0) = 0).
+template <class F>
+__device__ inline int scene_search(int n, uint64_t v, F key) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (key(mid) <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 struct RenderArgs {
   Frame fr;
@@ -82,6 +118,10 @@ struct RenderArgs {
   float4* vrec;          // training-path vertex records
   float4* path_l;        // training-path radiance and vertex count
   const tet_nrc* nrc;    // host handle (the query pass), never read on the device
+  // batch of scenes
+  const SceneDesc* scenes;
+  int32_t nscenes;
+  uint64_t total_entries;
 };
 
 // Pixel of training path j: floor(w npix / 2^24), w = the upper 24 bits of
@@ -374,6 +414,81 @@ __device__ inline bool enter_cube(float3 o, float3 d, float3& p) {
 }
 
 // ---------------------------------------------------------------- kernels
+// Camera ray of sample s of pixel (px, py), its entry into the grid, the
+// entry tet and the first free-flight depth.
+template <class Med>
+__device__ inline RayEntry camera_entry(const Frame& fr, uint64_t seed, const Med& med, int32_t px, int32_t py,
+                                        uint32_t pix, uint32_t s) {
+  uint2 u = uniform01x2(seed, pix, s, 0, kStreamCamera, 0);
+  float u0 = u01(u.x), u1 = u01(u.y);
+  float sx = ((2.0f * (((float)px + u0) / (float)fr.w)) - 1.0f) * fr.tan_x;
+  float sy = (1.0f - 2.0f * (((float)py + u1) / (float)fr.h)) * fr.tan_y;
+  float3 o = make_float3(fr.pos[0], fr.pos[1], fr.pos[2]);
+  float3 d = normalize3(make_float3((fr.f[0] + sx * fr.r[0]) + sy * fr.u[0], (fr.f[1] + sx * fr.r[1]) + sy * fr.u[1],
+                                    (fr.f[2] + sx * fr.r[2]) + sy * fr.u[2]));
+  float3 p = o;
+  int64_t c = -1;
+  if (enter_cube(o, d, p)) c = med.locate(p);
+  RayEntry r;
+  r.px = p.x;
+  r.py = p.y;
+  r.pz = p.z;
+  r.cell = c < 0 ? kMiss : (uint32_t)c;
+  r.dx = d.x;
+  r.dy = d.y;
+  r.dz = d.z;
+  r.tau = c < 0 ? 0.0f : exp_tau(uniform01(seed, pix, s, 0, kStreamFlight, 0));
+  return r;
+}
+
+__device__ inline RayEntry miss_entry() {
+  RayEntry z;
+  memset(&z, 0, sizeof(z));
+  z.cell = kMiss;
+  return z;
+}
+
+// Entry records of every (pixel, sample) of a batch of scenes.
+template <class Med>
+__global__ __launch_bounds__(256) void k_raygen_batch(RenderArgs A, Med med, RayEntry* __restrict__ entries) {
+  uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= A.total_entries) return;
+  const int k = scene_search(A.nscenes, e, [&](int i) { return A.scenes[i].entry0; });
+  const SceneDesc& S = A.scenes[k];
+  uint64_t local = e - S.entry0;
+  uint32_t slot = (uint32_t)(local / (uint32_t)S.spp);
+  uint32_t s = S.s0 + (uint32_t)(local % (uint32_t)S.spp);
+  int32_t px, py;
+  if (!slot_pixel(slot, S.tiles_x, S.fr.w, S.fr.h, px, py)) {
+    entries[e] = miss_entry();
+    return;
+  }
+  Med m = med;
+  m.rec = (decltype(m.rec))S.rec;
+  m.keys = S.keys;
+  m.n = S.n;
+  m.dmax = S.dmax;
+  entries[e] = camera_entry(S.fr, S.seed, m, px, py, (uint32_t)(py * S.fr.w + px), s);
+}
+
+// Zeroes (zero != 0) or divides by spp every pixel of a batch's images.
+__global__ void k_batch_images(const SceneDesc* __restrict__ sc, int32_t n, uint64_t total_px, int zero) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total_px) return;
+  const int k = scene_search(n, i, [&](int j) { return sc[j].pix0; });
+  float* o = sc[k].out + 3 * (i - sc[k].pix0);
+  if (zero) {
+    o[0] = 0.0f;
+    o[1] = 0.0f;
+    o[2] = 0.0f;
+  } else {
+    float div = (float)sc[k].spp;
+    o[0] = o[0] / div;
+    o[1] = o[1] / div;
+    o[2] = o[2] / div;
+  }
+}
+
 template <class Med>
 __global__ __launch_bounds__(256) void k_raygen(RenderArgs A, Med med, RayEntry* __restrict__ entries) {
   uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -389,35 +504,12 @@ __global__ __launch_bounds__(256) void k_raygen(RenderArgs A, Med med, RayEntry*
     uint32_t slot = (uint32_t)(e / (uint32_t)A.pass_spp);
     s = (uint32_t)(A.pass_start + (int32_t)(e % (uint32_t)A.pass_spp));
     if (!slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
-      RayEntry z;
-      memset(&z, 0, sizeof(z));
-      z.cell = kMiss;
-      entries[e] = z;  // padding slot of an edge tile: never traced, never queried
+      entries[e] = miss_entry();  // padding slot of an edge tile: never traced, never queried
       return;
     }
     pix = (uint32_t)(py * A.fr.w + px);
   }
-  uint2 u = uniform01x2(A.seed, pix, s, 0, kStreamCamera, 0);
-  float u0 = u01(u.x), u1 = u01(u.y);
-  float sx = ((2.0f * (((float)px + u0) / (float)A.fr.w)) - 1.0f) * A.fr.tan_x;
-  float sy = (1.0f - 2.0f * (((float)py + u1) / (float)A.fr.h)) * A.fr.tan_y;
-  float3 o = make_float3(A.fr.pos[0], A.fr.pos[1], A.fr.pos[2]);
-  float3 d = normalize3(make_float3((A.fr.f[0] + sx * A.fr.r[0]) + sy * A.fr.u[0],
-                                    (A.fr.f[1] + sx * A.fr.r[1]) + sy * A.fr.u[1],
-                                    (A.fr.f[2] + sx * A.fr.r[2]) + sy * A.fr.u[2]));
-  float3 p = o;
-  int64_t c = -1;
-  if (enter_cube(o, d, p)) c = med.locate(p);
-  RayEntry r;
-  r.px = p.x;
-  r.py = p.y;
-  r.pz = p.z;
-  r.cell = c < 0 ? kMiss : (uint32_t)c;
-  r.dx = d.x;
-  r.dy = d.y;
-  r.dz = d.z;
-  r.tau = c < 0 ? 0.0f : exp_tau(uniform01(A.seed, pix, s, 0, kStreamFlight, 0));
-  entries[e] = r;
+  entries[e] = camera_entry(A.fr, A.seed, med, px, py, pix, s);
 }
 
 enum { M_TRACK = 0, M_SHADOW = 1, M_COLLIDE = 2, M_SCATTER = 3, M_ESCAPE = 4, M_FINISH = 5, M_FETCH = 6,
@@ -454,7 +546,10 @@ __device__ inline void set_segment(float* tab, float3 o, float3 d, float oscale)
 // NRC: 0 plain estimator; 1 paths stop at real vertex A.truncate and leave
 // a query for the radiance cache in their entry record; 2 training paths
 // (A.train), whose first vertices and final radiance are recorded.
-template <class Med, int W, int NRC>
+// BATCH: the lanes' samples come from a batch of scenes (A.scenes); each
+// lane keeps its sample's scene index and that grid's record pointer, and
+// reads the scene's light, medium, seed and image from the table at events.
+template <class Med, int W, int NRC, bool BATCH = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_render(RenderArgs A, Med med) {
   __shared__ float s_tab[256 * kTabStride];
   float* tab = s_tab + threadIdx.x * kTabStride;
@@ -468,7 +563,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   uint32_t n_steps = 0, n_null = 0, n_real = 0, n_esc = 0, n_trunc = 0, n_query = 0;
   int range = blockIdx.x & 7, tried = 0;  // wave-uniform work range state
   uint32_t bnext = 0, bend = 0;          // wave-uniform batch of work items
-  const float3 sun = make_float3(A.sun[0], A.sun[1], A.sun[2]);
+  const float3 sun0 = make_float3(A.sun[0], A.sun[1], A.sun[2]);
+  uint32_t sc = 0, bsc = 0;  // lane's scene; wave-uniform scene of the current batch
+  Med lm = med;              // the lane's medium (its scene's records)
+#define TV_SC A.scenes[sc]
+#define TV_SEED (BATCH ? TV_SC.seed : A.seed)
+#define TV_ALBEDO (BATCH ? TV_SC.albedo : A.albedo)
+#define TV_G (BATCH ? TV_SC.g : A.g)
+#define TV_E(i) (BATCH ? TV_SC.E[i] : A.E[i])
+#define TV_ENV(i) (BATCH ? TV_SC.env[i] : A.env[i])
+#define TV_OUT (BATCH ? TV_SC.out : A.out)
+#define TV_SUN (BATCH ? make_float3(TV_SC.sun[0], TV_SC.sun[1], TV_SC.sun[2]) : sun0)
 
   for (;;) {
     // ================= events: run when enough lanes wait for one, or when
@@ -481,7 +586,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         n_real++;
         bounce++;
         float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-        A.qrec[2 * (size_t)ent] = make_float4(x.x, x.y, x.z, med.sigma_at(cell));
+        A.qrec[2 * (size_t)ent] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
         A.qrec[2 * (size_t)ent + 1] = make_float4(d.x, d.y, d.z, beta);
         n_query++;
         mode = M_FINISH;
@@ -492,47 +597,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         bounce++;
         if (NRC == 2 && (int32_t)bounce <= A.rec_vertices) {
           float4* q = A.vrec + ((size_t)ent * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
-          q[0] = make_float4(x.x, x.y, x.z, med.sigma_at(cell));
+          q[0] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
           q[1] = make_float4(d.x, d.y, d.z, beta);
           q[2] = make_float4(L.x, L.y, L.z, 0.0f);
         }
         jf = 0;
         jn = 0;
-        beta = beta * A.albedo;
+        beta = beta * TV_ALBEDO;
         dsave = d;
         o = x;
-        d = sun;
+        d = TV_SUN;
         t = 0.0f;
         cell_x = cell;
         od = A.transmittance == 0 ? 0.0f : 1.0f;
-        if (A.transmittance != 0) tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+        if (A.transmittance != 0) tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamLight, jn++));
         set_segment(tab, o, d, Med::kOriginScale);
         mode = M_SHADOW;
       }
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
         float Tr = A.transmittance == 0 ? exp_neg(od) : od;
-        float mu = (dsave.x * sun.x + dsave.y * sun.y) + dsave.z * sun.z;
-        float ph = hg_pdf(A.g, mu);
-        L.x = L.x + ((beta * ph) * A.E[0]) * Tr;
-        L.y = L.y + ((beta * ph) * A.E[1]) * Tr;
-        L.z = L.z + ((beta * ph) * A.E[2]) * Tr;
+        float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
+        float ph = hg_pdf(TV_G, mu);
+        L.x = L.x + ((beta * ph) * TV_E(0)) * Tr;
+        L.y = L.y + ((beta * ph) * TV_E(1)) * Tr;
+        L.z = L.z + ((beta * ph) * TV_E(2)) * Tr;
         if ((int32_t)bounce >= A.max_bounces) {
           mode = M_FINISH;
         } else {
-          uint2 v = uniform01x2(A.seed, pix, (uint32_t)s, bounce, kStreamPhase, 0);
-          d = hg_scatter(dsave, A.g, u01(v.x), u01(v.y));
+          uint2 v = uniform01x2(TV_SEED, pix, (uint32_t)s, bounce, kStreamPhase, 0);
+          d = hg_scatter(dsave, TV_G, u01(v.x), u01(v.y));
           t = 0.0f;
           cell = cell_x;
-          tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
+          tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
           set_segment(tab, o, d, Med::kOriginScale);
           mode = M_TRACK;
         }
       }
       if (mode == M_ESCAPE) {  // left the grid: the environment
         n_esc++;
-        L.x = L.x + beta * A.env[0];
-        L.y = L.y + beta * A.env[1];
-        L.z = L.z + beta * A.env[2];
+        L.x = L.x + beta * TV_ENV(0);
+        L.y = L.y + beta * TV_ENV(1);
+        L.z = L.z + beta * TV_ENV(2);
         mode = M_FINISH;
       }
       if (mode == M_FINISH) {  // sample done: accumulate; next sample or next item
@@ -549,7 +654,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         } else if (NRC == 2) {
           mode = M_FETCH;
         } else {
-          float* px = A.out + 3 * (size_t)pix;
+          float* px = TV_OUT + 3 * (size_t)pix;
           if (A.accumulate) {
             atomicAdd(px, acc.x);
             atomicAdd(px + 1, acc.y);
@@ -582,13 +687,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           } else {
             bnext = r0 + base;
             bend = min(bnext + A.batch, rend);
+            if constexpr (BATCH) bsc = (uint32_t)scene_search(A.nscenes, bnext, [&](int i) { return A.scenes[i].item0; });
           }
         }
         if (bnext < bend) {
           uint32_t item = bnext + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
           if (need && item < bend) {
-            if (NRC == 2) {
-              pix = train_pixel(A.seed, item, A.npix);
+            if constexpr (BATCH) {
+              const SceneDesc& S = A.scenes[bsc];
+              uint32_t local = item - S.item0;
+              int32_t px, py;
+              if (local < S.items &&
+                  slot_pixel(local / (uint32_t)S.spp, S.tiles_x, S.fr.w, S.fr.h, px, py)) {
+                pix = (uint32_t)(py * S.fr.w + px);
+                s = (int32_t)(S.s0 + local % (uint32_t)S.spp);
+                s_end = s + 1;
+                ent = (uint32_t)(S.entry0 + local);
+                sc = bsc;
+                lm.rec = (decltype(lm.rec))S.rec;
+                acc = make_float3(0, 0, 0);
+                mode = M_START;
+              } else {
+                mode = M_FETCH;  // padding item or slot: take another
+              }
+            } else if (NRC == 2) {
+              pix = train_pixel(TV_SEED, item, A.npix);
               s = (int32_t)item;
               s_end = s + 1;
               ent = item;
@@ -622,7 +745,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         uint32_t c = __float_as_uint(a.w);
         steps = 0;
         if (c == kMiss) {
-          L = make_float3(A.env[0], A.env[1], A.env[2]);
+          L = make_float3(TV_ENV(0), TV_ENV(1), TV_ENV(2));
           bounce = 0;
           mode = M_FINISH;
         } else {
@@ -648,7 +771,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         n_trunc++;
         mode = M_FINISH;  // truncated path keeps what it has gathered
       } else {
-        Step st = med.step(cell, o, d, tab, t);
+        Step st = lm.step(cell, o, d, tab, t);
         steps++;
         float sg = st.sigma, sb = st.majorant;
         if (mode == M_TRACK) {
@@ -662,14 +785,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
               while (tau < dtau) {
                 tc = t + tau / sb;
                 bool real = true;
-                if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
+                if (sg < sb) real = uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
                 if (real) {
                   collided = true;
                   break;
                 }
                 n_null++;
                 t = tc;
-                tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
+                tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
                 dtau = sb * (st.te - t);
               }
               if (!collided) tau = tau - dtau;
@@ -696,14 +819,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                   od = od * (1.0f - sg / sb);
                 } else {
                   bool real = true;
-                  if (sg < sb) real = uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++) < sg / sb;
+                  if (sg < sb) real = uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamLight, jn++) < sg / sb;
                   if (real) {
                     od = 0.0f;
                     done = true;
                     break;
                   }
                 }
-                tau = exp_tau(uniform01(A.seed, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+                tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamLight, jn++));
                 dtau = sb * (st.te - t);
               }
               if (!done) tau = tau - dtau;
@@ -720,6 +843,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       }
     }
   }
+#undef TV_SUN
+#undef TV_OUT
+#undef TV_ENV
+#undef TV_E
+#undef TV_G
+#undef TV_ALBEDO
+#undef TV_SEED
+#undef TV_SC
   // ---- counters: wave reductions, one atomic per wave and counter
   unsigned long long v[6] = {n_steps, n_null, n_real, n_esc, n_trunc, n_query};
 #pragma unroll
@@ -1077,6 +1208,238 @@ int render_voxels(const tet_density* dens, const tet_camera* cam, const tet_medi
   dv.on_device = 1;
   return render_common(1, nullptr, &dv, cam, m, l, spp, seed, o, out, on_device, st, stats);
 }
+
+// ---------------------------------------------------------------- batches of scenes
+struct BatchState {
+  int device = 0;
+  int n = 0;
+  bool use32 = true;
+  tet_render_opts o;
+  SceneDesc* pinned = nullptr;  // host staging of the scene table (page-locked)
+  SceneDesc* table = nullptr;   // device scene table
+  char* scratch = nullptr;      // counters and statistics, then the entry records
+  RenderArgs A;
+  uint64_t total_px = 0;
+  int grid = 1, bs = 256;
+  hipStream_t cap = nullptr;    // capture stream of the frame graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~BatchState() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    dev_free(table);
+    dev_free(scratch);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, const tet_camera* cams,
+                       const tet_medium* media, const tet_light* lights, const int32_t* spp,
+                       const tet_render_opts* opts_in, float* const* outs) {
+  if (n < 1 || n > 4096 || !grids || !cams || !media || !lights || !spp || !outs)
+    return fail(TET_ERR_INVALID_ARG, "render batch: bad arguments (1 <= n <= 4096, no NULL arrays)");
+  tet_render_opts o;
+  if (opts_in) o = *opts_in;
+  else tet_render_opts_defaults(&o);
+  if (int rc = check_render_opts(o)) return rc;
+  if (o.nrc) return fail(TET_ERR_UNSUPPORTED, "render batch: no radiance cache in batches");
+  bool use32 = o.record_layout != 48;
+  for (int i = 0; i < n; i++) {
+    if (!grids[i] || !outs[i]) return fail(TET_ERR_INVALID_ARG, "render batch: NULL grid or output");
+    if (int rc = check_camera(&cams[i])) return rc;
+    if (!(media[i].g > -1.0f && media[i].g < 1.0f) || !(media[i].albedo >= 0.0f))
+      return fail(TET_ERR_INVALID_ARG, "render batch: medium needs albedo >= 0 and -1 < g < 1");
+    if (spp[i] < 1 || (int64_t)o.sample_offset + spp[i] > (1ll << 31))
+      return fail(TET_ERR_INVALID_ARG, "render batch: bad spp");
+    if (!grids[i]->rec32) use32 = false;
+  }
+  if (!use32 && o.record_layout == 32)
+    return fail(TET_ERR_UNSUPPORTED, "render batch: a grid has no compact records");
+  B->n = n;
+  B->o = o;
+  B->use32 = use32;
+  if (hipGetDevice(&B->device) != hipSuccess) return fail(TET_ERR_DEVICE, "render batch: no device");
+  std::vector<SceneDesc> host((size_t)n);
+  uint64_t item = 0, entry = 0, px = 0;
+  for (int i = 0; i < n; i++) {
+    SceneDesc& S = host[i];
+    memset(&S, 0, sizeof(S));
+    make_frame(cams[i], &S.fr);
+    S.albedo = media[i].albedo;
+    S.g = media[i].g;
+    for (int c = 0; c < 3; c++) {
+      S.sun[c] = lights[i].sun_dir[c];
+      S.E[c] = lights[i].sun_irradiance[c];
+      S.env[c] = lights[i].env_radiance[c];
+    }
+    S.spp = spp[i];
+    S.tiles_x = (cams[i].width + 7) / 8;
+    int64_t tiles_y = (cams[i].height + 7) / 8;
+    uint64_t items = (uint64_t)S.tiles_x * (uint64_t)tiles_y * 64ull * (uint64_t)spp[i];
+    S.s0 = (uint32_t)o.sample_offset;
+    S.items = (uint32_t)std::min<uint64_t>(items, 0xFFFFFFFFull);
+    S.item0 = (uint32_t)std::min<uint64_t>(item, 0xFFFFFFFFull);
+    S.entry0 = entry;
+    S.pix0 = px;
+    const tet_grid* g = grids[i];
+    S.rec = use32 ? (const void*)g->rec32 : (const void*)g->rec;
+    S.keys = g->keys;
+    S.n = g->n;
+    S.dmax = g->max_depth;
+    S.out = outs[i];
+    item += (items + 63) / 64 * 64;
+    entry += items;
+    px += (uint64_t)cams[i].width * (uint64_t)cams[i].height;
+    if (items >= (1ull << 32) || item >= (1ull << 32) || entry >= (1ull << 32))
+      return fail(TET_ERR_INVALID_ARG, "render batch: more than 2^32 samples in one batch");
+  }
+  B->total_px = px;
+  B->table = (SceneDesc*)dev_alloc(sizeof(SceneDesc) * (size_t)n);
+  B->scratch = (char*)dev_alloc(256 + (size_t)entry * sizeof(RayEntry));
+  if (hipHostMalloc((void**)&B->pinned, sizeof(SceneDesc) * (size_t)n, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    B->pinned = nullptr;
+  }
+  if (!B->table || !B->scratch || !B->pinned) return fail(TET_ERR_OUT_OF_MEMORY, "render batch: device memory");
+  memcpy(B->pinned, host.data(), sizeof(SceneDesc) * (size_t)n);
+  RenderArgs& A = B->A;
+  memset(&A, 0, sizeof(A));
+  A.max_bounces = o.max_bounces;
+  A.transmittance = o.transmittance;
+  A.max_steps = (uint32_t)std::min<int64_t>(o.max_steps_per_path, 0x7FFFFFFF);
+  A.per_item = 1;
+  A.items = (uint32_t)item;
+  A.range_size = (uint32_t)(((item + 7) / 8 + 63) / 64 * 64);
+  A.batch = 64;
+  A.event_wait = o.event_wait ? o.event_wait : 48;
+  A.accumulate = 1;
+  A.counter = (uint32_t*)B->scratch;
+  A.stats = (unsigned long long*)(B->scratch + 64);
+  A.entries = (const RayEntry*)(B->scratch + 256);
+  A.scenes = B->table;
+  A.nscenes = n;
+  A.total_entries = entry;
+  B->bs = o.block_size ? o.block_size : 256;
+  int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
+  B->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cu_count() * bpc, ((int64_t)item + B->bs - 1) / B->bs));
+  return TET_OK;
+}
+
+// The frame's kernels (no host synchronisation, no memset: capturable).
+static int batch_enqueue(const BatchState* B, hipStream_t st) {
+  const RenderArgs& A = B->A;
+  RayEntry* entries = (RayEntry*)(B->scratch + 256);
+  unsigned pblocks = (unsigned)((B->total_px + 255) / 256);
+  unsigned eblocks = (unsigned)((A.total_entries + 255) / 256);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)B->scratch, 64);
+  hipLaunchKernelGGL(k_batch_images, dim3(pblocks), dim3(256), 0, st, (const SceneDesc*)B->table, B->n, B->total_px, 1);
+  if (B->use32) {
+    TetMedium32 m{nullptr, nullptr, 0, 0};
+    hipLaunchKernelGGL(k_raygen_batch<TetMedium32>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
+    hipLaunchKernelGGL((k_render<TetMedium32, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
+  } else {
+    TetMedium m{nullptr, nullptr, 0, 0};
+    hipLaunchKernelGGL(k_raygen_batch<TetMedium>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
+    hipLaunchKernelGGL((k_render<TetMedium, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
+  }
+  hipLaunchKernelGGL(k_batch_images, dim3(pblocks), dim3(256), 0, st, (const SceneDesc*)B->table, B->n, B->total_px, 0);
+  TV_HIP(hipGetLastError());
+  return TET_OK;
+}
+
+// One frame: new seeds into the table, then the kernels (eagerly, or the
+// captured graph), then the counters.
+static int batch_run(BatchState* B, const uint64_t* seeds, hipStream_t st, tet_render_stats* stats) {
+  if (!seeds) return fail(TET_ERR_INVALID_ARG, "render batch: seeds is NULL");
+  for (int i = 0; i < B->n; i++) B->pinned[i].seed = seeds[i];
+  hipEvent_t e0, e1;
+  TV_HIP(hipEventCreate(&e0));
+  TV_HIP(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } ev{e0, e1};
+  TV_HIP(hipMemcpyAsync(B->table, B->pinned, sizeof(SceneDesc) * (size_t)B->n, hipMemcpyHostToDevice, st));
+  TV_HIP(hipEventRecord(e0, st));
+  if (B->exec) {
+    TV_HIP(hipGraphLaunch(B->exec, st));
+  } else if (int rc = batch_enqueue(B, st)) {
+    return rc;
+  }
+  TV_HIP(hipEventRecord(e1, st));
+  unsigned long long hs[6] = {0, 0, 0, 0, 0, 0};
+  TV_HIP(hipMemcpyAsync(hs, B->A.stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  TV_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->tet_steps = (int64_t)hs[0];
+    stats->null_collisions = (int64_t)hs[1];
+    stats->real_collisions = (int64_t)hs[2];
+    stats->escapes = (int64_t)hs[3];
+    stats->truncated = (int64_t)hs[4];
+    stats->ms = ms;
+    stats->trace_ms = ms;
+  }
+  return TET_OK;
+}
+
+int render_batch(int32_t n, const tet_grid* const* grids, const tet_camera* cams, const tet_medium* media,
+                 const tet_light* lights, const int32_t* spp, const uint64_t* seeds, const tet_render_opts* opts,
+                 float* const* outs, hipStream_t st, tet_render_stats* stats) {
+  BatchState B;
+  if (int rc = batch_setup(&B, n, grids, cams, media, lights, spp, opts, outs)) return rc;
+  return batch_run(&B, seeds, st, stats);
+}
+
+int batch_create(int32_t n, const tet_grid* const* grids, const tet_camera* cams, const tet_medium* media,
+                 const tet_light* lights, const int32_t* spp, const tet_render_opts* opts, float* const* outs,
+                 void** out) {
+  if (!out) return fail(TET_ERR_INVALID_ARG, "tet_batch_create: out is NULL");
+  *out = nullptr;
+  BatchState* B = new BatchState();
+  if (int rc = batch_setup(B, n, grids, cams, media, lights, spp, opts, outs)) {
+    delete B;
+    return rc;
+  }
+  // capture the frame's kernels once; frames replay the graph
+  hipError_t e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete B;
+    return fail(TET_ERR_DEVICE, std::string("tet_batch_create: capture: ") + hipGetErrorString(e));
+  }
+  int rc = batch_enqueue(B, B->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(B->cap, &g);
+  B->graph = g;
+  if (rc || e != hipSuccess) {
+    delete B;
+    return rc ? rc : fail(TET_ERR_DEVICE, std::string("tet_batch_create: capture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    B->exec = nullptr;
+    delete B;
+    return fail(TET_ERR_DEVICE, std::string("tet_batch_create: instantiate: ") + hipGetErrorString(e));
+  }
+  *out = B;
+  return TET_OK;
+}
+
+int batch_render(void* b, const uint64_t* seeds, hipStream_t st, tet_render_stats* stats) {
+  if (!b) return fail(TET_ERR_INVALID_ARG, "tet_batch_render: batch is NULL");
+  return batch_run((BatchState*)b, seeds, st, stats);
+}
+
+void batch_free(void* b) { delete (BatchState*)b; }
+
+int batch_device(const void* b) { return b ? ((const BatchState*)b)->device : 0; }
 
 int locate_points(const tet_grid* g, const float* pts, int64_t count, int64_t* out, int32_t on_device,
                   hipStream_t st) {

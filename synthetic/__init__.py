@@ -134,3 +134,33 @@ def scene(name: str, **over) -> dict:
         else:
             s[k] = v
     return s
+
+
+def scene_batch(count: int = 64, first_seed: int = 100) -> list:
+    """A batch of small scenes for batched rendering: scene i has seed
+    first_seed + i; even i are Gaussian blobs at 64^3 on a uniform depth-9
+    grid (3,072 tets), odd i fBm clouds at 64^3, 128^3 or 256^3 on adaptive
+    grids; the camera orbits the cube (angle 2 pi i / count); images of 64,
+    128, 256 or 512 pixels square and 4, 8, 16, 32 or 64 spp, cycling."""
+    out = []
+    for i in range(count):
+        seed = first_seed + i
+        ang = 2.0 * math.pi * i / count
+        size = [64, 128, 256, 512][i % 4]
+        spp = [4, 8, 16, 32, 64][i % 5]
+        cam = dict(pos=[0.5 + 1.4 * math.sin(ang), 0.45 + 0.1 * math.cos(3 * ang), 0.5 - 1.4 * math.cos(ang)],
+                   look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=42.0, width=size, height=size)
+        if i % 2 == 0:
+            n = 64
+            fn = (lambda sd: (lambda: blobs(sd, 64)))(seed)
+            build = dict(want_mode=1, uniform_depth=9, max_depth=9, majorant_mode=0, variation_tau=0.0,
+                         target_px=1.0, density_scale=1.0, max_tets=1 << 20)
+        else:
+            n = [64, 128, 256][(i // 2) % 3]
+            fn = (lambda sd, nn: (lambda: cloud(sd, nn)))(seed, n)
+            build = dict(want_mode=0, uniform_depth=0, max_depth=24, majorant_mode=0, variation_tau=0.2,
+                         target_px=1.0, density_scale=1.0, max_tets=1 << 24)
+        out.append(dict(density_fn=fn, n=n, camera=cam, medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
+                        build=build, render=dict(spp=spp, max_bounces=16, transmittance=0,
+                                                 max_steps_per_path=1 << 20), seed=seed))
+    return out

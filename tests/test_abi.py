@@ -61,6 +61,26 @@ def test_defaults_and_argument_errors_without_gpu():
     L.tet_grid_free(None)
 
 
+def test_batch_and_cache_argument_errors_without_gpu():
+    from paper_2506_11510_amd import _abi
+    L = _abi.lib()
+    h = ctypes.c_void_p()
+    assert L.tet_render_batch(0, None, None, None, None, None, None, None, None, None, None) == _abi.TET_ERR_INVALID_ARG
+    assert L.tet_batch_create(0, None, None, None, None, None, None, None, ctypes.byref(h)) == _abi.TET_ERR_INVALID_ARG
+    assert h.value is None
+    assert L.tet_batch_render(None, None, None, None) == _abi.TET_ERR_INVALID_ARG
+    L.tet_batch_free(None)
+    o = _abi.TetNrcOpts()
+    L.tet_nrc_opts_defaults(ctypes.byref(o))
+    assert (o.truncate_bounce, o.train_paths, o.train_vertices, o.train_steps) == (2, 16384, 4, 4)
+    assert o.lr == pytest.approx(1e-3) and o.beta2 == pytest.approx(0.99)
+    o.train_vertices = 17
+    assert L.tet_nrc_create(ctypes.byref(o), ctypes.byref(h)) == _abi.TET_ERR_INVALID_ARG and h.value is None
+    assert L.tet_nrc_info(None, None, None) == _abi.TET_ERR_INVALID_ARG
+    assert L.tet_nrc_export(None, None, 0, None) == _abi.TET_ERR_INVALID_ARG
+    L.tet_nrc_free(None)
+
+
 def test_product_never_imports_the_oracle():
     """The product package must not reach the oracle in any way."""
     pkg = os.path.join(ROOT, "paper_2506_11510_amd")
