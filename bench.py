@@ -8,7 +8,9 @@ render kernel's roofline fraction and the CPU oracle timed on a bounded
 sample of the same workload.  The radiance-cache leg ("nrc") trains the
 cache online on the same grid and compares, at equal RMSE against a
 1024-spp plain render, the time of truncated renders with the cache (plus
-one training frame each) with the plain renderer's.
+one training frame each) with the plain renderer's.  The batch leg
+("batch") renders 64 small scenes (64^2..512^2, 4..64 spp, 3k..5M tets) as
+one captured HIP-graph frame and as 64 tet_render calls one after another.
 """
 from __future__ import annotations
 
@@ -169,7 +171,8 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
     noise (the plain 32-spp noise scaled by 32/1024) is subtracted from every
     mean squared error.  The plain renderer's RMSE at any spp follows from
     its 32-spp RMSE by 1/sqrt(spp) and its time by spp (no fixed cost, which
-    favours it).  A cache render's time includes one training frame."""
+    favours it).  A cache render's time includes its frame's training: the
+    training paths ride the render launch, the Adam steps follow it."""
     import numpy as np
     cam, med, light = sc["camera"], sc["medium"], sc["light"]
     ro = sc["render"]
@@ -203,15 +206,16 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
         train_ms.append(st["ms"])
     rows = []
     for i, spp in enumerate([1, 2, 4, 8, 16, 32, 128]):
-        st_t = nrc.train_frame(grid, cam, med, light, 90000 + i, ro)
-        img, st = tv.render(grid, cam, med, light, spp, 4000 + i, dict(ro, nrc=nrc))
+        # one frame of online rendering: the truncated render also traces the
+        # frame's training paths in the same launch, then the cache trains
+        img, st = tv.render(grid, cam, med, light, spp, 4000 + i, dict(ro, nrc=nrc, nrc_train=1))
         e = rmse(img.cpu().numpy().astype(np.float64))
-        t = st["ms"] + st_t["ms"]
+        t = st["ms"]
         plain_spp = 32.0 * (rmse_plain32 / e) ** 2 if e > 0 else float("inf")
         plain_ms = ms_plain32 * plain_spp / 32.0
-        rows.append({"spp": spp, "rmse": round(e, 6), "ms_render": round(st["ms"], 3),
-                     "ms_train_frame": round(st_t["ms"], 3), "tet_steps": st["tet_steps"],
-                     "queries": st["cache_queries"], "query_ms": round(st["cache_ms"], 3),
+        rows.append({"spp": spp, "rmse": round(e, 6), "ms_frame": round(t, 3), "ms_trace": round(st["trace_ms"], 3),
+                     "tet_steps": st["tet_steps"], "queries": st["cache_queries"],
+                     "query_ms": round(st["cache_ms"], 3), "train_records": st["cache_records"],
                      "plain_spp_equal_rmse": round(plain_spp, 2), "plain_ms_equal_rmse": round(plain_ms, 3),
                      "speedup": round(plain_ms / t, 3)})
     best = max(rows[:-1], key=lambda r: r["speedup"])
@@ -232,6 +236,52 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
                                "flop_per_query": NRC_FLOP_PER_QUERY}}
 
 
+def batch_leg(tv, torch, count: int, frames: int = 3) -> dict:
+    """`count` scenes of the batch generator: one graph frame (all scenes'
+    samples in one persistent launch), the same batch eagerly, and one
+    tet_render call per scene in sequence; wall-clock per frame."""
+    import numpy as np
+    import synthetic
+    sb = synthetic.scene_batch(count)
+    grids, tets = [], 0
+    for s in sb:
+        g = tv.leb_build(torch.from_numpy(s["density_fn"]()).cuda(), s["n"], s["camera"], build=s["build"])
+        tets += g.num_tets
+        grids.append(g)
+    cams = [s["camera"] for s in sb]
+    media = [s["medium"] for s in sb]
+    lights = [s["light"] for s in sb]
+    spp = [s["render"]["spp"] for s in sb]
+    ro = dict(max_bounces=sb[0]["render"]["max_bounces"])
+    samples = sum(c["width"] * c["height"] * k for c, k in zip(cams, spp))
+    b = tv.Batch(grids, cams, media, lights, spp, ro)
+
+    def timed(fn):
+        fn(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = None
+        for f in range(frames):
+            out = fn(1 + f)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / frames, out
+
+    ms_graph, st = timed(lambda f: b.render([s["seed"] + 1000 * f for s in sb]))
+    ms_eager, _ = timed(lambda f: tv.render_batch(grids, cams, media, lights, spp,
+                                                  [s["seed"] + 1000 * f for s in sb], ro, outs=b.outs))
+
+    def sequential(f):
+        for i, s in enumerate(sb):
+            tv.render(grids[i], cams[i], media[i], lights[i], spp[i], s["seed"] + 1000 * f, ro, out=b.outs[i])
+    ms_seq, _ = timed(sequential)
+    return {"scenes": count, "samples_per_frame": int(samples), "tets_total": int(tets),
+            "ms_graph_frame": round(ms_graph, 3), "ms_eager_batch": round(ms_eager, 3),
+            "ms_sequential_calls": round(ms_seq, 3), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 3),
+            "msamples_per_s_graph": round(samples / (ms_graph / 1e3) / 1e6, 3),
+            "tet_steps_per_frame": int(st["tet_steps"]),
+            "tet_steps_per_s_graph": round(st["tet_steps"] / (ms_graph / 1e3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +292,7 @@ def main():
     ap.add_argument("--render-only", action="store_true", help="time only the render (grid built once)")
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a plain 1 GiB device copy")
     ap.add_argument("--no-nrc", action="store_true", help="skip the radiance-cache leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch leg")
     ap.add_argument("--nrc-frames", type=int, default=100)
     ap.add_argument("--nrc-lr", type=float, default=3e-3)
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
@@ -345,6 +396,8 @@ def main():
         if grid is None:
             grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
         res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr)
+    if not args.no_batch:
+        res["batch"] = batch_leg(tv, torch, 64)
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

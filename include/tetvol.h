@@ -107,6 +107,10 @@ typedef struct {
   int32_t event_wait;         /* lanes of a wave that wait for an event before events run (0 = default 48) */
   const tet_nrc* nrc;         /* radiance cache: NULL = plain estimator; else paths stop at the cache's
                                  truncate_bounce-th real vertex and add throughput x cache (tet grids only) */
+  int32_t nrc_train;          /* with a cache: the same launch also traces the cache's training paths of
+                                 this frame (frame seed = seed XOR 0x6A09E667F3BCC909), then the cache takes
+                                 its Adam steps; the image uses the weights from before the call.  The
+                                 cache is modified: no other call may use it meanwhile. */
 } tet_render_opts;
 
 typedef struct {
@@ -119,6 +123,8 @@ typedef struct {
   double trace_ms;         /* device time of the persistent tracing kernel(s) alone */
   double cache_ms;         /* device time of the radiance-cache queries (0 without a cache) */
   int64_t cache_queries;   /* paths that stopped at the cache */
+  int64_t cache_records;   /* training records of the frame (nrc_train) */
+  double cache_loss;       /* their mean batch loss before the Adam steps (nrc_train) */
 } tet_render_stats;
 
 typedef struct {

@@ -54,14 +54,14 @@ class TetRenderOpts(ctypes.Structure):
                 ("samples_per_item", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("record_layout", ctypes.c_int32), ("batch_items", ctypes.c_int32), ("event_wait", ctypes.c_int32),
-                ("nrc", ctypes.c_void_p)]
+                ("nrc", ctypes.c_void_p), ("nrc_train", ctypes.c_int32)]
 
 
 class TetRenderStats(ctypes.Structure):
     _fields_ = [("tet_steps", ctypes.c_int64), ("null_collisions", ctypes.c_int64),
                 ("real_collisions", ctypes.c_int64), ("escapes", ctypes.c_int64), ("truncated", ctypes.c_int64),
                 ("ms", ctypes.c_double), ("trace_ms", ctypes.c_double), ("cache_ms", ctypes.c_double),
-                ("cache_queries", ctypes.c_int64)]
+                ("cache_queries", ctypes.c_int64), ("cache_records", ctypes.c_int64), ("cache_loss", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -35,6 +35,13 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
                          uint64_t frame_seed, const tet_render_opts* opts, int32_t n_paths, int32_t kv, float4* vrec,
                          float4* path_l, hipStream_t st, float* ms);
 
+// Compaction of training paths a render traced and the cache's Adam steps
+// on their records (nrc.hip); *records, *loss (nullable) report them.
+int nrc_train_paths(tet_nrc* n, const float4* vrec, const float4* path_l, int32_t n_paths, int32_t kv, hipStream_t st,
+                    int64_t* records, double* loss);
+// sigma_ref from the grid's largest extinction when it is not set yet.
+int nrc_resolve_sigma_ref(tet_nrc* n, const tet_grid* g, hipStream_t st);
+
 // Host side of the C ABI (nrc.hip).
 int nrc_create(const tet_nrc_opts* opts, tet_nrc** out);
 void nrc_free(tet_nrc* n);

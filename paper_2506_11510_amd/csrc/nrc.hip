@@ -742,17 +742,30 @@ int launch_reduce(tet_nrc* nrc, int32_t count, const float* part, const float* l
   return TET_OK;
 }
 
-// One Adam step on device-resident records.
-int train_step(tet_nrc* nrc, int32_t count, const float* pos, const float* dir, const float* sigma,
-               const float* target, float* loss_dev, hipStream_t st) {
-  int nblk = (count + 63) / 64;
+// `steps` Adam steps over `count` device-resident records split in equal
+// consecutive batches; the batch losses (before each step) go to loss_dev
+// (device, `steps` floats); *used = the steps taken.
+int train_records(tet_nrc* nrc, int64_t count, const float* pos, const float* dir, const float* sigma,
+                  const float* target, int steps, float* loss_dev, int* used, hipStream_t st) {
+  *used = 0;
+  if (count <= 0) return TET_OK;
+  int64_t per = (count + steps - 1) / steps;
+  int nblk = (int)((per + 63) / 64);
   Scratch part((size_t)nblk * kNrcParams * 4 + (size_t)nblk * 4);
   if (!part.p) return fail(TET_ERR_OUT_OF_MEMORY, "radiance cache: gradient scratch");
   float* pp = (float*)part.c();
   float* lp = pp + (size_t)nblk * kNrcParams;
-  if (int rc = launch_train(nrc, count, pos, dir, sigma, target, nullptr, nullptr, nullptr, pp, lp, st)) return rc;
-  if (int rc = launch_reduce(nrc, count, pp, lp, nullptr, loss_dev, true, st)) return rc;
-  TV_HIP(hipStreamSynchronize(st));  // scratch is released on return
+  for (int k = 0; k < steps; k++) {
+    int64_t a = (int64_t)k * per, b = std::min<int64_t>(count, a + per);
+    if (b <= a) break;
+    int32_t c = (int32_t)(b - a);
+    if (int rc = launch_train(nrc, c, pos + 3 * a, dir + 3 * a, sigma + a, target + 3 * a, nullptr, nullptr, nullptr,
+                              pp, lp, st))
+      return rc;
+    if (int rc = launch_reduce(nrc, c, pp, lp, nullptr, loss_dev + k, true, st)) return rc;
+    (*used)++;
+  }
+  TV_HIP(hipStreamSynchronize(st));  // the gradient scratch is released on return
   return TET_OK;
 }
 
@@ -777,6 +790,8 @@ int resolve_sigma_ref(tet_nrc* nrc, const tet_grid* g, hipStream_t st) {
 }
 
 }  // namespace
+
+int nrc_resolve_sigma_ref(tet_nrc* n, const tet_grid* g, hipStream_t st) { return resolve_sigma_ref(n, g, st); }
 
 int nrc_create(const tet_nrc_opts* in, tet_nrc** out) {
   if (!out) return fail(TET_ERR_INVALID_ARG, "tet_nrc_create: out is NULL");
@@ -964,7 +979,8 @@ int nrc_train_batch(tet_nrc* n, int32_t count, const float* pos, const float* di
     TV_HIP(hipMemcpyAsync((void*)dt, target, b3, hipMemcpyHostToDevice, st));
     TV_HIP(hipMemcpyAsync((void*)ds, sigma, b1, hipMemcpyHostToDevice, st));
   }
-  if (int rc = train_step(n, count, dp, dd, ds, dt, dl, st)) return rc;
+  int used = 0;
+  if (int rc = train_records(n, count, dp, dd, ds, dt, 1, dl, &used, st)) return rc;
   if (loss) {
     TV_HIP(hipMemcpyAsync(loss, dl, 4, hipMemcpyDeviceToHost, st));
     TV_HIP(hipStreamSynchronize(st));
@@ -973,22 +989,16 @@ int nrc_train_batch(tet_nrc* n, int32_t count, const float* pos, const float* di
 }
 
 namespace {
-// Traces the frame's training paths and compacts their records into
-// device arrays (pos 3, dir 3, sigma 1, target 3 floats, tag) of capacity
-// `cap`; *count = the number of records.
-int collect_device(const tet_nrc* n, const tet_grid* g, const tet_camera* cam, const tet_medium* med,
-                   const tet_light* light, uint64_t frame_seed, const tet_render_opts* ro, float* pos, float* dir,
-                   float* sigma, float* target, int32_t* tag, int64_t cap, int64_t* count, hipStream_t st,
-                   float* trace_ms) {
-  const int32_t np = n->opts.train_paths, kv = n->opts.train_vertices;
-  size_t vb = (size_t)np * kv * 48, lb = (size_t)np * 16, cb = ((size_t)np + 1) * 4;
-  Scratch s(vb + lb + 2 * cb + 512);
-  if (!s.p) return fail(TET_ERR_OUT_OF_MEMORY, "radiance cache: training-path scratch");
-  float4* vrec = (float4*)s.c();
-  float4* pl = (float4*)(s.c() + vb);
-  uint32_t* cnt = (uint32_t*)(s.c() + vb + lb);
-  uint32_t* off = (uint32_t*)(s.c() + vb + lb + cb + 256);
-  if (int rc = trace_training_paths(g, cam, med, light, frame_seed, ro, np, kv, vrec, pl, st, trace_ms)) return rc;
+// Compacts traced training paths (up to kv vertex records each) into record
+// arrays (pos 3, dir 3, sigma 1, target 3 floats, tag) of capacity `cap`;
+// *count = the number of records.
+int compact_records(int32_t np, int32_t kv, const float4* vrec, const float4* pl, float* pos, float* dir,
+                    float* sigma, float* target, int32_t* tag, int64_t cap, int64_t* count, hipStream_t st) {
+  size_t cb = ((size_t)np + 1) * 4;
+  Scratch s(2 * cb + 256);
+  if (!s.p) return fail(TET_ERR_OUT_OF_MEMORY, "radiance cache: compaction scratch");
+  uint32_t* cnt = (uint32_t*)s.c();
+  uint32_t* off = (uint32_t*)(s.c() + cb + 128);
   hipLaunchKernelGGL(k_nrc_count, dim3((np + 255) / 256), dim3(256), 0, st, vrec, pl, np, kv, cnt);
   hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, cnt, np, off);
   NrcEmitArgs E{vrec, pl, off, np, kv, cap, pos, dir, sigma, target, tag};
@@ -1000,7 +1010,47 @@ int collect_device(const tet_nrc* n, const tet_grid* g, const tet_camera* cam, c
   *count = total;
   return TET_OK;
 }
+
+// Traces the frame's training paths and compacts their records.
+int collect_device(const tet_nrc* n, const tet_grid* g, const tet_camera* cam, const tet_medium* med,
+                   const tet_light* light, uint64_t frame_seed, const tet_render_opts* ro, float* pos, float* dir,
+                   float* sigma, float* target, int32_t* tag, int64_t cap, int64_t* count, hipStream_t st,
+                   float* trace_ms) {
+  const int32_t np = n->opts.train_paths, kv = n->opts.train_vertices;
+  size_t vb = (size_t)np * kv * 48, lb = (size_t)np * 16;
+  Scratch s(vb + lb + 256);
+  if (!s.p) return fail(TET_ERR_OUT_OF_MEMORY, "radiance cache: training-path scratch");
+  float4* vrec = (float4*)s.c();
+  float4* pl = (float4*)(s.c() + vb);
+  if (int rc = trace_training_paths(g, cam, med, light, frame_seed, ro, np, kv, vrec, pl, st, trace_ms)) return rc;
+  return compact_records(np, kv, vrec, pl, pos, dir, sigma, target, tag, cap, count, st);
+}
 }  // namespace
+
+// Compaction and train_steps Adam steps over training paths a render traced
+// (vertex records and path radiance on the device).
+int nrc_train_paths(tet_nrc* n, const float4* vrec, const float4* pl, int32_t np, int32_t kv, hipStream_t st,
+                    int64_t* records, double* loss) {
+  int64_t cap = (int64_t)np * kv;
+  int steps = n->opts.train_steps;
+  Scratch s(40 * (size_t)cap + (size_t)steps * 4 + 256);
+  if (!s.p) return fail(TET_ERR_OUT_OF_MEMORY, "radiance cache: record scratch");
+  float* h = (float*)s.c();
+  float *dp = h, *dd = h + 3 * cap, *dt = h + 6 * cap, *ds = h + 9 * cap, *dl = h + 10 * cap;
+  int64_t c = 0;
+  if (int rc = compact_records(np, kv, vrec, pl, dp, dd, ds, dt, nullptr, cap, &c, st)) return rc;
+  int used = 0;
+  if (int rc = train_records(n, c, dp, dd, ds, dt, steps, dl, &used, st)) return rc;
+  if (records) *records = c;
+  if (loss) {
+    std::vector<float> hl(std::max(used, 1), 0.0f);
+    if (used) TV_HIP(hipMemcpy(hl.data(), dl, (size_t)used * 4, hipMemcpyDeviceToHost));
+    double sum = 0.0;
+    for (int k = 0; k < used; k++) sum += hl[k];
+    *loss = used ? sum / used : 0.0;
+  }
+  return TET_OK;
+}
 
 int nrc_collect(const tet_nrc* n, const tet_grid* g, const tet_camera* cam, const tet_medium* med,
                 const tet_light* light, uint64_t frame_seed, const tet_render_opts* ro, float* pos, float* dir,
@@ -1051,38 +1101,24 @@ int nrc_train_frame(tet_nrc* n, const tet_grid* g, const tet_camera* cam, const 
   } ev{e0, e1};
   TV_HIP(hipEventRecord(e0, st));
   if (int rc = resolve_sigma_ref(n, g, st)) return rc;
-  int64_t cap = (int64_t)n->opts.train_paths * n->opts.train_vertices;
-  size_t b3 = (size_t)cap * 12, b1 = (size_t)cap * 4;
-  int steps = n->opts.train_steps;
-  Scratch s(3 * b3 + b1 + (size_t)steps * 4 + 256);
+  const int32_t np = n->opts.train_paths, kv = n->opts.train_vertices;
+  size_t vb = (size_t)np * kv * 48, lb = (size_t)np * 16;
+  Scratch s(vb + lb + 256);
   if (!s.p) return fail(TET_ERR_OUT_OF_MEMORY, "tet_nrc_train_frame: scratch");
-  float* h = (float*)s.c();
-  float *dp = h, *dd = h + 3 * cap, *dt = h + 6 * cap, *ds = h + 9 * cap, *dl = h + 10 * cap;
-  int64_t c = 0;
+  float4* vrec = (float4*)s.c();
+  float4* pl = (float4*)(s.c() + vb);
   float tms = 0.0f;
-  if (int rc = collect_device(n, g, cam, med, light, frame_seed, ro, dp, dd, ds, dt, nullptr, cap, &c, st, &tms))
-    return rc;
-  int used = 0;
-  if (c > 0) {
-    int64_t per = (c + steps - 1) / steps;
-    for (int k = 0; k < steps; k++) {
-      int64_t a = (int64_t)k * per, b = std::min<int64_t>(c, a + per);
-      if (b <= a) break;
-      if (int rc = train_step(n, (int32_t)(b - a), dp + 3 * a, dd + 3 * a, ds + a, dt + 3 * a, dl + k, st)) return rc;
-      used++;
-    }
-  }
+  if (int rc = trace_training_paths(g, cam, med, light, frame_seed, ro, np, kv, vrec, pl, st, &tms)) return rc;
+  int64_t c = 0;
+  double loss = 0.0;
+  if (int rc = nrc_train_paths(n, vrec, pl, np, kv, st, &c, &loss)) return rc;
   TV_HIP(hipEventRecord(e1, st));
   TV_HIP(hipEventSynchronize(e1));
   float ms = 0.0f;
   TV_HIP(hipEventElapsedTime(&ms, e0, e1));
   if (stats) {
-    std::vector<float> hl(std::max(used, 1), 0.0f);
-    if (used) TV_HIP(hipMemcpy(hl.data(), dl, (size_t)used * 4, hipMemcpyDeviceToHost));
-    double sum = 0.0;
-    for (int k = 0; k < used; k++) sum += hl[k];
     stats->records = c;
-    stats->loss = used ? sum / used : 0.0;
+    stats->loss = loss;
     stats->ms = ms;
     stats->trace_ms = tms;
   }

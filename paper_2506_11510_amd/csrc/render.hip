@@ -118,6 +118,9 @@ struct RenderArgs {
   float4* vrec;          // training-path vertex records
   float4* path_l;        // training-path radiance and vertex count
   const tet_nrc* nrc;    // host handle (the query pass), never read on the device
+  uint32_t train_items;  // cache mode 1: the first items are training paths (first pass only)
+  uint32_t train_ent0;   // their entry records follow the image's
+  uint64_t train_seed;   // their Philox key
   // batch of scenes
   const SceneDesc* scenes;
   int32_t nscenes;
@@ -565,9 +568,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   uint32_t bnext = 0, bend = 0;          // wave-uniform batch of work items
   const float3 sun0 = make_float3(A.sun[0], A.sun[1], A.sun[2]);
   uint32_t sc = 0, bsc = 0;  // lane's scene; wave-uniform scene of the current batch
+  bool trainp = false;       // cache mode 1: the lane's path is a training path
   Med lm = med;              // the lane's medium (its scene's records)
 #define TV_SC A.scenes[sc]
-#define TV_SEED (BATCH ? TV_SC.seed : A.seed)
+#define TV_SEED (BATCH ? TV_SC.seed : ((NRC == 1 && trainp) ? A.train_seed : A.seed))
 #define TV_ALBEDO (BATCH ? TV_SC.albedo : A.albedo)
 #define TV_G (BATCH ? TV_SC.g : A.g)
 #define TV_E(i) (BATCH ? TV_SC.E[i] : A.E[i])
@@ -581,7 +585,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     unsigned long long waiting = __ballot(mode > M_SHADOW);
     if (waiting && (__popcll(waiting) >= A.event_wait || __popcll(waiting) == 64 ||
                     __ballot(mode <= M_SHADOW) == 0)) {
-      if (NRC == 1 && mode == M_COLLIDE && (int32_t)bounce + 1 == A.truncate) {
+      if (NRC == 1 && mode == M_COLLIDE && !trainp && (int32_t)bounce + 1 == A.truncate) {
         // the cache stands for the rest of the path: leave a query
         n_real++;
         bounce++;
@@ -595,8 +599,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         n_real++;
         float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
         bounce++;
-        if (NRC == 2 && (int32_t)bounce <= A.rec_vertices) {
-          float4* q = A.vrec + ((size_t)ent * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
+        if ((NRC == 2 || (NRC == 1 && trainp)) && (int32_t)bounce <= A.rec_vertices) {
+          uint32_t j = NRC == 2 ? ent : ent - A.train_ent0;
+          float4* q = A.vrec + ((size_t)j * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
           q[0] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
           q[1] = make_float4(d.x, d.y, d.z, beta);
           q[2] = make_float4(L.x, L.y, L.z, 0.0f);
@@ -646,12 +651,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         acc.z = acc.z + L.z;
         n_steps += steps;
         steps = 0;
-        if (NRC == 2) A.path_l[ent] = make_float4(L.x, L.y, L.z, __uint_as_float(bounce));
+        if (NRC == 2 || (NRC == 1 && trainp))
+          A.path_l[NRC == 2 ? ent : ent - A.train_ent0] = make_float4(L.x, L.y, L.z, __uint_as_float(bounce));
         s++;
         if (s < s_end) {
           ent++;
           mode = M_START;
-        } else if (NRC == 2) {
+        } else if (NRC == 2 || (NRC == 1 && trainp)) {
           mode = M_FETCH;
         } else {
           float* px = TV_OUT + 3 * (size_t)pix;
@@ -717,9 +723,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
               ent = item;
               acc = make_float3(0, 0, 0);
               mode = M_START;
+            } else if (NRC == 1 && item < A.train_items) {
+              pix = train_pixel(A.train_seed, item, A.npix);
+              s = (int32_t)item;
+              s_end = s + 1;
+              ent = A.train_ent0 + item;
+              trainp = true;
+              acc = make_float3(0, 0, 0);
+              mode = M_START;
             } else {
-              uint32_t slot = item / (uint32_t)A.items_per_pixel;
-              uint32_t chunk = item % (uint32_t)A.items_per_pixel;
+              const uint32_t it = NRC == 1 ? item - A.train_items : item;
+              if (NRC == 1) trainp = false;
+              uint32_t slot = it / (uint32_t)A.items_per_pixel;
+              uint32_t chunk = it % (uint32_t)A.items_per_pixel;
               int32_t px, py;
               if (slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) {
                 pix = (uint32_t)(py * A.fr.w + px);
@@ -959,12 +975,22 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     RenderArgs P = A;
     P.per_item = per;
     P.items_per_pixel = ipp;
-    P.items = A.slots * (uint32_t)ipp;
+    P.train_items = (NRC == 1 && done == 0) ? A.train_items : 0u;  // training paths ride the first pass
+    P.items = A.slots * (uint32_t)ipp + P.train_items;
     P.entries = entries;
     P.range_size = (P.items + 7) / 8;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 8);
     uint64_t ne = (uint64_t)A.slots * (uint64_t)P.pass_spp;
     hipLaunchKernelGGL(k_raygen<Med>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, P, med, entries);
+    if (P.train_items) {  // entry records of the training paths, after the image's
+      RenderArgs T = P;
+      T.train = 1;
+      T.seed = A.train_seed;
+      T.slots = P.train_items;
+      T.pass_spp = 1;
+      hipLaunchKernelGGL(k_raygen<Med>, dim3((P.train_items + 255) / 256), dim3(256), 0, st, T, med,
+                         entries + A.train_ent0);
+    }
     int64_t grid = (int64_t)cu_count() * bpc;
     int64_t need = ((int64_t)P.items + bs - 1) / bs;
     grid = std::max<int64_t>(1, std::min(grid, need));
@@ -1041,6 +1067,10 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (int rc = check_render_opts(o)) return rc;
   const tet_nrc* nrc = o.nrc;
   if (nrc && kind != 0) return fail(TET_ERR_UNSUPPORTED, "render: the radiance cache needs a tet grid");
+  const bool train = nrc && o.nrc_train;
+  const int32_t n_train = train ? nrc->opts.train_paths : 0, kv = train ? nrc->opts.train_vertices : 0;
+  if (train)
+    if (int rc = nrc_resolve_sigma_ref(const_cast<tet_nrc*>(nrc), g, st)) return rc;
   if (nrc && !(nrc->opts.sigma_ref > 0.0f))
     return fail(TET_ERR_INVALID_ARG, "render: the radiance cache has no sigma_ref yet (train it or set one)");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
@@ -1072,11 +1102,20 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     A.nrc = nrc;
     A.truncate = nrc->opts.truncate_bounce;
   }
+  if (train) {
+    A.train_items = (uint32_t)n_train;
+    A.train_ent0 = (uint32_t)(slots * pass_cap);
+    A.train_seed = seed ^ 0x6A09E667F3BCC909ull;
+    A.npix = (uint32_t)npix;
+    A.rec_vertices = kv;
+  }
 
-  // scratch: counters, entry records of one pass, image when the output is on the host
+  // scratch: counters, entry records of one pass (then those of the training
+  // paths), image when the output is on the host, training-path records
   size_t img_bytes = (size_t)npix * 3 * sizeof(float);
-  size_t ent_bytes = (size_t)slots * (size_t)pass_cap * sizeof(RayEntry);
-  size_t scratch = 256 + ent_bytes + (on_device ? 0 : img_bytes);
+  size_t ent_bytes = ((size_t)slots * (size_t)pass_cap + (size_t)n_train) * sizeof(RayEntry);
+  size_t vrec_bytes = (size_t)n_train * (size_t)kv * 48, pl_bytes = (size_t)n_train * 16;
+  size_t scratch = 256 + ent_bytes + (on_device ? 0 : img_bytes) + vrec_bytes + pl_bytes;
   char* sc = (char*)dev_alloc(scratch);
   if (!sc) return fail(TET_ERR_OUT_OF_MEMORY, "render: scratch");
   struct Free {
@@ -1087,6 +1126,11 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.stats = (unsigned long long*)(sc + 64);  // counters: 8 work ranges in sc[0..32)
   RayEntry* entries = (RayEntry*)(sc + 256);
   A.out = on_device ? out_rgb : (float*)(sc + 256 + ent_bytes);
+  if (train) {
+    char* tr = sc + 256 + ent_bytes + (on_device ? 0 : img_bytes);
+    A.vrec = (float4*)tr;
+    A.path_l = (float4*)(tr + vrec_bytes);
+  }
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
 
   A.qrec = (float4*)entries;
@@ -1106,6 +1150,28 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     rc = run_passes<VoxelMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   }
   if (rc) return rc;
+  int64_t records = 0;
+  double loss = 0.0;
+  if (train) {  // the cache's Adam steps on the frame's training paths (timed into ms)
+    hipEvent_t t0, t1;
+    TV_HIP(hipEventCreate(&t0));
+    TV_HIP(hipEventCreate(&t1));
+    struct Ev {
+      hipEvent_t a, b;
+      ~Ev() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } ev{t0, t1};
+    TV_HIP(hipEventRecord(t0, st));
+    if (int trc = nrc_train_paths(const_cast<tet_nrc*>(nrc), A.vrec, A.path_l, n_train, kv, st, &records, &loss))
+      return trc;
+    TV_HIP(hipEventRecord(t1, st));
+    TV_HIP(hipEventSynchronize(t1));
+    float tms = 0.0f;
+    TV_HIP(hipEventElapsedTime(&tms, t0, t1));
+    ms += tms;
+  }
   unsigned long long hs[6] = {0, 0, 0, 0, 0, 0};
   TV_HIP(hipMemcpyAsync(hs, A.stats, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (!on_device) TV_HIP(hipMemcpyAsync(out_rgb, A.out, img_bytes, hipMemcpyDeviceToHost, st));
@@ -1120,6 +1186,8 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     stats->trace_ms = ms_trace;
     stats->cache_ms = ms_cache;
     stats->cache_queries = (int64_t)hs[5];
+    stats->cache_records = records;
+    stats->cache_loss = loss;
   }
   return TET_OK;
 }

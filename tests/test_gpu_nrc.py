@@ -316,3 +316,31 @@ def test_trained_cache_lowers_error(tv):
     assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])
     assert e_t < e_p and e_t < 0.5 * e_u
     assert st["tet_steps"] < sp["tet_steps"]
+
+
+def test_training_inside_the_render_launch(tv, tiny):
+    """nrc_train: the render also traces the frame's training paths (key =
+    seed XOR 0x6A09E667F3BCC909) and then trains.  The image is the one the
+    pre-call weights give, and the weights after it are those a separate
+    training frame with that key gives, bit for bit (same paths, same
+    records, same batches)."""
+    say("case nrc training inside the render launch")
+    g, _ = tiny
+    cam = dict(TINY["camera"], width=48, height=40)
+    ro = dict(TINY["render"], max_bounces=8)
+    P = rand_params(13, scale=0.5)
+    a = tv.Nrc(dict(sigma_ref=10.0, train_paths=4000))
+    b = tv.Nrc(dict(sigma_ref=10.0, train_paths=4000))
+    a.load(P)
+    b.load(P)
+    seed = 77
+    img_plain, _ = tv.render(g, cam, TINY["medium"], TINY["light"], 8, seed, dict(ro, nrc=a))
+    img, st = tv.render(g, cam, TINY["medium"], TINY["light"], 8, seed, dict(ro, nrc=a, nrc_train=1))
+    sf = b.train_frame(g, cam, TINY["medium"], TINY["light"], seed ^ 0x6A09E667F3BCC909, ro)
+    say(f"  records {st['cache_records']} vs {sf['records']}, loss {st['cache_loss']:.5g} vs {sf['loss']:.5g}")
+    assert st["cache_records"] == sf["records"] > 1000
+    assert st["cache_loss"] == sf["loss"]
+    assert np.array_equal(a.export(), b.export())
+    assert a.info()["adam_steps"] == b.info()["adam_steps"] == 4
+    x, y = img.cpu().numpy().astype(np.float64), img_plain.cpu().numpy().astype(np.float64)
+    assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30)
