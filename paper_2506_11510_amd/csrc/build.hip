@@ -376,7 +376,17 @@ __global__ void k_keys(int64_t n, const uint64_t* __restrict__ ids, uint64_t* __
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
-  if (__lane_id() == 0) atomicMax(maxd, d);
+  // block maximum, then one atomic per block, skipped when it cannot raise
+  // the running maximum (one address: contended atomics would serialise)
+  __shared__ int s_max[16];
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == 0) s_max[w] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = s_max[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) m = max(m, s_max[k]);
+    if (m > __hip_atomic_load(maxd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxd, m);
+  }
 }
 
 // Root Kuhn tets: vertex 1 = S e_p0, vertex 2 = S (e_p0 + e_p1), over the
@@ -839,7 +849,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   hipError_t he = hipMemcpyAsync(g->ids, A.ids.p, cur * 8, hipMemcpyDeviceToDevice, st);
   if (he == hipSuccess) he = hipMemcpyAsync(g->verts, A.verts.p, cur * 32, hipMemcpyDeviceToDevice, st);
   if (he == hipSuccess) {
-    hipLaunchKernelGGL(k_keys, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, g->ids, g->keys, d_flag + 1);
+    hipLaunchKernelGGL(k_keys, dim3(nblocks(cur, 1024)), dim3(1024), 0, st, cur, g->ids, g->keys, d_flag + 1);
     he = hipMemcpyAsync(&flag, d_flag + 1, 4, hipMemcpyDeviceToHost, st);
   }
   if (he == hipSuccess) he = hipStreamSynchronize(st);
