@@ -164,7 +164,68 @@ def cpu_baseline(sc, d, n_threads: int) -> dict:
             "tet_steps_per_s": st["tet_steps"] / t_render}
 
 
-def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
+def dda_leg(tv, dev, sc, steps: int = 3) -> dict:
+    """The regular-grid reference renderer (Amanatides-Woo over the same
+    voxels, same integrator) on the benchmark frame."""
+    cam, spp = sc["camera"], sc["render"]["spp"]
+    ro = dict(sc["render"], samples_per_item=1, batch_items=64, waves_per_simd=5, event_wait=48)
+    tv.dda_render(dev, sc["n"], 1.0, cam, sc["medium"], sc["light"], spp, 3, ro)
+    ms, st = [], None
+    for i in range(steps):
+        _, st = tv.dda_render(dev, sc["n"], 1.0, cam, sc["medium"], sc["light"], spp, 30 + i, ro)
+        ms.append(st["ms"])
+    m = sum(ms) / len(ms)
+    samples = cam["width"] * cam["height"] * spp
+    return {"ms": round(m, 3), "msamples_per_s": round(samples / (m / 1e3) / 1e6, 3),
+            "voxel_steps_per_frame": int(st["tet_steps"]),
+            "voxel_steps_per_s": round(st["tet_steps"] / (st["trace_ms"] / 1e3), 1)}
+
+
+def plume_leg(tv, torch) -> dict:
+    """The production-scale configuration: 1024^3 plume density resident in
+    HBM, adaptive LEB build (~86 M tets), 1024^2 renders at 32 and 1024 spp
+    with 64 bounces.  Returns the figures and (grid, scene, 1024-spp image)
+    for the radiance-cache leg."""
+    import numpy as np
+    import synthetic
+    sc = synthetic.scene("plume")
+    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
+                        event_wait=48)
+    t0 = time.perf_counter()
+    dev = torch.from_numpy(sc["density_fn"]()).cuda()
+    gen_s = time.perf_counter() - t0
+    builds = []
+    for _ in range(2):
+        g = tv.leb_build(dev, sc["n"], sc["camera"], build=sc["build"])
+        builds.append(g.info())
+    del dev
+    cam = sc["camera"]
+    tv.render(g, cam, sc["medium"], sc["light"], 32, 1, sc["render"])
+    r32 = []
+    for i in range(3):
+        _, st = tv.render(g, cam, sc["medium"], sc["light"], 32, 10 + i, sc["render"])
+        r32.append(st)
+    ref, st1024 = tv.render(g, cam, sc["medium"], sc["light"], 1024, 7777, sc["render"])
+    ms32 = float(np.mean([r["ms"] for r in r32]))
+    tr32 = float(np.mean([r["trace_ms"] for r in r32]))
+    steps32 = float(np.mean([r["tet_steps"] for r in r32]))
+    px = cam["width"] * cam["height"]
+    achieved = steps32 * BYTES_PER_TET_STEP / (tr32 / 1e3) / 1e9
+    out = {"workload": "1024^3 curl-advected fBm plume (seed 2, 5% occupancy, sigma_t max 50) -> adaptive LEB grid "
+                       "(1 px target, tau 0.2, depth <= 30) -> 1024x1024, 64 bounces, albedo 0.95, HG g 0.6",
+           "density_gen_s_host": round(gen_s, 2), "num_tets": builds[-1]["num_tets"],
+           "max_depth": builds[-1]["max_depth"], "build_rounds": builds[-1]["rounds"],
+           "build_ms": round(builds[-1]["ms"], 3),
+           "spp32": {"ms": round(ms32, 3), "trace_ms": round(tr32, 3),
+                     "msamples_per_s": round(px * 32 / (ms32 / 1e3) / 1e6, 3),
+                     "tet_steps_per_s": round(steps32 / (tr32 / 1e3), 1), "tet_steps": int(steps32),
+                     "roofline_frac_algorithmic": round(achieved / HBM_PEAK_GBS, 4)},
+           "spp1024": {"ms": round(st1024["ms"], 3), "msamples_per_s": round(px * 1024 / (st1024["ms"] / 1e3) / 1e6, 3),
+                       "tet_steps": int(st1024["tet_steps"])}}
+    return out, (g, sc, ref)
+
+
+def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int = 1024) -> dict:
     """Online-trained radiance cache vs the plain renderer at equal RMSE.
 
     RMSE is measured against a 1024-spp plain render; that reference's own
@@ -176,14 +237,15 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
     import numpy as np
     cam, med, light = sc["camera"], sc["medium"], sc["light"]
     ro = sc["render"]
-    ref, _ = tv.render(grid, cam, med, light, 1024, 7777, ro)
+    if ref is None:
+        ref, _ = tv.render(grid, cam, med, light, ref_spp, 7777, ro)
     ref = ref.cpu().numpy().astype(np.float64)
     a, sa = tv.render(grid, cam, med, light, 32, 1, ro)
     a = a.cpu().numpy().astype(np.float64)
     b, sb = tv.render(grid, cam, med, light, 32, 2, ro)
     b = b.cpu().numpy().astype(np.float64)
     var32 = float(((a - b) ** 2).mean()) / 2.0  # per-pixel variance of a 32-spp render
-    mse_ref = var32 * 32.0 / 1024.0
+    mse_ref = var32 * 32.0 / ref_spp
 
     def rmse(img):
         return float(np.sqrt(max(float(((img - ref) ** 2).mean()) - mse_ref, 0.0)))
@@ -225,7 +287,7 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float) -> dict:
     return {"speedup_equal_rmse": best["speedup"], "at_spp": best["spp"],
             "plain": {"spp": 32, "rmse": round(rmse_plain32, 6), "ms": round(ms_plain32, 3),
                       "tet_steps": sa["tet_steps"]},
-            "reference_spp": 1024, "truncate_bounce": nrc.info()["truncate_bounce"],
+            "reference_spp": ref_spp, "truncate_bounce": nrc.info()["truncate_bounce"],
             "train_frames": frames, "lr": lr, "train_frame_ms": round(float(np.mean(train_ms)), 3),
             "loss_first_last": [round(float(np.mean(losses[:5])), 5), round(float(np.mean(losses[-5:])), 5)],
             "rmse_untrained_32spp": round(untrained, 6), "bias_floor_rmse_128spp": rows[-1]["rmse"],
@@ -293,6 +355,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a plain 1 GiB device copy")
     ap.add_argument("--no-nrc", action="store_true", help="skip the radiance-cache leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch leg")
+    ap.add_argument("--no-dda", action="store_true", help="skip the regular-grid (DDA) leg")
+    ap.add_argument("--no-plume", action="store_true",
+                    help="skip the 1024^3 plume leg (the radiance-cache leg then runs on the cloud)")
     ap.add_argument("--nrc-frames", type=int, default=100)
     ap.add_argument("--nrc-lr", type=float, default=3e-3)
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
@@ -392,12 +457,26 @@ def main():
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP)},
         "cpu_baseline": None,
     }
-    if not args.no_nrc:
-        if grid is None:
-            grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
-        res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr)
+    if not args.no_dda:
+        res["dda"] = dda_leg(tv, dev, sc)
+        res["dda"]["tet_vs_dda_render_speedup"] = round(res["dda"]["ms"] / mean_render_ms, 3)
     if not args.no_batch:
         res["batch"] = batch_leg(tv, torch, 64)
+    if grid is None:
+        grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+    del dev
+    plume = None
+    if not args.no_plume:
+        res["plume"], plume = plume_leg(tv, torch)
+    if not args.no_nrc:
+        if plume is not None:  # the cache study runs on the production-scale scene
+            del grid
+            g, psc, ref = plume
+            res["nrc"] = nrc_leg(tv, torch, g, psc, args.nrc_frames, args.nrc_lr, ref=ref, ref_spp=1024)
+            res["nrc"]["scene"] = "plume 1024^3 (64 bounces)"
+        else:
+            res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr)
+            res["nrc"]["scene"] = "cloud 256^3 (32 bounces)"
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -129,6 +129,7 @@ def lib():
         L.oracle_nrc_encode.argtypes = [ctypes.c_int64, vp, vp, vp, ctypes.c_float, vp]
         L.oracle_mlp_forward.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_int32]
         L.oracle_mlp_backward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int32]
+        L.oracle_ema_step.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_double, ctypes.c_int64, vp]
         L.oracle_nrc_eval_point.argtypes = [vp, ctypes.c_int32, ctypes.c_float, vp, vp, ctypes.c_float, vp]
         L.oracle_nrc_eval_point.restype = None
         L.oracle_nrc_render.argtypes = [vp, ctypes.POINTER(OCam), ctypes.POINTER(OMedium), ctypes.POINTER(OLight),
@@ -457,6 +458,17 @@ def mlp_backward(params, x, dy, bf16: bool = False):
     _check(lib().oracle_mlp_backward(_vp(params), len(x), _vp(x), _vp(dy), _vp(y), _vp(g), int(bool(bf16))),
            "oracle_mlp_backward")
     return y, g
+
+
+def ema_step(ema, params, beta, step):
+    """One step of the weight average (in place on `ema`); returns the
+    bias-corrected weights."""
+    assert ema.dtype == np.float64 and ema.flags.c_contiguous
+    params = np.ascontiguousarray(params, np.float64)
+    out = np.empty_like(ema)
+    _check(lib().oracle_ema_step(len(ema), _vp(ema), _vp(params), float(beta), int(step), _vp(out)),
+           "oracle_ema_step")
+    return out
 
 
 def nrc_eval_point(params, p, d, sigma, sigma_ref, bf16: bool = True) -> np.ndarray:

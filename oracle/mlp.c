@@ -13,7 +13,10 @@
  * linear output.  Parameters: per layer W (row-major [out][in]) then b.
  * Loss: relative L2 (Mueller et al. 2021),
  *   loss = 1/(3B) sum (y - t)^2 / (stopgrad(y)^2 + 0.01).
- * Optimiser: Adam (Kingma & Ba 2015) with bias correction.
+ * Optimiser: Adam (Kingma & Ba 2015) with bias correction.  Inference may use
+ * an exponential moving average of the weights after each step, bias
+ * corrected like Adam's moments: ema_t = b ema_{t-1} + (1 - b) w_t, ema_0 = 0,
+ * weights = ema_t / (1 - b^t).
  *
  * BF16-operand mode (bf16 != 0) states the precision the GPU network runs
  * in: every operand of a matrix product is rounded to bfloat16 (round to
@@ -186,6 +189,16 @@ int oracle_adam_step(int64_t n, double* params, const double* grads, double* m, 
     v[i] = beta2 * v[i] + (1.0 - beta2) * grads[i] * grads[i];
     double mh = m[i] / c1, vh = v[i] / c2;
     params[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+  return 0;
+}
+
+int oracle_ema_step(int64_t n, double* ema, const double* params, double beta, int64_t step, double* out) {
+  if (n < 0 || step < 1 || !ema || !params || !out || !(beta >= 0.0 && beta < 1.0)) return -1;
+  double c = 1.0 - pow(beta, (double)step);
+  for (int64_t i = 0; i < n; i++) {
+    ema[i] = beta * ema[i] + (1.0 - beta) * params[i];
+    out[i] = ema[i] / c;
   }
   return 0;
 }

@@ -141,6 +141,7 @@ int  oracle_nrc_loss_grad(int64_t count, const double* y, const double* target, 
                           double* dy);
 int  oracle_adam_step(int64_t n, double* params, const double* grads, double* m, double* v,
                       int64_t step, double lr, double beta1, double beta2, double eps);
+int  oracle_ema_step(int64_t n, double* ema, const double* params, double beta, int64_t step, double* out);
 void oracle_nrc_eval_point(const double* params, int32_t bf16, float sigma_ref, const float p[3],
                            const float d[3], float sigma, float out[3]);
 /* Truncated render with the cache, training pixel choice and training

@@ -64,14 +64,24 @@ class Grid:
     def num_tets(self) -> int:
         return self.info()["num_tets"]
 
-    def export(self) -> dict:
-        """Host copies of ids, neighbour links, extinction, majorant, vertices."""
+    def export(self, device: bool = False, fields=("ids", "nbr", "sigma", "majorant", "verts")) -> dict:
+        """Copies of ids, neighbour links, extinction, majorant, vertices:
+        numpy arrays, or CUDA tensors with device=True (ids and links as
+        int64 / int32 bit patterns); only the listed fields."""
         n = self.num_tets
-        out = dict(ids=np.empty(n, np.uint64), nbr=np.empty((n, 4), np.uint32), sigma=np.empty(n, np.float32),
-                   majorant=np.empty(n, np.float32), verts=np.empty((n, 4, 3), np.int32))
-        check(lib().tet_grid_export(self._h, out["ids"].ctypes.data, out["nbr"].ctypes.data,
-                                    out["sigma"].ctypes.data, out["majorant"].ctypes.data,
-                                    out["verts"].ctypes.data, 0, _stream()), "tet_grid_export")
+        shapes = dict(ids=(n,), nbr=(n, 4), sigma=(n,), majorant=(n,), verts=(n, 4, 3))
+        if device:
+            import torch
+            dt = dict(ids=torch.int64, nbr=torch.int32, sigma=torch.float32, majorant=torch.float32,
+                      verts=torch.int32)
+            out = {k: torch.empty(shapes[k], dtype=dt[k], device="cuda") for k in fields}
+            ptr = {k: ctypes.c_void_p(v.data_ptr()) for k, v in out.items()}
+        else:
+            dt = dict(ids=np.uint64, nbr=np.uint32, sigma=np.float32, majorant=np.float32, verts=np.int32)
+            out = {k: np.empty(shapes[k], dt[k]) for k in fields}
+            ptr = {k: ctypes.c_void_p(v.ctypes.data) for k, v in out.items()}
+        check(lib().tet_grid_export(self._h, ptr.get("ids"), ptr.get("nbr"), ptr.get("sigma"), ptr.get("majorant"),
+                                    ptr.get("verts"), int(device), _stream()), "tet_grid_export")
         return out
 
     def locate(self, pts):

@@ -226,17 +226,6 @@ __device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_
   return lo - 1;
 }
 
-// Exact a b < c d for FP32 operands: each product as p + e with p = fl(a b)
-// and e = fma(a, b, -p) (exact unless |a b| < 2^-103, which these walks
-// never produce: the products are 0 or above 2^-60), compared
-// lexicographically -- rounding is monotone, so p < q implies a b < c d,
-// and for p == q the errors decide.
-__device__ inline bool prod_lt(float a, float b, float c, float d) {
-  float p = a * b, q = c * d;
-  float e = fmaf(a, b, -p), f = fmaf(c, d, -q);
-  return p < q || (p == q && e < f);
-}
-
 struct TetMedium {
   static constexpr float kOriginScale = 1.0f;
   const TetRec* __restrict__ rec;
@@ -248,7 +237,7 @@ struct TetMedium {
   // Exit of the tet along the segment whose direction-dot table is `tab`
   // (tab[N] = dir_N . d, tab[9 + N] = dir_N . o) from t: faces with
   // n.d > 0 are candidates; the exit face has the smallest exact quotient
-  // num / den (exact cross products, lowest face on ties); one FP32
+  // num / den (exact FP64 cross products, lowest face on ties); one FP32
   // division gives the exit distance.  Branchless, so the whole record is
   // loaded at once.
   __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
@@ -269,7 +258,7 @@ struct TetMedium {
       float dot = __uint_as_float(__float_as_uint(tab[9 + (c >> 1)]) ^ sg);
       float num = off[f] - dot;
       bool cand = den > 0.0f;
-      bool better = cand && (!any || prod_lt(num, bden, bnum, den));
+      bool better = cand && (!any || (double)num * (double)bden < (double)bnum * (double)den);
       bnum = better ? num : bnum;
       bden = better ? den : bden;
       blink = better ? link[f] : blink;
@@ -317,7 +306,7 @@ struct TetMedium32 {
       float den = __uint_as_float(__float_as_uint(e[0]) ^ sg);
       float dot = __uint_as_float(__float_as_uint(e[9]) ^ sg);
       float num = (float)ioff[f] - dot;
-      bool better = den > 0.0f && prod_lt(num, bden, bnum, den);
+      bool better = den > 0.0f && (double)num * (double)bden < (double)bnum * (double)den;
       bnum = better ? num : bnum;
       bden = better ? den : bden;
       blink = better ? (lw[f] & kLink27Boundary) : blink;

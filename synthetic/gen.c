@@ -125,7 +125,26 @@ static void curl(double x, double y, double z, uint64_t seed, double v[3]) {
   v[2] = dpy_dx - dpx_dy;
 }
 
+/* The advection map p -> q(p) is smooth (the curl field's features span a
+ * third of the domain), so it is sampled on a lattice of 129^3 points over
+ * [0,1]^3 and interpolated trilinearly at the voxel centres. */
+#define PLUME_L 129
 void synth_plume_raw(uint64_t seed, int32_t n, float* out) {
+  const int64_t L = PLUME_L;
+  double* Q = (double*)malloc(sizeof(double) * 3 * (size_t)(L * L * L));
+  if (!Q) return;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < L; k++)
+    for (int64_t j = 0; j < L; j++)
+      for (int64_t i = 0; i < L; i++) {
+        double q[3] = {3.0 * i / (L - 1), 3.0 * j / (L - 1), 3.0 * k / (L - 1)};
+        for (int s = 0; s < 4; s++) {
+          double c[3];
+          curl(q[0], q[1], q[2], seed, c);
+          for (int a = 0; a < 3; a++) q[a] -= 0.06 * c[a];
+        }
+        for (int a = 0; a < 3; a++) Q[3 * (i + L * (j + L * k)) + a] = q[a];
+      }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t k = 0; k < n; k++)
     for (int64_t j = 0; j < n; j++)
@@ -137,14 +156,75 @@ void synth_plume_raw(uint64_t seed, int32_t n, float* out) {
         double mask = exp(-(dx * dx + dz * dz) / (2.0 * rr * rr)) * exp(-h / 0.45);
         double v = 0.0;
         if (mask > 1e-3) {
-          double q[3] = {p[0] * 3.0, p[1] * 3.0, p[2] * 3.0};
-          for (int s = 0; s < 4; s++) {
-            double c[3];
-            curl(q[0], q[1], q[2], seed, c);
-            for (int a = 0; a < 3; a++) q[a] -= 0.06 * c[a];
+          double g[3], f[3];
+          int64_t c0[3];
+          for (int a = 0; a < 3; a++) {
+            g[a] = p[a] * (L - 1);
+            c0[a] = (int64_t)g[a];
+            if (c0[a] > L - 2) c0[a] = L - 2;
+            f[a] = g[a] - c0[a];
+          }
+          double q[3] = {0.0, 0.0, 0.0};
+          for (int c = 0; c < 8; c++) {
+            int64_t ci = c0[0] + (c & 1), cj = c0[1] + ((c >> 1) & 1), ck = c0[2] + ((c >> 2) & 1);
+            double w = ((c & 1) ? f[0] : 1.0 - f[0]) * (((c >> 1) & 1) ? f[1] : 1.0 - f[1]) *
+                       (((c >> 2) & 1) ? f[2] : 1.0 - f[2]);
+            const double* qq = Q + 3 * (ci + L * (cj + L * ck));
+            for (int a = 0; a < 3; a++) q[a] += w * qq[a];
           }
           v = (0.5 + 0.8 * fbm(q[0] / 3.0, q[1] / 3.0 - 0.2 * h, q[2] / 3.0, 5, 6.0, seed + 77)) * mask;
         }
         out[i + n * (j + n * k)] = (float)(v > 0.0 ? v : 0.0);
       }
+  free(Q);
+}
+
+/* In place: v = max(v - cut, 0) * (float)(peak / max), cut = the value of
+ * rank floor((1 - keep_fraction) count) in ascending order (exact radix
+ * selection on the bit patterns of these non-negative floats: upper 16
+ * bits, then lower 16 bits). */
+void synth_threshold(float* v, int64_t count, double keep_fraction, double peak) {
+  int64_t rank = (int64_t)((1.0 - keep_fraction) * (double)count);
+  if (rank >= count) rank = count - 1;
+  uint64_t* hist = (uint64_t*)calloc(65536, sizeof(uint64_t));
+  if (!hist) return;
+  uint32_t prefix = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    memset(hist, 0, 65536 * sizeof(uint64_t));
+#pragma omp parallel
+    {
+      uint64_t* h = (uint64_t*)calloc(65536, sizeof(uint64_t));
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < count; i++) {
+        uint32_t u;
+        memcpy(&u, v + i, 4);
+        if (pass == 0) h[u >> 16]++;
+        else if ((u >> 16) == prefix) h[u & 0xFFFFu]++;
+      }
+#pragma omp critical
+      for (int b = 0; b < 65536; b++) hist[b] += h[b];
+      free(h);
+    }
+    int b = 0;
+    while (rank >= (int64_t)hist[b]) {
+      rank -= (int64_t)hist[b];
+      b++;
+    }
+    prefix = pass == 0 ? (uint32_t)b : ((prefix << 16) | (uint32_t)b);
+  }
+  free(hist);
+  float cut;
+  memcpy(&cut, &prefix, 4);
+  float m = 0.0f;
+#pragma omp parallel for reduction(max : m)
+  for (int64_t i = 0; i < count; i++) {
+    float d = v[i] - cut;
+    v[i] = d > 0.0f ? d : 0.0f;
+    m = v[i] > m ? v[i] : m;
+  }
+  if (m > 0.0f) {
+    float sc = (float)(peak / (double)m);
+#pragma omp parallel for
+    for (int64_t i = 0; i < count; i++) v[i] = v[i] * sc;
+  }
 }

@@ -186,3 +186,19 @@ def test_training_reduces_loss():
         _, g = oracle.mlp_backward(P, x, dy)
         oracle.adam_step(P, g, m, v, step, lr=3e-3)
     assert loss < 0.2 * first
+
+
+def test_weight_average_closed_forms():
+    """Bias-corrected exponential average: constant weights give themselves;
+    two steps give (b w1 + w2) / (1 + b)."""
+    rng = np.random.default_rng(14)
+    c = rng.normal(size=50)
+    ema = np.zeros(50)
+    for t in range(1, 6):
+        out = oracle.ema_step(ema, c, 0.9, t)
+        assert np.allclose(out, c, rtol=1e-14, atol=0)
+    w1, w2 = rng.normal(size=50), rng.normal(size=50)
+    ema = np.zeros(50)
+    oracle.ema_step(ema, w1, 0.95, 1)
+    out = oracle.ema_step(ema, w2, 0.95, 2)
+    assert np.allclose(out, (0.95 * w1 + w2) / 1.95, rtol=1e-14, atol=1e-16)
