@@ -225,7 +225,8 @@ def plume_leg(tv, torch) -> dict:
     return out, (g, sc, ref)
 
 
-def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int = 1024) -> dict:
+def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int = 1024,
+            frames_per_row: int = 3, ema: float = 0.95) -> dict:
     """Online-trained radiance cache vs the plain renderer at equal RMSE.
 
     RMSE is measured against a 1024-spp plain render; that reference's own
@@ -252,7 +253,7 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int 
 
     rmse_plain32 = 0.5 * (rmse(a) + rmse(b))
     ms_plain32 = 0.5 * (sa["ms"] + sb["ms"])
-    nrc = tv.Nrc(dict(lr=lr))
+    nrc = tv.Nrc(dict(lr=lr, ema=ema))
     p0 = nrc.export()
     untrained = None
     losses, train_ms = [], []
@@ -268,11 +269,18 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int 
         train_ms.append(st["ms"])
     rows = []
     for i, spp in enumerate([1, 2, 4, 8, 16, 32, 128]):
-        # one frame of online rendering: the truncated render also traces the
-        # frame's training paths in the same launch, then the cache trains
-        img, st = tv.render(grid, cam, med, light, spp, 4000 + i, dict(ro, nrc=nrc, nrc_train=1))
-        e = rmse(img.cpu().numpy().astype(np.float64))
-        t = st["ms"]
+        # frames of online rendering: the truncated render also traces the
+        # frame's training paths in the same launch, then the cache trains;
+        # RMSE and time averaged over `frames_per_row` consecutive frames
+        mse, t, sts = 0.0, 0.0, []
+        for f in range(frames_per_row):
+            img, st = tv.render(grid, cam, med, light, spp, 4000 + 16 * i + f, dict(ro, nrc=nrc, nrc_train=1))
+            e = rmse(img.cpu().numpy().astype(np.float64))
+            mse += e * e / frames_per_row
+            t += st["ms"] / frames_per_row
+            sts.append(st)
+        e = float(np.sqrt(mse))
+        st = sts[-1]
         plain_spp = 32.0 * (rmse_plain32 / e) ** 2 if e > 0 else float("inf")
         plain_ms = ms_plain32 * plain_spp / 32.0
         rows.append({"spp": spp, "rmse": round(e, 6), "ms_frame": round(t, 3), "ms_trace": round(st["trace_ms"], 3),
@@ -288,7 +296,7 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int 
             "plain": {"spp": 32, "rmse": round(rmse_plain32, 6), "ms": round(ms_plain32, 3),
                       "tet_steps": sa["tet_steps"]},
             "reference_spp": ref_spp, "truncate_bounce": nrc.info()["truncate_bounce"],
-            "train_frames": frames, "lr": lr, "train_frame_ms": round(float(np.mean(train_ms)), 3),
+            "train_frames": frames, "lr": lr, "weight_average": nrc.info()["ema"], "frames_per_row": frames_per_row, "train_frame_ms": round(float(np.mean(train_ms)), 3),
             "loss_first_last": [round(float(np.mean(losses[:5])), 5), round(float(np.mean(losses[-5:])), 5)],
             "rmse_untrained_32spp": round(untrained, 6), "bias_floor_rmse_128spp": rows[-1]["rmse"],
             "rows": rows,
@@ -359,7 +367,8 @@ def main():
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 1024^3 plume leg (the radiance-cache leg then runs on the cloud)")
     ap.add_argument("--nrc-frames", type=int, default=100)
-    ap.add_argument("--nrc-lr", type=float, default=3e-3)
+    ap.add_argument("--nrc-lr", type=float, default=1e-2)
+    ap.add_argument("--nrc-ema", type=float, default=0.99)
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="")
@@ -472,10 +481,11 @@ def main():
         if plume is not None:  # the cache study runs on the production-scale scene
             del grid
             g, psc, ref = plume
-            res["nrc"] = nrc_leg(tv, torch, g, psc, args.nrc_frames, args.nrc_lr, ref=ref, ref_spp=1024)
+            res["nrc"] = nrc_leg(tv, torch, g, psc, args.nrc_frames, args.nrc_lr, ref=ref, ref_spp=1024,
+                                 ema=args.nrc_ema)
             res["nrc"]["scene"] = "plume 1024^3 (64 bounces)"
         else:
-            res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr)
+            res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr, ema=args.nrc_ema)
             res["nrc"]["scene"] = "cloud 256^3 (32 bounces)"
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")

@@ -252,7 +252,9 @@ typedef struct {
   float lr, beta1, beta2, eps; /* Adam (defaults 1e-3, 0.9, 0.99, 1e-8) */
   float sigma_ref;          /* extinction normaliser of the features, > 0; 0 = the largest extinction of
                                the first grid trained on (default 0) */
-  int32_t reserved;
+  float ema;                /* queries use the average ema_t = e ema_{t-1} + (1 - e) w_t of the weights
+                               after each Adam step, divided by 1 - e^t (0 = the current weights;
+                               default 0.95, 0 <= e < 1) */
   uint64_t seed;            /* weight initialisation (He-uniform weights, zero biases) */
 } tet_nrc_opts;
 
@@ -270,8 +272,11 @@ void tet_nrc_free(tet_nrc* nrc);
 /* Options in force (sigma_ref resolved once set) and Adam steps taken. */
 int tet_nrc_info(const tet_nrc* nrc, tet_nrc_opts* opts, int64_t* adam_steps);
 /* FP32 master parameters out / in (17,603 values, layout above); import
- * also resets the Adam moments and step count. */
+ * also resets the Adam moments, the weight average and the step count.
+ * tet_nrc_export_inference gives the weights queries use (the averaged
+ * ones when ema > 0). */
 int tet_nrc_export(const tet_nrc* nrc, float* params, int32_t on_device, void* hip_stream);
+int tet_nrc_export_inference(const tet_nrc* nrc, float* params, int32_t on_device, void* hip_stream);
 int tet_nrc_import(tet_nrc* nrc, const float* params, int32_t on_device, void* hip_stream);
 /* Network outputs (unclamped) at `count` points: pos, dir count x 3,
  * sigma count (raw extinction), y count x 3; all on one side.  Needs

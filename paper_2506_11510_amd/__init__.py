@@ -264,6 +264,12 @@ class Nrc:
         check(lib().tet_nrc_export(self._h, p.ctypes.data, 0, _stream()), "tet_nrc_export")
         return p
 
+    def export_inference(self) -> np.ndarray:
+        """The weights queries use (the bias-corrected average when ema > 0)."""
+        p = np.empty(N_PARAMS, np.float32)
+        check(lib().tet_nrc_export_inference(self._h, p.ctypes.data, 0, _stream()), "tet_nrc_export_inference")
+        return p
+
     def load(self, params) -> None:
         """Sets the master weights (17,603 FP32) and resets Adam."""
         p = np.ascontiguousarray(params, np.float32).reshape(-1)

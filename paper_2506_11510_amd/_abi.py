@@ -71,10 +71,10 @@ class TetNrcOpts(ctypes.Structure):
     _fields_ = [("truncate_bounce", ctypes.c_int32), ("train_paths", ctypes.c_int32),
                 ("train_vertices", ctypes.c_int32), ("train_steps", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("sigma_ref", ctypes.c_float), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("sigma_ref", ctypes.c_float), ("ema", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class TetNrcStats(ctypes.Structure):
@@ -123,6 +123,7 @@ SIGNATURES = {
     "tet_nrc_free": (None, [VP]),
     "tet_nrc_info": (ctypes.c_int, [VP, ctypes.POINTER(TetNrcOpts), ctypes.POINTER(ctypes.c_int64)]),
     "tet_nrc_export": (ctypes.c_int, [VP, VP, ctypes.c_int32, VP]),
+    "tet_nrc_export_inference": (ctypes.c_int, [VP, VP, ctypes.c_int32, VP]),
     "tet_nrc_import": (ctypes.c_int, [VP, VP, ctypes.c_int32, VP]),
     "tet_nrc_infer": (ctypes.c_int, [VP, ctypes.c_int64, VP, VP, VP, VP, ctypes.c_int32, VP]),
     "tet_nrc_forward_backward": (ctypes.c_int, [VP, ctypes.c_int32, VP, VP, VP, VP, ctypes.c_int32, VP]),

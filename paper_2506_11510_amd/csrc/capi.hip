@@ -348,6 +348,7 @@ void tet_nrc_opts_defaults(tet_nrc_opts* o) {
   o->beta2 = 0.99f;
   o->eps = 1e-8f;
   o->sigma_ref = 0.0f;
+  o->ema = 0.95f;
   o->seed = 0x5EEDull;
 }
 
@@ -370,6 +371,10 @@ int tet_nrc_info(const tet_nrc* nrc, tet_nrc_opts* opts, int64_t* adam_steps) {
 
 int tet_nrc_export(const tet_nrc* nrc, float* params, int32_t on_device, void* hip_stream) {
   TV_GUARD(nrc_export(nrc, params, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_nrc_export_inference(const tet_nrc* nrc, float* params, int32_t on_device, void* hip_stream) {
+  TV_GUARD(nrc_export_inference(nrc, params, on_device, (hipStream_t)hip_stream));
 }
 
 int tet_nrc_import(tet_nrc* nrc, const float* params, int32_t on_device, void* hip_stream) {

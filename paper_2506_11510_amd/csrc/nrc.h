@@ -47,6 +47,7 @@ int nrc_create(const tet_nrc_opts* opts, tet_nrc** out);
 void nrc_free(tet_nrc* n);
 int nrc_export(const tet_nrc* n, float* params, int32_t on_device, hipStream_t st);
 int nrc_import(tet_nrc* n, const float* params, int32_t on_device, hipStream_t st);
+int nrc_export_inference(const tet_nrc* n, float* params, int32_t on_device, hipStream_t st);
 int nrc_infer(const tet_nrc* n, int64_t count, const float* pos, const float* dir, const float* sigma, float* y,
               int32_t on_device, hipStream_t st);
 int nrc_forward_backward(const tet_nrc* n, int32_t count, const float* feats, const float* dy, float* y, float* grads,
@@ -70,5 +71,10 @@ struct tet_nrc {
   float* master;   // FP32 parameters
   float* m;        // Adam first moments
   float* v;        // Adam second moments
-  char* net;       // packed network (kNrcNetBytes)
+  char* net;       // packed network of the master weights (training)
+  float* ema;      // weight average (zero-initialised)
+  float* infer;    // the weights queries use: ema / (1 - e^step), or the master weights
+  char* net_infer; // packed network of `infer`
+  // packed network the queries use
+  const char* query_net() const { return opts.ema > 0.0f ? net_infer : net; }
 };

@@ -535,6 +535,9 @@ struct NrcReduceArgs {
   const float* loss_part;
   float* loss;  // nullable: sum of loss_part times norm
   float norm;
+  float* ema;    // nullable: weight average, updated after the Adam step
+  float* infer;  // its bias-corrected value
+  float ema_b, ema_c;  // e, 1 - e^step
 };
 
 // Gradient = sum of the blocks' parts in block order (deterministic); then
@@ -551,7 +554,13 @@ __global__ void k_nrc_reduce(NrcReduceArgs A) {
       A.m[p] = mm;
       A.v[p] = vv;
       float mh = mm / A.c1, vh = vv / A.c2;
-      A.master[p] = A.master[p] - A.lr * mh / (sqrtf(vh) + A.eps);
+      float w = A.master[p] - A.lr * mh / (sqrtf(vh) + A.eps);
+      A.master[p] = w;
+      if (A.ema) {
+        float e = A.ema_b * A.ema[p] + (1.0f - A.ema_b) * w;
+        A.ema[p] = e;
+        A.infer[p] = e / A.ema_c;
+      }
     }
   }
   if (p == 0 && A.loss) {
@@ -671,9 +680,13 @@ int check_nrc(const tet_nrc* nrc) {
   return TET_OK;
 }
 
+// Packs the master weights (training) and, with a weight average, the
+// weights the queries use.
 int pack(tet_nrc* nrc, hipStream_t st) {
   int total = kNrcFrags * 256 + kNrcBias;
   hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, nrc->master, nrc->net);
+  if (nrc->opts.ema > 0.0f)
+    hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, nrc->infer, nrc->net_infer);
   TV_HIP(hipGetLastError());
   return TET_OK;
 }
@@ -735,6 +748,12 @@ int launch_reduce(tet_nrc* nrc, int32_t count, const float* part, const float* l
     A.eps = o.eps;
     A.c1 = (float)(1.0 - std::pow((double)o.beta1, (double)nrc->step));
     A.c2 = (float)(1.0 - std::pow((double)o.beta2, (double)nrc->step));
+    if (o.ema > 0.0f) {
+      A.ema = nrc->ema;
+      A.infer = nrc->infer;
+      A.ema_b = o.ema;
+      A.ema_c = (float)(1.0 - std::pow((double)o.ema, (double)nrc->step));
+    }
   }
   hipLaunchKernelGGL(k_nrc_reduce, dim3((kNrcParams + 255) / 256), dim3(256), 0, st, A);
   TV_HIP(hipGetLastError());
@@ -801,7 +820,8 @@ int nrc_create(const tet_nrc_opts* in, tet_nrc** out) {
   else tet_nrc_opts_defaults(&o);
   if (o.truncate_bounce < 1 || o.train_paths < 1 || o.train_paths > (1 << 24) || o.train_vertices < 1 ||
       o.train_vertices > 16 || o.train_steps < 1 || !(o.lr > 0.0f) || !(o.beta1 >= 0.0f && o.beta1 < 1.0f) ||
-      !(o.beta2 >= 0.0f && o.beta2 < 1.0f) || !(o.eps > 0.0f) || !(o.sigma_ref >= 0.0f))
+      !(o.beta2 >= 0.0f && o.beta2 < 1.0f) || !(o.eps > 0.0f) || !(o.sigma_ref >= 0.0f) ||
+      !(o.ema >= 0.0f && o.ema < 1.0f))
     return fail(TET_ERR_INVALID_ARG, "tet_nrc_create: bad options");
   tet_nrc* n = new tet_nrc();
   memset(n, 0, sizeof(*n));
@@ -812,7 +832,9 @@ int nrc_create(const tet_nrc_opts* in, tet_nrc** out) {
   }
   size_t pb = (size_t)kNrcParams * 4;
   if (hipMalloc(&n->master, pb) != hipSuccess || hipMalloc(&n->m, pb) != hipSuccess ||
-      hipMalloc(&n->v, pb) != hipSuccess || hipMalloc(&n->net, kNrcNetBytes) != hipSuccess) {
+      hipMalloc(&n->v, pb) != hipSuccess || hipMalloc(&n->net, kNrcNetBytes) != hipSuccess ||
+      hipMalloc(&n->ema, pb) != hipSuccess || hipMalloc(&n->infer, pb) != hipSuccess ||
+      hipMalloc(&n->net_infer, kNrcNetBytes) != hipSuccess) {
     (void)hipGetLastError();
     nrc_free(n);
     return fail(TET_ERR_OUT_OF_MEMORY, "tet_nrc_create: device memory");
@@ -843,6 +865,9 @@ void nrc_free(tet_nrc* n) {
   if (n->m) (void)hipFree(n->m);
   if (n->v) (void)hipFree(n->v);
   if (n->net) (void)hipFree(n->net);
+  if (n->ema) (void)hipFree(n->ema);
+  if (n->infer) (void)hipFree(n->infer);
+  if (n->net_infer) (void)hipFree(n->net_infer);
   delete n;
 }
 
@@ -863,8 +888,19 @@ int nrc_import(tet_nrc* n, const float* params, int32_t on_device, hipStream_t s
   std::vector<float> z(kNrcParams, 0.0f);
   TV_HIP(hipMemcpyAsync(n->m, z.data(), pb, hipMemcpyHostToDevice, st));
   TV_HIP(hipMemcpyAsync(n->v, z.data(), pb, hipMemcpyHostToDevice, st));
+  TV_HIP(hipMemcpyAsync(n->ema, z.data(), pb, hipMemcpyHostToDevice, st));
+  TV_HIP(hipMemcpyAsync(n->infer, n->master, pb, hipMemcpyDeviceToDevice, st));
   n->step = 0;
   if (int rc = pack(n, st)) return rc;
+  TV_HIP(hipStreamSynchronize(st));
+  return TET_OK;
+}
+
+int nrc_export_inference(const tet_nrc* n, float* params, int32_t on_device, hipStream_t st) {
+  if (int rc = check_nrc(n)) return rc;
+  if (!params) return fail(TET_ERR_INVALID_ARG, "tet_nrc_export_inference: params is NULL");
+  TV_HIP(hipMemcpyAsync(params, n->opts.ema > 0.0f ? n->infer : n->master, (size_t)kNrcParams * 4,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
   TV_HIP(hipStreamSynchronize(st));
   return TET_OK;
 }
@@ -880,7 +916,7 @@ int nrc_infer(const tet_nrc* n, int64_t count, const float* pos, const float* di
   if (!s.p) return fail(TET_ERR_OUT_OF_MEMORY, "tet_nrc_infer: scratch");
   NrcQueryArgs Q;
   memset(&Q, 0, sizeof(Q));
-  Q.net = n->net;
+  Q.net = n->query_net();
   Q.lref = std::log1p((double)n->opts.sigma_ref);
   Q.count = count;
   if (on_device) {
@@ -911,7 +947,7 @@ int nrc_query_pass(const tet_nrc* n, float4* entries, int64_t count, hipStream_t
   if (count <= 0) return TET_OK;
   NrcQueryArgs Q;
   memset(&Q, 0, sizeof(Q));
-  Q.net = n->net;
+  Q.net = n->query_net();
   Q.lref = std::log1p((double)n->opts.sigma_ref);
   Q.count = count;
   Q.rec = entries;

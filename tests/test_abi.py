@@ -73,7 +73,7 @@ def test_batch_and_cache_argument_errors_without_gpu():
     o = _abi.TetNrcOpts()
     L.tet_nrc_opts_defaults(ctypes.byref(o))
     assert (o.truncate_bounce, o.train_paths, o.train_vertices, o.train_steps) == (2, 16384, 4, 4)
-    assert o.lr == pytest.approx(1e-3) and o.beta2 == pytest.approx(0.99)
+    assert o.lr == pytest.approx(1e-3) and o.beta2 == pytest.approx(0.99) and o.ema == pytest.approx(0.95)
     o.train_vertices = 17
     assert L.tet_nrc_create(ctypes.byref(o), ctypes.byref(h)) == _abi.TET_ERR_INVALID_ARG and h.value is None
     assert L.tet_nrc_info(None, None, None) == _abi.TET_ERR_INVALID_ARG

@@ -344,3 +344,28 @@ def test_training_inside_the_render_launch(tv, tiny):
     assert a.info()["adam_steps"] == b.info()["adam_steps"] == 4
     x, y = img.cpu().numpy().astype(np.float64), img_plain.cpu().numpy().astype(np.float64)
     assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30)
+
+
+def test_weight_average_matches_oracle(tv):
+    """Queries use the bias-corrected average of the weights after each Adam
+    step (ema 0.9 here); it equals the oracle's average of the exported
+    master weights to FP32 rounding."""
+    say("case nrc weight average")
+    P = rand_params(15, scale=0.5)
+    pos, d, s = rand_points(16, 1024)
+    t = np.abs(np.random.default_rng(17).normal(0.5, 0.3, (1024, 3))).astype(np.float32)
+    n = tv.Nrc(dict(sigma_ref=20.0, ema=0.9))
+    n.load(P)
+    assert np.array_equal(n.export_inference(), P)  # before any step: the weights themselves
+    ema = np.zeros(NP)
+    for step in range(1, 4):
+        n.train_batch(pos, d, s, t)
+        want = oracle.ema_step(ema, n.export().astype(np.float64), 0.9, step)
+        got = n.export_inference().astype(np.float64)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say(f"  step {step}: worst relative difference {err:.3g}")
+        assert err <= 1e-6
+    # the queries use these weights
+    y = n.infer(pos[:256], d[:256], s[:256]).cpu().numpy()
+    x = oracle.nrc_encode(pos[:256], d[:256], s[:256], 20.0).astype(np.float64)
+    assert_bf16_parity(y, oracle.mlp_forward(n.export_inference().astype(np.float64), x, bf16=True), "averaged infer")
