@@ -300,7 +300,7 @@ def nrc_leg(tv, torch, grid, sc, frames: int, lr: float, ref=None, ref_spp: int 
             "loss_first_last": [round(float(np.mean(losses[:5])), 5), round(float(np.mean(losses[-5:])), 5)],
             "rmse_untrained_32spp": round(untrained, 6), "bias_floor_rmse_128spp": rows[-1]["rmse"],
             "rows": rows,
-            "query_roofline": {"bound": "mfma", "kernel": "k_nrc_query<1> + k_nrc_gather (32 spp frame)",
+            "query_roofline": {"bound": "mfma", "kernel": "k_nrc_query<1> (32 spp frame)",
                                "achieved": round(achieved, 3), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 5),
                                "flop_per_query": NRC_FLOP_PER_QUERY}}

@@ -22,10 +22,12 @@ constexpr int kNrcFwdFrags = 38;
 constexpr int kNrcBias = 272;
 constexpr size_t kNrcNetBytes = (size_t)kNrcFrags * 1024 + (size_t)kNrcBias * 4;
 
-// A truncated path's query, 32 bytes, written over the sample's entry
-// record: (x, y, z, sigma), (dx, dy, dz, beta); beta == 0 means no query.
-// The query pass replaces the first half by (contribution rgb, 0).
-int nrc_query_pass(const tet_nrc* nrc, float4* entries, int64_t count, hipStream_t st);
+// The cache queries of a render pass: *qcount compacted queries of 32
+// bytes, (x, y, z, sigma), (dx, dy, dz, beta), and their pixels; each adds
+// beta * max(cache, 0) to its pixel's running sum in `out` (atomically).
+// capacity bounds *qcount.
+int nrc_query_pass(const tet_nrc* nrc, const float4* q, const uint32_t* qpix, const uint32_t* qcount, float* out,
+                   int64_t capacity, hipStream_t st);
 
 // Traces the training paths of a frame (untruncated), writing per path up
 // to kv vertex records of 3 float4 -- (x, sigma), (d, beta before the

@@ -196,11 +196,14 @@ struct NrcQueryArgs {
   const float* dir;
   const float* sigma;
   float* y;
-  float4* rec;  // mode 1: query records, contributions written back
+  const float4* q;          // mode 1: compacted query records, their pixels, their number
+  const uint32_t* qpix;
+  const uint32_t* qcount;
+  float* out;               // running pixel sums
 };
 
 // Mode 0: network outputs at explicit points.  Mode 1: a render pass's
-// queries; each becomes beta * max(y, 0) in its record's first half.
+// queries; each adds beta * max(y, 0) to its pixel.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_nrc_query(NrcQueryArgs Q) {
   __shared__ u32x4 s_frag[kNrcFwdFrags * 64];
@@ -215,25 +218,24 @@ __global__ __launch_bounds__(256) void k_nrc_query(NrcQueryArgs Q) {
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t base = wave * 64; base < Q.count; base += nwaves * 64) {
+  const int64_t count = MODE == 1 ? (int64_t)min((uint64_t)*Q.qcount, (uint64_t)Q.count) : Q.count;
+  for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
     float p[4][3], d[4][3], sg[4], beta[4];
     bool valid[4];
     bool any = false;
 #pragma unroll
     for (int cb = 0; cb < 4; cb++) {
       int64_t n = base + 16 * cb + r;
-      valid[cb] = n < Q.count;
+      valid[cb] = n < count;
       float4 a = make_float4(0, 0, 0, 0), b = a;
-      if (MODE == 0) {
-        if (valid[cb]) {
+      if (valid[cb]) {
+        if (MODE == 0) {
           a = make_float4(Q.pos[3 * n], Q.pos[3 * n + 1], Q.pos[3 * n + 2], Q.sigma[n]);
           b = make_float4(Q.dir[3 * n], Q.dir[3 * n + 1], Q.dir[3 * n + 2], 1.0f);
+        } else {
+          a = Q.q[2 * n];
+          b = Q.q[2 * n + 1];
         }
-      } else {
-        if (valid[cb]) b = Q.rec[2 * n + 1];
-        valid[cb] = valid[cb] && b.w > 0.0f;
-        if (valid[cb]) a = Q.rec[2 * n];
-        else b = make_float4(0, 0, 0, 0);
       }
       p[cb][0] = a.x;
       p[cb][1] = a.y;
@@ -273,8 +275,10 @@ __global__ __launch_bounds__(256) void k_nrc_query(NrcQueryArgs Q) {
           Q.y[3 * n + 1] = o[cb][1];
           Q.y[3 * n + 2] = o[cb][2];
         } else {
-          Q.rec[2 * n] = make_float4(beta[cb] * fmaxf(o[cb][0], 0.0f), beta[cb] * fmaxf(o[cb][1], 0.0f),
-                                     beta[cb] * fmaxf(o[cb][2], 0.0f), 0.0f);
+          float* px = Q.out + 3 * (size_t)Q.qpix[n];
+          atomicAdd(px, beta[cb] * fmaxf(o[cb][0], 0.0f));
+          atomicAdd(px + 1, beta[cb] * fmaxf(o[cb][1], 0.0f));
+          atomicAdd(px + 2, beta[cb] * fmaxf(o[cb][2], 0.0f));
         }
       }
     }
@@ -943,18 +947,23 @@ int nrc_infer(const tet_nrc* n, int64_t count, const float* pos, const float* di
   return TET_OK;
 }
 
-int nrc_query_pass(const tet_nrc* n, float4* entries, int64_t count, hipStream_t st) {
-  if (count <= 0) return TET_OK;
+int nrc_query_pass(const tet_nrc* n, const float4* q, const uint32_t* qpix, const uint32_t* qcount, float* out,
+                   int64_t capacity, hipStream_t st) {
+  if (capacity <= 0) return TET_OK;
   NrcQueryArgs Q;
   memset(&Q, 0, sizeof(Q));
   Q.net = n->query_net();
   Q.lref = std::log1p((double)n->opts.sigma_ref);
-  Q.count = count;
-  Q.rec = entries;
+  Q.count = capacity;
+  Q.q = q;
+  Q.qpix = qpix;
+  Q.qcount = qcount;
+  Q.out = out;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int64_t waves = (count + 63) / 64;
-  unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, (int64_t)cus * 8));
+  // persistent blocks (the number of queries is on the device): 2 per CU
+  int64_t waves = (capacity + 63) / 64;
+  unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, (int64_t)cus * 2));
   hipLaunchKernelGGL(k_nrc_query<1>, dim3(grid), dim3(256), 0, st, Q);
   TV_HIP(hipGetLastError());
   return TET_OK;

@@ -114,7 +114,9 @@ struct RenderArgs {
   uint32_t npix;         // width * height
   int32_t truncate;      // real vertex where a path queries the cache
   int32_t rec_vertices;  // vertices recorded per training path
-  float4* qrec;          // queries, over the entry records
+  float4* qbuf;          // cache queries of the pass, compacted: (x, sigma), (d, beta)
+  uint32_t* qpix;        // their pixels
+  uint32_t* qcount;      // queries so far (one atomic per wave)
   float4* vrec;          // training-path vertex records
   float4* path_l;        // training-path radiance and vertex count
   const tet_nrc* nrc;    // host handle (the query pass), never read on the device
@@ -585,15 +587,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     unsigned long long waiting = __ballot(mode > M_SHADOW);
     if (waiting && (__popcll(waiting) >= A.event_wait || __popcll(waiting) == 64 ||
                     __ballot(mode <= M_SHADOW) == 0)) {
-      if (NRC == 1 && mode == M_COLLIDE && !trainp && (int32_t)bounce + 1 == A.truncate) {
-        // the cache stands for the rest of the path: leave a query
-        n_real++;
-        bounce++;
-        float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-        A.qrec[2 * (size_t)ent] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
-        A.qrec[2 * (size_t)ent + 1] = make_float4(d.x, d.y, d.z, beta);
-        n_query++;
-        mode = M_FINISH;
+      if (NRC == 1) {  // the cache stands for the rest of the path: append a query
+        const bool isq = mode == M_COLLIDE && !trainp && (int32_t)bounce + 1 == A.truncate;
+        const unsigned long long qm = __ballot(isq);
+        if (qm) {
+          const int lead = __builtin_ctzll(qm);
+          uint32_t base = 0;
+          if (lane == lead) base = atomicAdd(A.qcount, (uint32_t)__popcll(qm));
+          base = __shfl(base, lead);
+          if (isq) {
+            const uint32_t q = base + (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
+            n_real++;
+            bounce++;
+            float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+            A.qbuf[2 * (size_t)q] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
+            A.qbuf[2 * (size_t)q + 1] = make_float4(d.x, d.y, d.z, beta);
+            A.qpix[q] = pix;
+            n_query++;
+            mode = M_FINISH;
+          }
+        }
       }
       if (mode == M_COLLIDE) {  // real collision at t: start the light ray
         n_real++;
@@ -757,7 +770,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       if (mode == M_START) {  // new sample: its precomputed entry into the grid
         const float4* q = (const float4*)(A.entries + ent);
         float4 a = q[0], b = q[1];
-        if (NRC == 1) ((float*)(A.qrec + 2 * (size_t)ent + 1))[3] = 0.0f;  // no query (yet)
         uint32_t c = __float_as_uint(a.w);
         steps = 0;
         if (c == kMiss) {
@@ -893,28 +905,6 @@ __global__ void k_scale_f32(float* p, int64_t n, float div) {
   if (i < n) p[i] = p[i] / div;
 }
 
-// Adds each pixel's cache contributions of one pass (its samples in order).
-__global__ void k_nrc_gather(RenderArgs A, const float4* __restrict__ rec) {
-  uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= A.slots) return;
-  int32_t px, py;
-  if (!slot_pixel(slot, A.tiles_x, A.fr.w, A.fr.h, px, py)) return;
-  float cx = 0.0f, cy = 0.0f, cz = 0.0f;
-  const float4* q = rec + 2 * (size_t)slot * (uint32_t)A.pass_spp;
-  for (int32_t k = 0; k < A.pass_spp; k++) {
-    if (q[2 * k + 1].w > 0.0f) {
-      float4 c = q[2 * k];
-      cx = cx + c.x;
-      cy = cy + c.y;
-      cz = cz + c.z;
-    }
-  }
-  float* o = A.out + 3 * ((size_t)py * A.fr.w + px);
-  o[0] = o[0] + cx;
-  o[1] = o[1] + cy;
-  o[2] = o[2] + cz;
-}
-
 __global__ void k_locate(TetMedium med, const float* __restrict__ pts, int64_t count, int64_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -979,7 +969,7 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     P.items = A.slots * (uint32_t)ipp + P.train_items;
     P.entries = entries;
     P.range_size = (P.items + 7) / 8;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 8);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 9);  // ranges, query count
     uint64_t ne = (uint64_t)A.slots * (uint64_t)P.pass_spp;
     hipLaunchKernelGGL(k_raygen<Med>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, P, med, entries);
     if (P.train_items) {  // entry records of the training paths, after the image's
@@ -1007,11 +997,8 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     }
     TV_HIP(hipGetLastError());
     TV_HIP(hipEventRecord(t1, st));
-    if (NRC == 1) {  // the pass's cache queries, then their sums per pixel
-      if (int rc = nrc_query_pass(A.nrc, (float4*)entries, (int64_t)ne, st)) return rc;
-      hipLaunchKernelGGL(k_nrc_gather, dim3((P.slots + 255) / 256), dim3(256), 0, st, P, (const float4*)entries);
-      TV_HIP(hipGetLastError());
-    }
+    if (NRC == 1)  // the pass's cache queries, added to their pixels
+      if (int rc = nrc_query_pass(A.nrc, A.qbuf, A.qpix, A.qcount, A.out, (int64_t)ne, st)) return rc;
     TV_HIP(hipEventRecord(e2, st));
     TV_HIP(hipEventSynchronize(e2));
     float ms = 0.0f;
@@ -1115,7 +1102,8 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   size_t img_bytes = (size_t)npix * 3 * sizeof(float);
   size_t ent_bytes = ((size_t)slots * (size_t)pass_cap + (size_t)n_train) * sizeof(RayEntry);
   size_t vrec_bytes = (size_t)n_train * (size_t)kv * 48, pl_bytes = (size_t)n_train * 16;
-  size_t scratch = 256 + ent_bytes + (on_device ? 0 : img_bytes) + vrec_bytes + pl_bytes;
+  size_t q_bytes = nrc ? (size_t)slots * (size_t)pass_cap * 36 : 0;  // at most one query per sample
+  size_t scratch = 256 + ent_bytes + (on_device ? 0 : img_bytes) + vrec_bytes + pl_bytes + q_bytes;
   char* sc = (char*)dev_alloc(scratch);
   if (!sc) return fail(TET_ERR_OUT_OF_MEMORY, "render: scratch");
   struct Free {
@@ -1123,7 +1111,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     ~Free() { dev_free(p); }
   } fr_{sc};
   A.counter = (uint32_t*)sc;
-  A.stats = (unsigned long long*)(sc + 64);  // counters: 8 work ranges in sc[0..32)
+  A.stats = (unsigned long long*)(sc + 64);  // counters: 8 work ranges in sc[0..32), query count at sc[32]
   RayEntry* entries = (RayEntry*)(sc + 256);
   A.out = on_device ? out_rgb : (float*)(sc + 256 + ent_bytes);
   if (train) {
@@ -1133,7 +1121,12 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   }
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
 
-  A.qrec = (float4*)entries;
+  if (nrc) {
+    char* qb = sc + 256 + ent_bytes + (on_device ? 0 : img_bytes) + vrec_bytes + pl_bytes;
+    A.qbuf = (float4*)qb;
+    A.qpix = (uint32_t*)(qb + (size_t)slots * (size_t)pass_cap * 32);
+    A.qcount = (uint32_t*)sc + 8;
+  }
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
