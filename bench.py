@@ -84,7 +84,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"])
-            if "k_render<tv::TetMedium32" in r["Kernel_Name"]:
+            if "k_render<" in r["Kernel_Name"] and ", 0, false>" in r["Kernel_Name"]:
                 trace.append(v)
             elif "copyBuffer" in r["Kernel_Name"]:
                 copies.append(v)
@@ -363,6 +363,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a plain 1 GiB device copy")
     ap.add_argument("--no-nrc", action="store_true", help="skip the radiance-cache leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch leg")
+    ap.add_argument("--no-autotune", action="store_true", help="use the fixed launch options")
+    ap.add_argument("--launch", default=None,
+                    help="JSON launch options for the tracing kernel (skips the autotuner), e.g. the ones a "
+                         "previous run chose")
     ap.add_argument("--no-dda", action="store_true", help="skip the regular-grid (DDA) leg")
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 1024^3 plume leg (the radiance-cache leg then runs on the cloud)")
@@ -391,15 +395,23 @@ def main():
     import paper_2506_11510_amd as tv
 
     sc = synthetic.scene("cloud")
-    # launch configuration of the tracing kernel: one sample per work item,
-    # batches of 64 items per wave, compact 32-byte records, 5 waves per SIMD,
-    # events handled once 48 lanes of a wave wait for one
+    # launch configuration of the tracing kernel: the library's autotuner
+    # times probe renders of this frame (8 spp) from this starting point
+    # (one sample per work item, batches of 64 items per wave, compact
+    # 32-byte records, 5 waves per SIMD, events once 48 lanes wait)
     sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
                         event_wait=48)
     cam, spp = sc["camera"], sc["render"]["spp"]
     d = sc["density_fn"]()
     dev = torch.from_numpy(d).cuda()
     out = torch.empty((cam["height"], cam["width"], 3), dtype=torch.float32, device="cuda")
+    tune_ms = None
+    if args.launch:
+        sc["render"] = dict(sc["render"], **json.loads(args.launch))
+    elif not args.no_autotune:
+        g0 = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+        sc["render"], tune_ms = tv.autotune(g0, cam, sc["medium"], sc["light"], sc["render"], probe_spp=8)
+        del g0
     torch.cuda.synchronize()
 
     def step(seed):
@@ -451,7 +463,8 @@ def main():
                                "HG g 0.3, sun + env, analytic light transmittance",
                    "step": "render only" if args.render_only else "leb_build + tet_render",
                    "num_tets": infos[-1]["num_tets"], "max_depth": infos[-1]["max_depth"],
-                   "build_rounds": infos[-1]["rounds"], "parallelism": "1 GPU"},
+                   "build_rounds": infos[-1]["rounds"], "parallelism": "1 GPU",
+                   "launch": {k: sc["render"][k] for k in tv.TUNED_FIELDS}, "autotune_probe_ms_8spp": tune_ms},
         "tet_steps_per_s": round(mean_steps / (mean_render_ms / 1e3), 1),
         "tet_steps_per_s_trace_kernel": round(mean_steps / (mean_trace_ms / 1e3), 1),
         "render_ms": round(mean_render_ms, 3), "trace_kernel_ms": round(mean_trace_ms, 3),
@@ -460,7 +473,9 @@ def main():
         "tet_steps_per_frame": int(mean_steps),
         "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated")},
         "image_mean": float(img.mean()),
-        "roofline": {"bound": "hbm", "kernel": "k_render<TetMedium32, 5, 0>", "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_render<TetMedium%s, %d, 0>" % ("32" if sc["render"]["record_layout"] == 32 else "",
+                                                                 sc["render"]["waves_per_simd"]), "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP)},

@@ -198,6 +198,28 @@ int tet_batch_create(int32_t n, const tet_grid* const* grids, const tet_camera* 
 int tet_batch_render(tet_batch* batch, const uint64_t* seeds, void* hip_stream, tet_render_stats* stats);
 void tet_batch_free(tet_batch* batch);
 
+/* Launch-option autotuner.  Times probe renders of the given frame (the
+ * same camera at probe_spp samples per pixel) over the options that shape
+ * scheduling only -- waves_per_simd, event_wait, batch_items, block_size,
+ * record_layout; samples_per_item is set to 1 -- by coordinate descent from
+ * `inout` (two sweeps, the
+ * fastest of probe_repeats timings per candidate), and writes the fastest
+ * into `inout`.  None of these options changes an image beyond FP32
+ * summation order.  With a cache_path the result is looked up first and
+ * stored after tuning, keyed by device, grid size (log2 of the tet count),
+ * image size, max_bounces and transmittance; *best_ms (nullable) receives
+ * the probe time of the chosen options (from the cache when found there). */
+typedef struct {
+  int32_t probe_spp;      /* samples per pixel of a probe render (default 2) */
+  int32_t probe_repeats;  /* timings per candidate, fastest kept (default 2) */
+  const char* cache_path; /* JSON cache file, or NULL */
+} tet_autotune_opts;
+
+void tet_autotune_opts_defaults(tet_autotune_opts* o);
+int tet_autotune(const tet_grid* grid, const tet_camera* camera, const tet_medium* medium, const tet_light* light,
+                 const tet_autotune_opts* aopts /* NULL = defaults */, tet_render_opts* inout, void* hip_stream,
+                 double* best_ms);
+
 /* Point location (the grid-entry step of Algorithm 1): canonical index of
  * the tet containing each point (3 FP32 per point, inside [0,1]^3), or -1.
  * pts and out live on the same side (on_device). */

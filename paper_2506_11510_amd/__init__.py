@@ -152,6 +152,25 @@ def dda_render(density, n: int, density_scale: float, camera: dict, medium: dict
     return out, st.as_dict()
 
 
+TUNED_FIELDS = ("waves_per_simd", "event_wait", "batch_items", "block_size", "record_layout", "samples_per_item")
+
+
+def autotune(grid: Grid, camera: dict, medium: dict, light: dict, render: dict | None = None, probe_spp: int = 2,
+             probe_repeats: int = 2, cache_path: str | None = None):
+    """Launch options for this frame chosen by the library's autotuner:
+    returns (render options dict = `render` with the tuned fields, probe ms)."""
+    o = _abi.make_render_opts(render)
+    ao = _abi.TetAutotuneOpts(int(probe_spp), int(probe_repeats),
+                              cache_path.encode() if cache_path else None)
+    ms = ctypes.c_double()
+    check(lib().tet_autotune(grid.handle, ctypes.byref(_abi.make_camera(camera)),
+                             ctypes.byref(_abi.make_medium(medium)), ctypes.byref(_abi.make_light(light)),
+                             ctypes.byref(ao), ctypes.byref(o), _stream(), ctypes.byref(ms)), "tet_autotune")
+    out = dict(render or {})
+    out.update({k: int(getattr(o, k)) for k in TUNED_FIELDS})
+    return out, ms.value
+
+
 class _SceneArrays:
     """ctypes arrays describing a batch of scenes (kept alive with it)."""
 
@@ -347,4 +366,4 @@ def release_cache():
     lib().tet_release_cache()
 
 
-__all__ = ["Grid", "Nrc", "Batch", "render_batch", "N_PARAMS", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]
+__all__ = ["Grid", "Nrc", "Batch", "render_batch", "autotune", "N_PARAMS", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]

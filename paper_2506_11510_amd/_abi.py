@@ -85,6 +85,10 @@ class TetNrcStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TetAutotuneOpts(ctypes.Structure):
+    _fields_ = [("probe_spp", ctypes.c_int32), ("probe_repeats", ctypes.c_int32), ("cache_path", ctypes.c_char_p)]
+
+
 class TetBuildStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("max_depth", ctypes.c_int32), ("num_tets", ctypes.c_int64),
                 ("ms", ctypes.c_double)]
@@ -112,6 +116,10 @@ SIGNATURES = {
                                   ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32, VP,
                                   ctypes.POINTER(TetRenderStats)]),
     "tet_grid_free": (None, [VP]),
+    "tet_autotune_opts_defaults": (None, [ctypes.POINTER(TetAutotuneOpts)]),
+    "tet_autotune": (ctypes.c_int, [VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium), ctypes.POINTER(TetLight),
+                                    ctypes.POINTER(TetAutotuneOpts), ctypes.POINTER(TetRenderOpts), VP,
+                                    ctypes.POINTER(ctypes.c_double)]),
     "tet_render_batch": (ctypes.c_int, [ctypes.c_int32, VP, VP, VP, VP, VP, VP, ctypes.POINTER(TetRenderOpts), VP,
                                         VP, ctypes.POINTER(TetRenderStats)]),
     "tet_batch_create": (ctypes.c_int, [ctypes.c_int32, VP, VP, VP, VP, VP, ctypes.POINTER(TetRenderOpts), VP,

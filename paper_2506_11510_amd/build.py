@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libtetvol.so")
-SOURCES = ["capi.hip", "build.hip", "render.hip", "nrc.hip", "batch.hip"]
+SOURCES = ["capi.hip", "build.hip", "render.hip", "nrc.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

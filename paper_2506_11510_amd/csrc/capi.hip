@@ -27,6 +27,8 @@ int batch_create(int32_t, const tet_grid* const*, const tet_camera*, const tet_m
 int batch_render(void*, const uint64_t*, hipStream_t, tet_render_stats*);
 void batch_free(void*);
 int batch_device(const void*);
+int autotune(const tet_grid*, const tet_camera*, const tet_medium*, const tet_light*, const tet_autotune_opts*,
+             tet_render_opts*, hipStream_t, double*);
 
 static thread_local std::string g_err;
 
@@ -309,6 +311,19 @@ void tet_release_cache(void) {
     it = g_free.erase(it);
   }
   (void)hipSetDevice(cur);
+}
+
+void tet_autotune_opts_defaults(tet_autotune_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->probe_spp = 2;
+  o->probe_repeats = 2;
+  o->cache_path = nullptr;
+}
+
+int tet_autotune(const tet_grid* grid, const tet_camera* camera, const tet_medium* medium, const tet_light* light,
+                 const tet_autotune_opts* aopts, tet_render_opts* inout, void* hip_stream, double* best_ms) {
+  TV_GUARD(autotune(grid, camera, medium, light, aopts, inout, (hipStream_t)hip_stream, best_ms));
 }
 
 int tet_render_batch(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,

@@ -145,3 +145,27 @@ def test_c3_batch_is_faster_than_sequential(tv):
     t_seq = (time.perf_counter() - t0) / 3
     say(f"  16 scenes: graph frame {t_batch * 1e3:.2f} ms, sequential {t_seq * 1e3:.2f} ms")
     assert t_batch < t_seq
+
+
+def test_autotune_picks_valid_options_and_caches_them(tv, scenes, tmp_path):
+    """The autotuner returns options from its candidate sets, stores them
+    under the workload key, returns the stored ones on a second call, and the
+    tuned options render the image the defaults render (summation order
+    aside)."""
+    say("case autotune")
+    import json
+    S = scenes
+    g, cam, med, light = S["grids"][0], dict(S["cams"][0], width=128, height=96), S["media"][0], S["lights"][0]
+    path = str(tmp_path / "tune.json")
+    opts, ms = tv.autotune(g, cam, med, light, RO, probe_spp=4, cache_path=path)
+    say(f"  tuned {opts}, {ms:.3f} ms")
+    assert opts["waves_per_simd"] in (4, 5, 6) and opts["event_wait"] in (16, 32, 48)
+    assert opts["batch_items"] in (32, 64, 128) and opts["block_size"] in (128, 256)
+    assert opts["record_layout"] in (32, 48) and opts["samples_per_item"] == 1 and ms > 0
+    stored = json.load(open(path))
+    assert len(stored) == 1 and list(stored.values())[0]["waves_per_simd"] == opts["waves_per_simd"]
+    opts2, ms2 = tv.autotune(g, cam, med, light, RO, probe_spp=4, cache_path=path)
+    assert opts2 == opts and ms2 == pytest.approx(ms, abs=1e-4)
+    a, _ = tv.render(g, cam, med, light, 8, 5, opts)
+    b, _ = tv.render(g, cam, med, light, 8, 5, RO)
+    sum_order_close(a.cpu().numpy(), b.cpu().numpy(), "tuned vs default options")
