@@ -652,17 +652,31 @@ __global__ void k_nrc_emit(NrcEmitArgs E) {
   }
 }
 
-__global__ void k_max_sigma32(const TetRec32* __restrict__ rec, int64_t n, uint32_t* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t v = i < n ? rec[i].w[3] : 0u;  // extinction >= 0: its bits order like the values
+// Largest extinction of a grid: wave and block maxima, then one atomic per
+// block, skipped when it cannot raise the running maximum (a single address
+// taking one atomic per wave would serialise).
+__device__ inline void block_max_to(uint32_t v, uint32_t* out) {
   for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+  __shared__ uint32_t s_max[16];
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = s_max[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) m = max(m, s_max[k]);
+    if (m > __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(out, m);
+  }
+}
+__global__ void k_max_sigma32(const TetRec32* __restrict__ rec, int64_t n, uint32_t* out) {
+  uint32_t v = 0u;  // extinction >= 0: its bits order like the values
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = max(v, rec[i].w[3]);
+  block_max_to(v, out);
 }
 __global__ void k_max_sigma48(const TetRec* __restrict__ rec, int64_t n, uint32_t* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t v = i < n ? __float_as_uint(rec[i].sigma) : 0u;
-  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+  uint32_t v = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = max(v, __float_as_uint(rec[i].sigma));
+  block_max_to(v, out);
 }
 
 __global__ void k_zero_word(uint32_t* p) { *p = 0u; }
@@ -799,7 +813,7 @@ int resolve_sigma_ref(tet_nrc* nrc, const tet_grid* g, hipStream_t st) {
   uint32_t* d = (uint32_t*)s.c();
   hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, st, d);
   int64_t n = g->n;
-  unsigned blocks = (unsigned)((n + 255) / 256);
+  unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
   if (g->rec32) hipLaunchKernelGGL(k_max_sigma32, dim3(blocks), dim3(256), 0, st, g->rec32, n, d);
   else hipLaunchKernelGGL(k_max_sigma48, dim3(blocks), dim3(256), 0, st, g->rec, n, d);
   TV_HIP(hipGetLastError());
