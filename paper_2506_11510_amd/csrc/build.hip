@@ -7,7 +7,9 @@
 // level-synchronous rounds:
 //   mark:  a leaf splits if it is wanted (subdivision criteria) or if a mesh
 //          vertex sits on the midpoint of one of its edges (a hanging vertex:
-//          some neighbour across that edge has been bisected);
+//          some neighbour across that edge has been bisected); the criteria
+//          depend on the leaf alone, so they run once per leaf, over a dense
+//          list of the leaves the previous round made;
 //   scan:  exclusive scan of (1 + split) gives every leaf its new position;
 //          children replace their parent in place, so depth-first order is
 //          kept without sorting;
@@ -191,18 +193,27 @@ __device__ inline bool vset_has(const uint64_t* __restrict__ tab, uint64_t mask,
   }
 }
 
-__device__ inline void vset_insert(uint64_t* tab, uint64_t mask, uint64_t key, uint32_t* count) {
+// Inserts key; true when it was not there before.
+__device__ inline bool vset_add(uint64_t* tab, uint64_t mask, uint64_t key) {
   uint64_t h = mix64(key) & mask;
   for (;;) {
     unsigned long long prev = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)kEmptyKey,
                                         (unsigned long long)key);
-    if (prev == kEmptyKey) {
-      atomicAdd(count, 1u);
-      return;
-    }
-    if (prev == key) return;
+    if (prev == kEmptyKey) return true;
+    if (prev == key) return false;
     h = (h + 1) & mask;
   }
+}
+
+// One atomic per wave for the number of new keys (called by every lane of
+// the wave, in uniform control flow).
+__device__ inline void count_new(bool added, uint32_t* count) {
+  unsigned long long m = __ballot(added);
+  if (m && __lane_id() == (int)__builtin_ctzll(m)) atomicAdd(count, (uint32_t)__popcll(m));
+}
+
+__device__ inline void vset_insert(uint64_t* tab, uint64_t mask, uint64_t key, uint32_t* count) {
+  if (vset_add(tab, mask, key)) atomicAdd(count, 1u);
 }
 
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
@@ -213,7 +224,8 @@ __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
 __global__ void k_vset_rehash(const uint64_t* __restrict__ old, int64_t ocap, uint64_t* tab, uint64_t mask,
                               uint32_t* count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ocap && old[i] != kEmptyKey) vset_insert(tab, mask, old[i], count);
+  bool added = i < ocap && old[i] != kEmptyKey && vset_add(tab, mask, old[i]);
+  count_new(added, count);
 }
 
 __global__ void k_vset_seed(const uint64_t* __restrict__ verts, int64_t n, uint64_t* tab, uint64_t mask,
@@ -223,39 +235,81 @@ __global__ void k_vset_seed(const uint64_t* __restrict__ verts, int64_t n, uint6
 }
 
 // ---------------------------------------------------------------- rounds
-// flags bit 0: the subdivision criteria have been evaluated and said no.
-__global__ void k_mark(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
-                       uint8_t* __restrict__ flags, uint32_t* __restrict__ cnt, Pyramid P, CamCrit cc, WantParams wp,
-                       const uint64_t* __restrict__ vset, uint64_t vmask) {
+// Leaf flags: bit 0 = the want predicate was false (it depends on the tet
+// alone, so it stays false); bit 1 = no mesh vertex sat on an edge midpoint
+// at the leaf's last check.  A leaf with bit 1 can only have gained such a
+// vertex from the last split pass, so it probes only the set of vertices
+// that pass created (nset) instead of all of them.
+
+// True when a vertex of `tab` sits on one of the tet's 6 edge midpoints;
+// the first probes are issued together, collision chains followed only
+// where the first slot holds another key.
+__device__ inline bool hanging(const uint64_t v[4], const uint64_t* __restrict__ tab, uint64_t mask) {
+  uint64_t key[6], h[6], e[6];
+  bool on[6];
+  int k = 0;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = a + 1; b < 4; b++, k++) {
+      int32_t x = vx(v[a]) + vx(v[b]), y = vy(v[a]) + vy(v[b]), z = vz(v[a]) + vz(v[b]);
+      on[k] = ((x | y | z) & 1) == 0;  // a midpoint on the lattice
+      key[k] = pack_vertex(x >> 1, y >> 1, z >> 1);
+      h[k] = mix64(key[k]) & mask;
+    }
+#pragma unroll
+  for (k = 0; k < 6; k++) e[k] = on[k] ? tab[h[k]] : kEmptyKey;
+  bool hit = false;
+#pragma unroll
+  for (k = 0; k < 6; k++) {
+    if (!on[k] || hit) continue;
+    if (e[k] == key[k]) hit = true;
+    else if (e[k] != kEmptyKey) hit = vset_has(tab, mask, key[k]);
+  }
+  return hit;
+}
+
+// Leaves whose want predicate is settled: split only when forced.
+__global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags,
+                       uint32_t* __restrict__ cnt, const uint64_t* __restrict__ vset, uint64_t vmask,
+                       const uint64_t* __restrict__ nset, uint64_t nmask) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const uint8_t fl = flags[i];
+  if (!(fl & 1)) return;  // a new leaf: k_want decides it
   uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
-  uint8_t fl = flags[i];
-  bool split = false;
-  if (!(fl & 1)) {
-    if (want(P, cc, wp, v, ids[i]))
-      split = true;
-    else
-      flags[i] = fl | 1;
-  }
-  if (!split) {
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int b = a + 1; b < 4; b++) {
-        int32_t x = vx(v[a]) + vx(v[b]), y = vy(v[a]) + vy(v[b]), z = vz(v[a]) + vz(v[b]);
-        if (((x | y | z) & 1) == 0 && !split) split = vset_has(vset, vmask, pack_vertex(x >> 1, y >> 1, z >> 1));
-      }
-  }
+  bool split = (fl & 2) ? hanging(v, nset, nmask) : hanging(v, vset, vmask);
+  if (!split && !(fl & 2)) flags[i] = fl | 2;
   cnt[i] = split ? 2u : 1u;
 }
 
-__global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
-                        const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
-                        const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids, uint64_t* __restrict__ nverts,
-                        uint8_t* __restrict__ nflags, uint64_t* vset, uint64_t vmask, uint32_t* vcount) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// The leaves made by the last split pass (a dense list, so the want
+// predicate's FP64 work runs on full waves): wanted, or forced.
+__global__ void k_want(int64_t m, const uint32_t* __restrict__ work, const uint64_t* __restrict__ ids,
+                       const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags, uint32_t* __restrict__ cnt,
+                       Pyramid P, CamCrit cc, WantParams wp, const uint64_t* __restrict__ vset, uint64_t vmask) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint32_t i = work[j];
+  uint64_t v[4] = {verts[4 * (size_t)i], verts[4 * (size_t)i + 1], verts[4 * (size_t)i + 2], verts[4 * (size_t)i + 3]};
+  bool split = want(P, cc, wp, v, ids[i]);
+  uint8_t nf = 0;
+  if (!split) {
+    nf = 1;
+    split = hanging(v, vset, vmask);
+    if (!split) nf = 3;
+  }
+  flags[i] = nf;
+  cnt[i] = split ? 2u : 1u;
+}
+
+// Copies leaf i, or writes its two children and adds the new vertex to both
+// vertex sets; true when the vertex is new.
+__device__ inline bool split_one(int64_t i, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
+                                 const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
+                                 const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids,
+                                 uint64_t* __restrict__ nverts, uint8_t* __restrict__ nflags, uint64_t* vset,
+                                 uint64_t vmask, uint64_t* nset, uint64_t nmask, uint32_t* __restrict__ work) {
   uint64_t id = ids[i];
   uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
   int64_t o = offs[i];
@@ -264,7 +318,7 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
     nflags[o] = flags[i];
 #pragma unroll
     for (int j = 0; j < 4; j++) nverts[4 * o + j] = v[j];
-    return;
+    return false;
   }
   int k = tag_of(id_depth(id));
   uint64_t a[4], b[4], z;
@@ -289,13 +343,31 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
   nids[o + 1] = 2 * id + 1;
   nflags[o] = 0;
   nflags[o + 1] = 0;
+  const int64_t r = o - i;  // splits before this leaf
+  work[2 * r] = (uint32_t)o;
+  work[2 * r + 1] = (uint32_t)(o + 1);
 #pragma unroll
   for (int j = 0; j < 4; j++) {
     nverts[4 * o + j] = a[j];
     nverts[4 * (o + 1) + j] = b[j];
   }
-  vset_insert(vset, vmask, z, vcount);
+  bool added = vset_add(vset, vmask, z);
+  vset_add(nset, nmask, z);
+  return added;
 }
+
+__global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
+                        const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
+                        const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids, uint64_t* __restrict__ nverts,
+                        uint8_t* __restrict__ nflags, uint64_t* vset, uint64_t vmask, uint32_t* vcount,
+                        uint64_t* nset, uint64_t nmask, uint32_t* __restrict__ work) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool added = false;
+  if (i < n)
+    added = split_one(i, ids, verts, flags, cnt, offs, nids, nverts, nflags, vset, vmask, nset, nmask, work);
+  count_new(added, vcount);
+}
+
 
 // ---------------------------------------------------------------- scan
 // Exclusive scan of n uint32 values, 1024 per block (256 threads x 4).
@@ -772,7 +844,11 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   }
   int64_t cur = 6;
   // vertex hash set
-  Buf vs, vs_old, cntb, offb, bsum;
+  Buf vs, vs_old, cntb, offb, bsum, ns, wk;  // ns: vertices made by the last split pass; wk: its new leaves
+  uint64_t nscap = 1024;
+  if (!ns.ensure(nscap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap, 256)), dim3(256), 0, st, ns.as<uint64_t>(), (int64_t)nscap,
+                     kEmptyKey);
   uint64_t vcap = 1 << 16;
   if (!vs.ensure(vcap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
   hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)vcap,
@@ -780,6 +856,13 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   hipLaunchKernelGGL(k_vset_seed, dim3(1), dim3(64), 0, st, A.verts.as<uint64_t>(), (int64_t)6, vs.as<uint64_t>(),
                      vcap - 1, d_vcount);
 
+  // the first worklist: the 6 roots
+  if (!wk.ensure(64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
+  {
+    uint32_t w0[6] = {0, 1, 2, 3, 4, 5};
+    TV_HIP(hipMemcpyAsync(wk.p, w0, sizeof(w0), hipMemcpyHostToDevice, st));
+  }
+  int64_t nwork = 6;
   uint32_t* hbuf = nullptr;
   TV_HIP(hipHostMalloc((void**)&hbuf, 16, hipHostMallocDefault));
   struct HostFree {
@@ -789,9 +872,12 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   int rounds = 0;
   for (;;) {
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
-    hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
-                       A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P, cc, wp,
-                       vs.as<uint64_t>(), vcap - 1);
+    hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
+                       A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
+                       nscap - 1);
+    hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
+                       A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P,
+                       cc, wp, vs.as<uint64_t>(), vcap - 1);
     if (scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scan");
     TV_HIP(hipMemcpyAsync(hbuf, d_total, 8, hipMemcpyDeviceToHost, st));
@@ -816,14 +902,24 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       vcap = ncap;
     }
     if (!B.ensure(total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+    if (!wk.ensure((size_t)splits * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
+    // the new-vertex set of this pass, at most half full
+    nscap = 1024;
+    while ((uint64_t)splits * 2 > nscap) nscap <<= 1;
+    if (!ns.ensure(nscap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap, 256)), dim3(256), 0, st, ns.as<uint64_t>(), (int64_t)nscap,
+                       kEmptyKey);
     hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
                        A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
                        B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
-                       vcap - 1, d_vcount);
+                       vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, wk.as<uint32_t>());
     A.swap_with(B);
     cur = total;
+    nwork = 2 * splits;
   }
   vs.release();
+  ns.release();
+  wk.release();
   cntb.release();
   offb.release();
   bsum.release();
