@@ -463,7 +463,7 @@ __global__ void k_keys(int64_t n, const uint64_t* __restrict__ ids, uint64_t* __
 
 // Root Kuhn tets: vertex 1 = S e_p0, vertex 2 = S (e_p0 + e_p1), over the
 // axis orders (0,1,2), (0,2,1), (1,0,2), (1,2,0), (2,0,1), (2,1,0).
-__device__ inline void root_verts(int r, int64_t v[4][3]) {
+__device__ inline void root_verts(int r, int32_t v[4][3]) {
   const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1};
 #pragma unroll
   for (int j = 0; j < 4; j++)
@@ -478,28 +478,17 @@ __device__ inline void root_verts(int r, int64_t v[4][3]) {
 __device__ inline int isgn(int64_t x) { return (x > 0) - (x < 0); }
 
 // Bisection step of the perturbed-point descent for a compile-time tag K:
-// the point is 3 * face centroid (q3) plus epsilon * outward normal.
+// the point is 3 * face centroid (q3, below 2^22) plus epsilon * outward
+// normal.
 template <int K>
-__device__ inline void descend_perturbed(int64_t v[4][3], uint64_t& h, const int64_t q3[3], const int nout[3]) {
-  constexpr int J1 = K == 1 ? 2 : 1, J2 = K == 3 ? 2 : 3;
-  int64_t z[3], a[3], b[3], nn[3];
+__device__ inline void descend_perturbed(int32_t v[4][3], uint64_t& h, const int32_t q3[3], const int nout[3]) {
+  int32_t z[3], u[3];
+  bisector<K>(v, z, u);
+  int32_t side = 0, pert = 0;
 #pragma unroll
   for (int i = 0; i < 3; i++) {
-    z[i] = (v[0][i] + v[K][i]) >> 1;
-    a[i] = v[J1][i] - z[i];
-    b[i] = v[J2][i] - z[i];
-  }
-  nn[0] = a[1] * b[2] - a[2] * b[1];
-  nn[1] = a[2] * b[0] - a[0] * b[2];
-  nn[2] = a[0] * b[1] - a[1] * b[0];
-  int64_t s0 = nn[0] * (v[0][0] - z[0]) + nn[1] * (v[0][1] - z[1]) + nn[2] * (v[0][2] - z[2]);
-  int o = s0 < 0 ? -1 : 1;
-  int64_t side = 0, pert = 0;
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    int u = isgn(nn[i]) * o;
-    side += u * (q3[i] - 3 * z[i]);
-    pert += u * nout[i];
+    side += __mul24(u[i], q3[i] - 3 * z[i]);
+    pert += __mul24(u[i], nout[i]);
   }
   bool first = side != 0 ? side > 0 : pert > 0;
   if (first) {
@@ -636,13 +625,13 @@ __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const ui
       r.nbr[f] = kBoundary;
       continue;
     }
-    int64_t w[4][3];
+    int32_t w[4][3], q3i[3] = {(int32_t)q3[0], (int32_t)q3[1], (int32_t)q3[2]};
     root_verts(root, w);
     uint64_t h = 8 + root;
     for (int d = 0; d < dmax; d += 3) {
-      descend_perturbed<3>(w, h, q3, un);
-      if (d + 1 < dmax) descend_perturbed<2>(w, h, q3, un);
-      if (d + 2 < dmax) descend_perturbed<1>(w, h, q3, un);
+      descend_perturbed<3>(w, h, q3i, un);
+      if (d + 1 < dmax) descend_perturbed<2>(w, h, q3i, un);
+      if (d + 2 < dmax) descend_perturbed<1>(w, h, q3i, un);
     }
     int64_t nb = search_keys(keys, n, h << (60 - dmax));
     // back face: the neighbour's vertex that is not on face f

@@ -153,25 +153,13 @@ struct Step {
 // ---------------------------------------------------------------- tet medium
 template <int K>
 __device__ inline void descend_point(int32_t v[4][3], uint64_t& h, const double P[3]) {
-  constexpr int J1 = K == 1 ? 2 : 1, J2 = K == 3 ? 2 : 3;
-  int32_t z[3];
-  int64_t a[3], b[3], nn[3];
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    z[i] = (v[0][i] + v[K][i]) >> 1;
-    a[i] = (int64_t)v[J1][i] - z[i];
-    b[i] = (int64_t)v[J2][i] - z[i];
-  }
-  nn[0] = a[1] * b[2] - a[2] * b[1];
-  nn[1] = a[2] * b[0] - a[0] * b[2];
-  nn[2] = a[0] * b[1] - a[1] * b[0];
-  int64_t s0 = nn[0] * (v[0][0] - z[0]) + nn[1] * (v[0][1] - z[1]) + nn[2] * (v[0][2] - z[2]);
+  int32_t z[3], u[3];
+  bisector<K>(v, z, u);
   double side = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; i++) {
-    int sg = (nn[i] > 0) - (nn[i] < 0);
-    if (s0 < 0) sg = -sg;
-    if (sg) side = side + (double)sg * (P[i] - (double)z[i]);
+    const double t = P[i] - (double)z[i];
+    if (u[i]) side = side + (u[i] > 0 ? t : -t);
   }
   if (side >= 0.0) {
 #pragma unroll
