@@ -303,17 +303,15 @@ __global__ void k_want(int64_t m, const uint32_t* __restrict__ work, const uint6
   cnt[i] = split ? 2u : 1u;
 }
 
-// Copies leaf i, or writes its two children and adds the new vertex to both
-// vertex sets; true when the vertex is new.
-__device__ inline bool split_one(int64_t i, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
-                                 const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
-                                 const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids,
-                                 uint64_t* __restrict__ nverts, uint8_t* __restrict__ nflags, uint64_t* vset,
-                                 uint64_t vmask, uint64_t* nset, uint64_t nmask, uint32_t* __restrict__ work) {
+// Copies leaf i to position o, or writes its two children there and adds
+// the new vertex to the vertex set (and to the new-vertex set when given);
+// true when the vertex is new.
+__device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_t* ids, const uint64_t* verts,
+                                 const uint8_t* flags, uint64_t* nids, uint64_t* nverts, uint8_t* nflags,
+                                 uint64_t* vset, uint64_t vmask, uint64_t* nset, uint64_t nmask, uint32_t* work) {
   uint64_t id = ids[i];
   uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
-  int64_t o = offs[i];
-  if (cnt[i] == 1u) {
+  if (!split) {
     nids[o] = id;
     nflags[o] = flags[i];
 #pragma unroll
@@ -352,7 +350,7 @@ __device__ inline bool split_one(int64_t i, const uint64_t* __restrict__ ids, co
     nverts[4 * (o + 1) + j] = b[j];
   }
   bool added = vset_add(vset, vmask, z);
-  vset_add(nset, nmask, z);
+  if (nset) vset_add(nset, nmask, z);
   return added;
 }
 
@@ -364,7 +362,8 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool added = false;
   if (i < n)
-    added = split_one(i, ids, verts, flags, cnt, offs, nids, nverts, nflags, vset, vmask, nset, nmask, work);
+    added = split_one(i, offs[i], cnt[i] != 1u, ids, verts, flags, nids, nverts, nflags, vset, vmask, nset, nmask,
+                      work);
   count_new(added, vcount);
 }
 
@@ -434,6 +433,141 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
   for (int q = 0; q < kScanItems; q++) {
     if (base + q < n) out[base + q] = ex;
     ex += v[q];
+  }
+}
+
+// ---------------------------------------------------------------- small grids
+// While the grid is small a round holds too little work to hide the cost of
+// its launches and of the host reading the leaf count back, so the first
+// rounds run in one cooperative launch (every block resident): each block
+// owns a contiguous chunk of the leaves, and a round is mark, grid barrier,
+// offsets from the per-block counts and split, grid barrier.  The kernel
+// stops when the grid is conforming and want-free, or once it holds more
+// than cap / 2 leaves (the next round could then exceed cap).  Marking
+// probes the whole vertex set (flag bit 1 is never set here), and the last
+// split leaves the list of its new leaves for the rounds that follow.
+constexpr uint32_t kBarrierSpins = 1u << 24;  // about a second of s_sleep per barrier
+constexpr int64_t kSmallCap = 1 << 21;         // leaves the cooperative rounds may reach
+
+struct SmallRounds {
+  uint64_t* ids[2];
+  uint64_t* verts[2];
+  uint8_t* flags[2];
+  uint32_t* cnt;    // per leaf: 1 or 2
+  uint32_t* bsum;   // per block: sum of cnt over its chunk
+  uint32_t* work;   // new leaves of the last split
+  uint64_t* vset;
+  uint64_t vmask;
+  uint32_t* vcount;
+  uint32_t* state;  // out: [0] leaves, [1] rounds, [2] splits of the last round, [3] converged;
+                    // [4] barrier arrivals (zero at launch), [5] nonzero: a barrier timed out
+  int64_t cur0, cap;
+};
+
+// Grid barrier number k (1, 2, ...): every block adds one arrival, then waits
+// until k * gridDim.x arrivals are in.  The wait is bounded; on time-out the
+// error word is set and every block leaves the kernel at its next check.
+__device__ inline bool grid_barrier(uint32_t* arrivals, uint32_t* err, uint32_t k, int* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(arrivals, 1u);
+    const uint32_t target = k * gridDim.x;
+    int ok = 1;
+    // relaxed polling (an acquiring load would invalidate this XCD's L2 on
+    // every poll, under the blocks still working); one fence after the wait
+    for (uint32_t spin = 0; __hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target;
+         spin++) {
+      if (spin >= kBarrierSpins) {
+        atomicOr(err, 1u);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+__global__ __launch_bounds__(256) void k_small_rounds(SmallRounds S, Pyramid P, CamCrit cc, WantParams wp) {
+  __shared__ uint32_t ws[kScanThreads / 64];
+  __shared__ int s_ok;
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  uint32_t nbar = 0, last = 0, rounds = 0, conv = 0;
+  int src = 0;
+  int64_t cur = S.cur0;
+  while (cur <= S.cap / 2) {
+    const int64_t chunk = ((cur + nb - 1) / nb + 255) / 256 * 256;
+    const int64_t lo = b * chunk, hi = min(cur, lo + chunk);
+    const uint64_t* ids = S.ids[src];
+    const uint64_t* verts = S.verts[src];
+    uint8_t* flags = S.flags[src];
+    // mark
+    uint32_t part = 0;
+    for (int64_t base = lo; base < hi; base += 256) {
+      const int64_t i = base + threadIdx.x;
+      if (i < hi) {
+        uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
+        const uint8_t fl = flags[i];
+        bool split = false;
+        if (!(fl & 1)) {
+          if (want(P, cc, wp, v, ids[i])) split = true;
+          else flags[i] = 1;
+        }
+        if (!split) split = hanging(v, S.vset, S.vmask);
+        S.cnt[i] = split ? 2u : 1u;
+        part += split ? 2u : 1u;
+      }
+    }
+    uint32_t btot;
+    block_exclusive(part, ws, &btot);
+    if (threadIdx.x == 0) S.bsum[b] = btot;
+    if (!grid_barrier(&S.state[4], &S.state[5], ++nbar, &s_ok)) return;
+    // output offset of this block and the new leaf count
+    uint32_t pre = 0, tot = 0;
+    for (int64_t k = threadIdx.x; k < nb; k += 256) {
+      const uint32_t x = S.bsum[k];
+      tot += x;
+      if (k < b) pre += x;
+    }
+    uint32_t bpre, btot2;
+    block_exclusive(pre, ws, &bpre);
+    block_exclusive(tot, ws, &btot2);
+    pre = bpre;
+    tot = btot2;
+    if ((int64_t)tot == cur) {
+      conv = 1;
+      break;
+    }
+    // split
+    uint32_t carry = pre;
+    for (int64_t base = lo; base < hi; base += 256) {
+      const int64_t i = base + threadIdx.x;
+      const uint32_t x = i < hi ? S.cnt[i] : 0u;
+      uint32_t t;
+      const uint32_t ex = block_exclusive(x, ws, &t);
+      bool added = false;
+      if (i < hi)
+        added = split_one(i, (int64_t)carry + ex, x != 1u, ids, verts, flags, S.ids[src ^ 1], S.verts[src ^ 1],
+                          S.flags[src ^ 1], S.vset, S.vmask, nullptr, 0, S.work);
+      count_new(added, S.vcount);
+      carry += t;
+    }
+    if (!grid_barrier(&S.state[4], &S.state[5], ++nbar, &s_ok)) return;
+    last = (uint32_t)(tot - cur);
+    cur = tot;
+    src ^= 1;
+    rounds++;
+  }
+  if (b == 0 && threadIdx.x == 0) {
+    S.state[0] = (uint32_t)cur;
+    S.state[1] = rounds;
+    S.state[2] = last;
+    S.state[3] = conv;
   }
 }
 
@@ -810,9 +944,22 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   wp.rand_seed = o.rand_seed;
   wp.rand_thresh = o.rand_thresh;
 
+  // the cooperative launch of the first rounds, where the device supports it
+  int coop = 0, ncu = 0, occ = 0, dev = 0;
+  TV_HIP(hipGetDevice(&dev));
+  TV_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  TV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  TV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_small_rounds), 256, 0));
+  const int64_t small_cap = std::min<int64_t>(kSmallCap, o.max_tets);
+  const bool small = coop && occ > 0 && ncu > 0 && small_cap >= 12;
+  // a quarter of the CUs: the rounds are small, and every block adds an
+  // arrival to each grid barrier
+  const int small_blocks = std::max(1, ncu / 4);
+
   // roots
   Leaves A, B;
-  if (!A.ensure(1 << 16) || !B.ensure(1 << 16)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+  const int64_t lcap = std::max<int64_t>(1 << 16, small ? small_cap : 0);
+  if (!A.ensure(lcap) || !B.ensure(lcap)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
   {
     uint64_t hid[6], hv[24];
     const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1};
@@ -838,7 +985,10 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   if (!ns.ensure(nscap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
   hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap, 256)), dim3(256), 0, st, ns.as<uint64_t>(), (int64_t)nscap,
                      kEmptyKey);
+  // capacities are even powers of two and grow by factors of 4, so the
+  // sizes the set passes through do not depend on where it started
   uint64_t vcap = 1 << 16;
+  while (small && vcap < 4 * (uint64_t)small_cap) vcap <<= 2;  // stays at most half full in the small rounds
   if (!vs.ensure(vcap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
   hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)vcap,
                      kEmptyKey);
@@ -846,20 +996,52 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
                      vcap - 1, d_vcount);
 
   // the first worklist: the 6 roots
-  if (!wk.ensure(64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
+  if (!wk.ensure(small ? small_cap * 4 : 64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
   {
     uint32_t w0[6] = {0, 1, 2, 3, 4, 5};
     TV_HIP(hipMemcpyAsync(wk.p, w0, sizeof(w0), hipMemcpyHostToDevice, st));
   }
   int64_t nwork = 6;
   uint32_t* hbuf = nullptr;
-  TV_HIP(hipHostMalloc((void**)&hbuf, 16, hipHostMallocDefault));
+  TV_HIP(hipHostMalloc((void**)&hbuf, 64, hipHostMallocDefault));
   struct HostFree {
     uint32_t* p;
     ~HostFree() { if (p) (void)hipHostFree(p); }
   } hf{hbuf};
   int rounds = 0;
-  for (;;) {
+  bool done = false;
+  if (small) {
+    if (!cntb.ensure(small_cap * 4) || !bsum.ensure((size_t)small_blocks * 4))
+      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
+    SmallRounds S;
+    S.ids[0] = A.ids.as<uint64_t>();
+    S.ids[1] = B.ids.as<uint64_t>();
+    S.verts[0] = A.verts.as<uint64_t>();
+    S.verts[1] = B.verts.as<uint64_t>();
+    S.flags[0] = A.flags.as<uint8_t>();
+    S.flags[1] = B.flags.as<uint8_t>();
+    S.cnt = cntb.as<uint32_t>();
+    S.bsum = bsum.as<uint32_t>();
+    S.work = wk.as<uint32_t>();
+    S.vset = vs.as<uint64_t>();
+    S.vmask = vcap - 1;
+    S.vcount = d_vcount;
+    S.state = misc.as<uint32_t>() + 8;
+    S.cur0 = cur;
+    S.cap = small_cap;
+    void* args[] = {&S, &P, &cc, &wp};
+    TV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_small_rounds), dim3(small_blocks), dim3(256),
+                                      args, 0, st));
+    TV_HIP(hipMemcpyAsync(hbuf + 4, S.state, 24, hipMemcpyDeviceToHost, st));
+    TV_HIP(hipStreamSynchronize(st));
+    if (hbuf[9]) return fail(TET_ERR_INTERNAL, "leb_build: grid barrier of the small rounds timed out");
+    cur = hbuf[4];
+    rounds = (int)hbuf[5];
+    nwork = 2 * (int64_t)hbuf[6];
+    done = hbuf[7] != 0;
+    if (rounds & 1) A.swap_with(B);
+  }
+  while (!done) {
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
     hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
                        A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
@@ -879,7 +1061,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     int64_t splits = total - cur;
     if ((vcount + (uint64_t)splits) * 2 > vcap) {  // keep the vertex set at most half full
       uint64_t ncap = vcap;
-      while ((vcount + (uint64_t)splits) * 4 > ncap) ncap <<= 1;
+      while ((vcount + (uint64_t)splits) * 4 > ncap) ncap <<= 2;
       vs.swap_with(vs_old);
       if (!vs.ensure(ncap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
       hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(ncap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)ncap,
