@@ -269,16 +269,50 @@ __device__ inline bool hanging(const uint64_t v[4], const uint64_t* __restrict__
   return hit;
 }
 
+// Cells of a 64^3 grid over the cube that received a vertex in the last
+// split pass, one bit per cell, 0 = received (the map is cleared to all
+// ones with the new-vertex set).  32 KB: it stays in the L1 caches.  An edge
+// midpoint lies in the tet's bounding box, so a leaf whose box touches no
+// marked cell cannot have gained a hanging vertex.
+constexpr int kCellShift = kLatBits - 6;
+constexpr int kCellWords = (64 * 64 * 64) / 32;
+
+__device__ inline int cell_of(int32_t c) { return min(c >> kCellShift, 63); }
+
+__device__ inline void cell_mark(uint32_t* cells, uint64_t z) {
+  const int x = cell_of(vx(z)), y = cell_of(vy(z)), w = cell_of(vz(z));
+  const int idx = (w * 64 + y) * 64 + x;
+  atomicAnd(&cells[idx >> 5], ~(1u << (idx & 31)));
+}
+
+// True when the box of v touches a marked cell (or spans more than 64 cells).
+__device__ inline bool cells_touched(const uint32_t* __restrict__ cells, const uint64_t v[4]) {
+  int32_t lo[3], hi[3];
+  tet_box(v, lo, hi);
+  const int x0 = cell_of(lo[0]), x1 = cell_of(hi[0]), y0 = cell_of(lo[1]), y1 = cell_of(hi[1]);
+  const int z0 = cell_of(lo[2]), z1 = cell_of(hi[2]);
+  if ((x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1) > 64) return true;
+  for (int z = z0; z <= z1; z++)
+    for (int y = y0; y <= y1; y++)
+      for (int x = x0; x <= x1; x++) {
+        const int idx = (z * 64 + y) * 64 + x;
+        if (!((cells[idx >> 5] >> (idx & 31)) & 1u)) return true;
+      }
+  return false;
+}
+
 // Leaves whose want predicate is settled: split only when forced.
 __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags,
                        uint32_t* __restrict__ cnt, const uint64_t* __restrict__ vset, uint64_t vmask,
-                       const uint64_t* __restrict__ nset, uint64_t nmask) {
+                       const uint64_t* __restrict__ nset, uint64_t nmask, const uint32_t* __restrict__ cells) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint8_t fl = flags[i];
   if (!(fl & 1)) return;  // a new leaf: k_want decides it
   uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
-  bool split = (fl & 2) ? hanging(v, nset, nmask) : hanging(v, vset, vmask);
+  bool split;
+  if (fl & 2) split = cells_touched(cells, v) && hanging(v, nset, nmask);
+  else split = hanging(v, vset, vmask);
   if (!split && !(fl & 2)) flags[i] = fl | 2;
   cnt[i] = split ? 2u : 1u;
 }
@@ -308,7 +342,8 @@ __global__ void k_want(int64_t m, const uint32_t* __restrict__ work, const uint6
 // true when the vertex is new.
 __device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_t* ids, const uint64_t* verts,
                                  const uint8_t* flags, uint64_t* nids, uint64_t* nverts, uint8_t* nflags,
-                                 uint64_t* vset, uint64_t vmask, uint64_t* nset, uint64_t nmask, uint32_t* work) {
+                                 uint64_t* vset, uint64_t vmask, uint64_t* nset, uint64_t nmask, uint32_t* cells,
+                                 uint32_t* work) {
   uint64_t id = ids[i];
   uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
   if (!split) {
@@ -350,7 +385,10 @@ __device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_
     nverts[4 * (o + 1) + j] = b[j];
   }
   bool added = vset_add(vset, vmask, z);
-  if (nset) vset_add(nset, nmask, z);
+  if (nset && added) {  // only vertices new to the mesh can hang on a checked leaf
+    vset_add(nset, nmask, z);
+    cell_mark(cells, z);
+  }
   return added;
 }
 
@@ -358,12 +396,12 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
                         const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
                         const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids, uint64_t* __restrict__ nverts,
                         uint8_t* __restrict__ nflags, uint64_t* vset, uint64_t vmask, uint32_t* vcount,
-                        uint64_t* nset, uint64_t nmask, uint32_t* __restrict__ work) {
+                        uint64_t* nset, uint64_t nmask, uint32_t* cells, uint32_t* __restrict__ work) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool added = false;
   if (i < n)
     added = split_one(i, offs[i], cnt[i] != 1u, ids, verts, flags, nids, nverts, nflags, vset, vmask, nset, nmask,
-                      work);
+                      cells, work);
   count_new(added, vcount);
 }
 
@@ -553,7 +591,7 @@ __global__ __launch_bounds__(256) void k_small_rounds(SmallRounds S, Pyramid P, 
       bool added = false;
       if (i < hi)
         added = split_one(i, (int64_t)carry + ex, x != 1u, ids, verts, flags, S.ids[src ^ 1], S.verts[src ^ 1],
-                          S.flags[src ^ 1], S.vset, S.vmask, nullptr, 0, S.work);
+                          S.flags[src ^ 1], S.vset, S.vmask, nullptr, 0, nullptr, S.work);
       count_new(added, S.vcount);
       carry += t;
     }
@@ -981,9 +1019,12 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   int64_t cur = 6;
   // vertex hash set
   Buf vs, vs_old, cntb, offb, bsum, ns, wk;  // ns: vertices made by the last split pass; wk: its new leaves
+  // ns: the new-vertex set (nscap keys) followed by the cell map, both
+  // cleared to all ones by one fill
   uint64_t nscap = 1024;
-  if (!ns.ensure(nscap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
-  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap, 256)), dim3(256), 0, st, ns.as<uint64_t>(), (int64_t)nscap,
+  if (!ns.ensure(nscap * 8 + kCellWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kCellWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
+                     (int64_t)(nscap + kCellWords / 2),
                      kEmptyKey);
   // capacities are even powers of two and grow by factors of 4, so the
   // sizes the set passes through do not depend on where it started
@@ -1045,7 +1086,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
     hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
                        A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
-                       nscap - 1);
+                       nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap));
     hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
                        A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P,
                        cc, wp, vs.as<uint64_t>(), vcap - 1);
@@ -1077,13 +1118,14 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     // the new-vertex set of this pass, at most half full
     nscap = 1024;
     while ((uint64_t)splits * 2 > nscap) nscap <<= 1;
-    if (!ns.ensure(nscap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
-    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap, 256)), dim3(256), 0, st, ns.as<uint64_t>(), (int64_t)nscap,
+    if (!ns.ensure(nscap * 8 + kCellWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kCellWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
+                       (int64_t)(nscap + kCellWords / 2),
                        kEmptyKey);
     hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
                        A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
                        B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
-                       vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, wk.as<uint32_t>());
+                       vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, (uint32_t*)(ns.as<uint64_t>() + nscap), wk.as<uint32_t>());
     A.swap_with(B);
     cur = total;
     nwork = 2 * splits;
