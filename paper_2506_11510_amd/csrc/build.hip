@@ -304,37 +304,71 @@ __device__ inline bool cells_touched(const uint32_t* __restrict__ cells, const u
 // Leaves whose want predicate is settled: split only when forced.
 __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags,
                        uint32_t* __restrict__ cnt, const uint64_t* __restrict__ vset, uint64_t vmask,
-                       const uint64_t* __restrict__ nset, uint64_t nmask, const uint32_t* __restrict__ cells) {
+                       const uint64_t* __restrict__ nset, uint64_t nmask, const uint32_t* __restrict__ cells,
+                       uint32_t* splitc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint8_t fl = flags[i];
-  if (!(fl & 1)) return;  // a new leaf: k_want decides it
-  uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
-  bool split;
-  if (fl & 2) split = cells_touched(cells, v) && hanging(v, nset, nmask);
-  else split = hanging(v, vset, vmask);
-  if (!split && !(fl & 2)) flags[i] = fl | 2;
-  cnt[i] = split ? 2u : 1u;
+  bool split = false;
+  if (i < n) {
+    const uint8_t fl = flags[i];
+    if (fl & 1) {  // new leaves (flag 0) are k_want's
+      uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
+      if (fl & 2) split = cells_touched(cells, v) && hanging(v, nset, nmask);
+      else split = hanging(v, vset, vmask);
+      if (!split && !(fl & 2)) flags[i] = fl | 2;
+      cnt[i] = split ? 2u : 1u;
+    }
+  }
+  if (splitc) count_new(split, splitc);  // running count of splits (tail rounds)
 }
 
 // The leaves made by the last split pass (a dense list, so the want
 // predicate's FP64 work runs on full waves): wanted, or forced.
 __global__ void k_want(int64_t m, const uint32_t* __restrict__ work, const uint64_t* __restrict__ ids,
                        const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags, uint32_t* __restrict__ cnt,
-                       Pyramid P, CamCrit cc, WantParams wp, const uint64_t* __restrict__ vset, uint64_t vmask) {
+                       Pyramid P, CamCrit cc, WantParams wp, const uint64_t* __restrict__ vset, uint64_t vmask,
+                       uint32_t* splitc) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  const uint32_t i = work[j];
-  uint64_t v[4] = {verts[4 * (size_t)i], verts[4 * (size_t)i + 1], verts[4 * (size_t)i + 2], verts[4 * (size_t)i + 3]};
-  bool split = want(P, cc, wp, v, ids[i]);
-  uint8_t nf = 0;
-  if (!split) {
-    nf = 1;
-    split = hanging(v, vset, vmask);
-    if (!split) nf = 3;
+  bool split = false;
+  if (j < m) {
+    const uint32_t i = work[j];
+    uint64_t v[4] = {verts[4 * (size_t)i], verts[4 * (size_t)i + 1], verts[4 * (size_t)i + 2],
+                     verts[4 * (size_t)i + 3]};
+    split = want(P, cc, wp, v, ids[i]);
+    uint8_t nf = 0;
+    if (!split) {
+      nf = 1;
+      split = hanging(v, vset, vmask);
+      if (!split) nf = 3;
+    }
+    flags[i] = nf;
+    cnt[i] = split ? 2u : 1u;
   }
-  flags[i] = nf;
-  cnt[i] = split ? 2u : 1u;
+  if (splitc) count_new(split, splitc);
+}
+
+// Maubach children of the tet (id, v): the first child replaces vertex x_k
+// (k = tag) by the midpoint z of (x0, x_k), the second is (x1..x_k, z,
+// x_{k+1}..x3).  Returns z.
+__device__ inline uint64_t children(uint64_t id, const uint64_t v[4], uint64_t a[4], uint64_t b[4]) {
+  uint64_t z;
+  switch (tag_of(id_depth(id))) {
+    case 1:
+      z = vmid(v[0], v[1]);
+      a[0] = v[0]; a[1] = z; a[2] = v[2]; a[3] = v[3];
+      b[0] = v[1]; b[1] = z; b[2] = v[2]; b[3] = v[3];
+      break;
+    case 2:
+      z = vmid(v[0], v[2]);
+      a[0] = v[0]; a[1] = v[1]; a[2] = z; a[3] = v[3];
+      b[0] = v[1]; b[1] = v[2]; b[2] = z; b[3] = v[3];
+      break;
+    default:
+      z = vmid(v[0], v[3]);
+      a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = z;
+      b[0] = v[1]; b[1] = v[2]; b[2] = v[3]; b[3] = z;
+      break;
+  }
+  return z;
 }
 
 // Copies leaf i to position o, or writes its two children there and adds
@@ -353,25 +387,8 @@ __device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_
     for (int j = 0; j < 4; j++) nverts[4 * o + j] = v[j];
     return false;
   }
-  int k = tag_of(id_depth(id));
-  uint64_t a[4], b[4], z;
-  switch (k) {  // first child: x_k -> z; second child: (x1..x_k, z, x_{k+1}..x3)
-    case 1:
-      z = vmid(v[0], v[1]);
-      a[0] = v[0]; a[1] = z; a[2] = v[2]; a[3] = v[3];
-      b[0] = v[1]; b[1] = z; b[2] = v[2]; b[3] = v[3];
-      break;
-    case 2:
-      z = vmid(v[0], v[2]);
-      a[0] = v[0]; a[1] = v[1]; a[2] = z; a[3] = v[3];
-      b[0] = v[1]; b[1] = v[2]; b[2] = z; b[3] = v[3];
-      break;
-    default:
-      z = vmid(v[0], v[3]);
-      a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = z;
-      b[0] = v[1]; b[1] = v[2]; b[2] = v[3]; b[3] = z;
-      break;
-  }
+  uint64_t a[4], b[4];
+  const uint64_t z = children(id, v, a, b);
   nids[o] = 2 * id;
   nids[o + 1] = 2 * id + 1;
   nflags[o] = 0;
@@ -405,6 +422,107 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
   count_new(added, vcount);
 }
 
+
+// Tail rounds, where few leaves split: no compaction.  Child 0 replaces its
+// parent in place (its depth-first key is the parent's, so the leaves below
+// nmain stay in key order), child 1 is appended at nmain + its slot, and
+// anc[slot] names the leaf below nmain it descends from.  Slots are taken
+// from the running counter slotc (wave-aggregated), so appended leaves are
+// in no particular order until k_merge.
+__global__ void k_split_append(int64_t n, int64_t nmain, uint64_t* __restrict__ ids, uint64_t* __restrict__ verts,
+                               uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
+                               uint32_t* __restrict__ anc, uint32_t* slotc, uint64_t* vset, uint64_t vmask,
+                               uint32_t* vcount, uint64_t* nset, uint64_t nmask, uint32_t* cells,
+                               uint32_t* __restrict__ work) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool split = i < n && cnt[i] == 2u;
+  const unsigned long long m = __ballot(split);
+  const int lane = __lane_id();
+  uint32_t base = 0;
+  if (m) {
+    const int leader = (int)__builtin_ctzll(m);
+    if (lane == leader) base = atomicAdd(slotc, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+  }
+  bool added = false;
+  if (split) {
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t o = nmain + base + (uint32_t)__popcll(m & below);
+    const uint64_t id = ids[i];
+    uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]}, a[4], b[4];
+    const uint64_t z = children(id, v, a, b);
+    ids[i] = 2 * id;
+    ids[o] = 2 * id + 1;
+    flags[i] = 0;
+    flags[o] = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      verts[4 * i + j] = a[j];
+      verts[4 * o + j] = b[j];
+    }
+    anc[o - nmain] = i < nmain ? (uint32_t)i : anc[i - nmain];
+    const int64_t r = o - n;  // this round's slot
+    work[2 * r] = (uint32_t)i;
+    work[2 * r + 1] = (uint32_t)o;
+    added = vset_add(vset, vmask, z);
+    if (added) {
+      vset_add(nset, nmask, z);
+      cell_mark(cells, z);
+    }
+  }
+  count_new(added, vcount);
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Merge of the appended leaves: g[i] = 1 + the number of appended leaves
+// descending from leaf i (g starts at 1).
+__global__ void k_group_count(int64_t m, const uint32_t* __restrict__ anc, uint32_t* g) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) atomicAdd(&g[anc[j]], 1u);
+}
+
+// With pos = exclusive scan of g, leaf i goes to pos[i] and its appended
+// descendants fill pos[i] + 1 .. pos[i] + g[i] - 1; slots lists them there
+// in arrival order (fill starts at 0).
+__global__ void k_group_slots(int64_t m, const uint32_t* __restrict__ anc, const uint32_t* __restrict__ pos,
+                              uint32_t* fill, uint32_t* __restrict__ slots) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint32_t i = anc[j];
+  slots[pos[i] + 1 + atomicAdd(&fill[i], 1u)] = (uint32_t)j;
+}
+
+__device__ inline uint64_t dfs_key(uint64_t id) { return id << (60 - id_depth(id)); }
+
+// Writes the leaves in depth-first order: leaf i < nmain at pos[i], then its
+// appended descendants ranked by key (they are leaves of one subtree, so
+// their keys are distinct).
+__global__ void k_merge(int64_t nmain, int64_t m, int64_t total, const uint64_t* __restrict__ ids,
+                        const uint64_t* __restrict__ verts, const uint32_t* __restrict__ anc,
+                        const uint32_t* __restrict__ pos, const uint32_t* __restrict__ slots,
+                        uint64_t* __restrict__ out_ids, uint64_t* __restrict__ out_verts) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nmain + m) return;
+  int64_t o;
+  if (t < nmain) {
+    o = pos[t];
+  } else {
+    const int64_t j = t - nmain;
+    const uint32_t i = anc[j];
+    const int64_t first = (int64_t)pos[i] + 1, end = i + 1 < nmain ? (int64_t)pos[i + 1] : total;
+    const uint64_t key = dfs_key(ids[t]);
+    int64_t r = 0;
+    for (int64_t k = first; k < end; k++) r += dfs_key(ids[nmain + slots[k]]) < key;
+    o = first + r;
+  }
+  out_ids[o] = ids[t];
+#pragma unroll
+  for (int q = 0; q < 4; q++) out_verts[4 * o + q] = verts[4 * t + q];
+}
 
 // ---------------------------------------------------------------- scan
 // Exclusive scan of n uint32 values, 1024 per block (256 threads x 4).
@@ -486,6 +604,7 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
 // split leaves the list of its new leaves for the rounds that follow.
 constexpr uint32_t kBarrierSpins = 1u << 24;  // about a second of s_sleep per barrier
 constexpr int64_t kSmallCap = 1 << 21;         // leaves the cooperative rounds may reach
+constexpr int64_t kAppendRatio = 64;           // tail rounds: fewer than leaves / 64 splits
 
 struct SmallRounds {
   uint64_t* ids[2];
@@ -892,7 +1011,33 @@ struct Leaves {
     cap = c;
     return true;
   }
+  // Room for n leaves, keeping the first `keep` (copied on the stream, which
+  // is drained before the old arrays return to the pool).
+  bool grow_keep(int64_t n, int64_t keep, hipStream_t st) {
+    if (n <= cap) return true;
+    Leaves t;
+    if (!t.ensure(std::max<int64_t>(n, cap + cap / 4))) return false;
+    if (keep > 0 && (hipMemcpyAsync(t.ids.p, ids.p, keep * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                     hipMemcpyAsync(t.verts.p, verts.p, keep * 32, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                     hipMemcpyAsync(t.flags.p, flags.p, keep, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                     hipStreamSynchronize(st) != hipSuccess))
+      return false;
+    swap_with(t);
+    return true;
+  }
 };
+
+// A device buffer grown keeping its first `keep` bytes.
+static bool grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t st) {
+  if (bytes <= b.bytes) return true;
+  Buf t;
+  if (!t.ensure(std::max(bytes, b.bytes + b.bytes / 4))) return false;
+  if (keep > 0 && (hipMemcpyAsync(t.p, b.p, keep, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                   hipStreamSynchronize(st) != hipSuccess))
+    return false;
+  b.swap_with(t);
+  return true;
+}
 }  // namespace
 
 static int64_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, Buf& bsum, uint32_t* d_total, hipStream_t st) {
@@ -945,6 +1090,8 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   int* d_flag = misc.as<int>();
   uint32_t* d_total = misc.as<uint32_t>() + 4;
   uint32_t* d_vcount = misc.as<uint32_t>() + 5;
+  uint32_t* d_splitc = misc.as<uint32_t>() + 6;  // running count of marked splits
+  uint32_t* d_slotc = misc.as<uint32_t>() + 7;   // running count of appended leaves
   hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d_dens, nvox, d_flag);
 
   // pyramid
@@ -1051,6 +1198,9 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   } hf{hbuf};
   int rounds = 0;
   bool done = false;
+  int64_t nmain = -1;  // >= 0 once the tail rounds append (leaves below nmain stay in key order)
+  uint32_t splitc = 0;  // last value read of the running split count
+  Buf anc;             // leaf below nmain each appended leaf descends from
   if (small) {
     if (!cntb.ensure(small_cap * 4) || !bsum.ensure((size_t)small_blocks * 4))
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
@@ -1086,16 +1236,17 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
     hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
                        A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
-                       nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap));
+                       nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap), nmain < 0 ? nullptr : d_splitc);
     hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
                        A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P,
-                       cc, wp, vs.as<uint64_t>(), vcap - 1);
-    if (scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
+                       cc, wp, vs.as<uint64_t>(), vcap - 1, nmain < 0 ? nullptr : d_splitc);
+    if (nmain < 0 && scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scan");
-    TV_HIP(hipMemcpyAsync(hbuf, d_total, 8, hipMemcpyDeviceToHost, st));
+    TV_HIP(hipMemcpyAsync(hbuf, d_total, 12, hipMemcpyDeviceToHost, st));
     TV_HIP(hipStreamSynchronize(st));
-    int64_t total = hbuf[0];
-    uint64_t vcount = hbuf[1];
+    const int64_t total = nmain < 0 ? (int64_t)hbuf[0] : cur + (int64_t)(hbuf[2] - splitc);
+    const uint64_t vcount = hbuf[1];
+    splitc = hbuf[2];
     if (total == cur) break;
     rounds++;
     if (total > o.max_tets) return fail(TET_ERR_CAPACITY, "leb_build: grid exceeds max_tets");
@@ -1113,7 +1264,21 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       vs_old.release();
       vcap = ncap;
     }
-    if (!B.ensure(total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+    // the tail: few splits, appended instead of compacted
+    if (nmain < 0 && splits * kAppendRatio < cur) {
+      nmain = cur;
+      B.ids.release();
+      B.verts.release();
+      B.flags.release();
+      B.cap = 0;
+      TV_HIP(hipMemsetAsync(d_slotc, 0, 4, st));
+    }
+    if (nmain < 0) {
+      if (!B.ensure(total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+    } else if (!A.grow_keep(std::max<int64_t>(total, cur + cur / 16), cur, st) ||
+               !grow_keep(anc, (size_t)(A.cap - nmain) * 4, (size_t)(cur - nmain) * 4, st)) {
+      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+    }
     if (!wk.ensure((size_t)splits * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
     // the new-vertex set of this pass, at most half full
     nscap = 1024;
@@ -1122,20 +1287,25 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kCellWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
                        (int64_t)(nscap + kCellWords / 2),
                        kEmptyKey);
-    hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
-                       A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
-                       B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
-                       vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, (uint32_t*)(ns.as<uint64_t>() + nscap), wk.as<uint32_t>());
-    A.swap_with(B);
+    uint32_t* cells = (uint32_t*)(ns.as<uint64_t>() + nscap);
+    if (nmain < 0) {
+      hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
+                         A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
+                         B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
+                         vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, cells, wk.as<uint32_t>());
+      A.swap_with(B);
+    } else {
+      hipLaunchKernelGGL(k_split_append, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, nmain,
+                         A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(),
+                         anc.as<uint32_t>(), d_slotc, vs.as<uint64_t>(), vcap - 1, d_vcount, ns.as<uint64_t>(),
+                         nscap - 1, cells, wk.as<uint32_t>());
+    }
     cur = total;
     nwork = 2 * splits;
   }
   vs.release();
   ns.release();
   wk.release();
-  cntb.release();
-  offb.release();
-  bsum.release();
   B.ids.release();
   B.verts.release();
   B.flags.release();
@@ -1155,8 +1325,38 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     tet_grid_free(g);
     return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: grid arrays");
   }
-  hipError_t he = hipMemcpyAsync(g->ids, A.ids.p, cur * 8, hipMemcpyDeviceToDevice, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(g->verts, A.verts.p, cur * 32, hipMemcpyDeviceToDevice, st);
+  hipError_t he = hipSuccess;
+  if (nmain < 0) {
+    he = hipMemcpyAsync(g->ids, A.ids.p, cur * 8, hipMemcpyDeviceToDevice, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(g->verts, A.verts.p, cur * 32, hipMemcpyDeviceToDevice, st);
+  } else {
+    // depth-first order of the main part and the appended leaves
+    const int64_t m = cur - nmain;
+    Buf slots;
+    if (!cntb.ensure(nmain * 4) || !offb.ensure(nmain * 4) || !slots.ensure(cur * 4)) {
+      tet_grid_free(g);
+      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: merge");
+    }
+    uint32_t* gc = cntb.as<uint32_t>();
+    uint32_t* pos = offb.as<uint32_t>();
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(nmain, 256)), dim3(256), 0, st, gc, nmain, 1u);
+    hipLaunchKernelGGL(k_group_count, dim3(nblocks(m, 256)), dim3(256), 0, st, m, anc.as<uint32_t>(), gc);
+    if (scan_u32(gc, nmain, pos, bsum, d_total, st)) {
+      tet_grid_free(g);
+      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: merge");
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(nmain, 256)), dim3(256), 0, st, gc, nmain, 0u);
+    hipLaunchKernelGGL(k_group_slots, dim3(nblocks(m, 256)), dim3(256), 0, st, m, anc.as<uint32_t>(), pos, gc,
+                       slots.as<uint32_t>());
+    hipLaunchKernelGGL(k_merge, dim3(nblocks(cur, 256)), dim3(256), 0, st, nmain, m, cur, A.ids.as<uint64_t>(),
+                       A.verts.as<uint64_t>(), anc.as<uint32_t>(), pos, slots.as<uint32_t>(), g->ids, g->verts);
+    he = hipGetLastError();
+    if (he == hipSuccess) he = hipStreamSynchronize(st);  // before the scratch returns to the pool
+  }
+  cntb.release();
+  offb.release();
+  bsum.release();
+  anc.release();
   if (he == hipSuccess) {
     hipLaunchKernelGGL(k_keys, dim3(nblocks(cur, 1024)), dim3(1024), 0, st, cur, g->ids, g->keys, d_flag + 1);
     he = hipMemcpyAsync(&flag, d_flag + 1, 4, hipMemcpyDeviceToHost, st);

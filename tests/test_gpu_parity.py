@@ -71,6 +71,28 @@ def test_build_criteria_bitexact(tv, maj, tau, tgt):
     assert_grids_equal(g.export(), o.export(), "criteria")
 
 
+RANDOM_706K = dict(want_mode=2, max_depth=17, rand_seed=3, rand_thresh=22000)  # 706,206 tets
+
+
+@pytest.mark.parametrize("max_tets", [706206, 1 << 22])
+def test_build_phases_bitexact(tv, tiny_density, max_tets):
+    """The build's three kinds of rounds meet: with max_tets at the final
+    size the rounds in one cooperative launch stop at half of it and the
+    compacting, then appending (tail) rounds finish the grid; with a large
+    max_tets the cooperative launch builds it all.  Both bit-exact, and one
+    tet fewer is a capacity error."""
+    say(f"case build phases max_tets {max_tets}")
+    b = dict(TINY["build"], **RANDOM_706K)
+    o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
+    g = gpu_build(tv, tiny_density, 64, TINY["camera"], dict(b, max_tets=max_tets))
+    assert g.info()["num_tets"] == 706206
+    assert_grids_equal(g.export(), o.export(), f"phases {max_tets}")
+    if max_tets == 706206:
+        with pytest.raises(tv.TetError) as e:
+            gpu_build(tv, tiny_density, 64, TINY["camera"], dict(b, max_tets=706205))
+        assert e.value.status == -3
+
+
 def test_locate_matches_oracle(tv, tiny_density):
     say("case locate")
     b = dict(TINY["build"], want_mode=2, max_depth=15, rand_seed=7, rand_thresh=40000)
