@@ -301,24 +301,38 @@ __device__ inline bool cells_touched(const uint32_t* __restrict__ cells, const u
   return false;
 }
 
+// Tail rounds: every leaf that splits is listed.  The list positions come
+// from the running split count (one atomic per wave); list0 is its value at
+// the start of the round.
+__device__ inline void list_split(bool split, uint32_t i, uint32_t* splitc, uint32_t list0, uint32_t* slist) {
+  const unsigned long long m = __ballot(split);
+  if (!m) return;
+  const int lane = __lane_id(), leader = (int)__builtin_ctzll(m);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(splitc, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (split) slist[base - list0 + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = i;
+}
+
 // Leaves whose want predicate is settled: split only when forced.
 __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags,
                        uint32_t* __restrict__ cnt, const uint64_t* __restrict__ vset, uint64_t vmask,
                        const uint64_t* __restrict__ nset, uint64_t nmask, const uint32_t* __restrict__ cells,
-                       uint32_t* splitc) {
+                       uint32_t* splitc, uint32_t list0, uint32_t* __restrict__ slist) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool split = false;
   if (i < n) {
+    // both loads issued together (nearly every leaf has a settled predicate)
     const uint8_t fl = flags[i];
+    uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
     if (fl & 1) {  // new leaves (flag 0) are k_want's
-      uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
       if (fl & 2) split = cells_touched(cells, v) && hanging(v, nset, nmask);
       else split = hanging(v, vset, vmask);
       if (!split && !(fl & 2)) flags[i] = fl | 2;
-      cnt[i] = split ? 2u : 1u;
+      if (!slist) cnt[i] = split ? 2u : 1u;
     }
   }
-  if (splitc) count_new(split, splitc);  // running count of splits (tail rounds)
+  if (slist) list_split(split, (uint32_t)i, splitc, list0, slist);
 }
 
 // The leaves made by the last split pass (a dense list, so the want
@@ -326,11 +340,12 @@ __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* _
 __global__ void k_want(int64_t m, const uint32_t* __restrict__ work, const uint64_t* __restrict__ ids,
                        const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags, uint32_t* __restrict__ cnt,
                        Pyramid P, CamCrit cc, WantParams wp, const uint64_t* __restrict__ vset, uint64_t vmask,
-                       uint32_t* splitc) {
+                       uint32_t* splitc, uint32_t list0, uint32_t* __restrict__ slist) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool split = false;
+  uint32_t i = 0;
   if (j < m) {
-    const uint32_t i = work[j];
+    i = work[j];
     uint64_t v[4] = {verts[4 * (size_t)i], verts[4 * (size_t)i + 1], verts[4 * (size_t)i + 2],
                      verts[4 * (size_t)i + 3]};
     split = want(P, cc, wp, v, ids[i]);
@@ -341,9 +356,9 @@ __global__ void k_want(int64_t m, const uint32_t* __restrict__ work, const uint6
       if (!split) nf = 3;
     }
     flags[i] = nf;
-    cnt[i] = split ? 2u : 1u;
+    if (!slist) cnt[i] = split ? 2u : 1u;
   }
-  if (splitc) count_new(split, splitc);
+  if (slist) list_split(split, i, splitc, list0, slist);
 }
 
 // Maubach children of the tet (id, v): the first child replaces vertex x_k
@@ -425,29 +440,18 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
 
 // Tail rounds, where few leaves split: no compaction.  Child 0 replaces its
 // parent in place (its depth-first key is the parent's, so the leaves below
-// nmain stay in key order), child 1 is appended at nmain + its slot, and
-// anc[slot] names the leaf below nmain it descends from.  Slots are taken
-// from the running counter slotc (wave-aggregated), so appended leaves are
-// in no particular order until k_merge.
-__global__ void k_split_append(int64_t n, int64_t nmain, uint64_t* __restrict__ ids, uint64_t* __restrict__ verts,
-                               uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
-                               uint32_t* __restrict__ anc, uint32_t* slotc, uint64_t* vset, uint64_t vmask,
-                               uint32_t* vcount, uint64_t* nset, uint64_t nmask, uint32_t* cells,
+// nmain stay in key order), child 1 of the s-th listed leaf goes to n + s,
+// and anc names the leaf below nmain it descends from.  The list is in no
+// particular order, so neither are the appended leaves until k_merge.
+__global__ void k_split_append(int64_t count, const uint32_t* __restrict__ slist, int64_t n, int64_t nmain,
+                               uint64_t* __restrict__ ids, uint64_t* __restrict__ verts,
+                               uint8_t* __restrict__ flags, uint32_t* __restrict__ anc, uint64_t* vset,
+                               uint64_t vmask, uint32_t* vcount, uint64_t* nset, uint64_t nmask, uint32_t* cells,
                                uint32_t* __restrict__ work) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool split = i < n && cnt[i] == 2u;
-  const unsigned long long m = __ballot(split);
-  const int lane = __lane_id();
-  uint32_t base = 0;
-  if (m) {
-    const int leader = (int)__builtin_ctzll(m);
-    if (lane == leader) base = atomicAdd(slotc, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-  }
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool added = false;
-  if (split) {
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int64_t o = nmain + base + (uint32_t)__popcll(m & below);
+  if (s < count) {
+    const int64_t i = slist[s], o = n + s;
     const uint64_t id = ids[i];
     uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]}, a[4], b[4];
     const uint64_t z = children(id, v, a, b);
@@ -461,9 +465,8 @@ __global__ void k_split_append(int64_t n, int64_t nmain, uint64_t* __restrict__ 
       verts[4 * o + j] = b[j];
     }
     anc[o - nmain] = i < nmain ? (uint32_t)i : anc[i - nmain];
-    const int64_t r = o - n;  // this round's slot
-    work[2 * r] = (uint32_t)i;
-    work[2 * r + 1] = (uint32_t)o;
+    work[2 * s] = (uint32_t)i;
+    work[2 * s + 1] = (uint32_t)o;
     added = vset_add(vset, vmask, z);
     if (added) {
       vset_add(nset, nmask, z);
@@ -1091,7 +1094,6 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   uint32_t* d_total = misc.as<uint32_t>() + 4;
   uint32_t* d_vcount = misc.as<uint32_t>() + 5;
   uint32_t* d_splitc = misc.as<uint32_t>() + 6;  // running count of marked splits
-  uint32_t* d_slotc = misc.as<uint32_t>() + 7;   // running count of appended leaves
   hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d_dens, nvox, d_flag);
 
   // pyramid
@@ -1236,10 +1238,11 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
     hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
                        A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
-                       nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap), nmain < 0 ? nullptr : d_splitc);
+                       nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap), d_splitc, splitc,
+                       nmain < 0 ? nullptr : cntb.as<uint32_t>());
     hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
                        A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P,
-                       cc, wp, vs.as<uint64_t>(), vcap - 1, nmain < 0 ? nullptr : d_splitc);
+                       cc, wp, vs.as<uint64_t>(), vcap - 1, d_splitc, splitc, nmain < 0 ? nullptr : cntb.as<uint32_t>());
     if (nmain < 0 && scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scan");
     TV_HIP(hipMemcpyAsync(hbuf, d_total, 12, hipMemcpyDeviceToHost, st));
@@ -1264,15 +1267,6 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       vs_old.release();
       vcap = ncap;
     }
-    // the tail: few splits, appended instead of compacted
-    if (nmain < 0 && splits * kAppendRatio < cur) {
-      nmain = cur;
-      B.ids.release();
-      B.verts.release();
-      B.flags.release();
-      B.cap = 0;
-      TV_HIP(hipMemsetAsync(d_slotc, 0, 4, st));
-    }
     if (nmain < 0) {
       if (!B.ensure(total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
     } else if (!A.grow_keep(std::max<int64_t>(total, cur + cur / 16), cur, st) ||
@@ -1294,11 +1288,20 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
                          B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
                          vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, cells, wk.as<uint32_t>());
       A.swap_with(B);
+      // the tail: once few leaves split, the rounds after this one list the
+      // splitting leaves and append children instead of compacting
+      if (splits * kAppendRatio < cur) {
+        nmain = total;
+        B.ids.release();
+        B.verts.release();
+        B.flags.release();
+        B.cap = 0;
+      }
     } else {
-      hipLaunchKernelGGL(k_split_append, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, nmain,
-                         A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(),
-                         anc.as<uint32_t>(), d_slotc, vs.as<uint64_t>(), vcap - 1, d_vcount, ns.as<uint64_t>(),
-                         nscap - 1, cells, wk.as<uint32_t>());
+      hipLaunchKernelGGL(k_split_append, dim3(nblocks(splits, 256)), dim3(256), 0, st, splits, cntb.as<uint32_t>(),
+                         cur, nmain, A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(),
+                         anc.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1,
+                         cells, wk.as<uint32_t>());
     }
     cur = total;
     nwork = 2 * splits;
