@@ -276,13 +276,24 @@ __device__ inline bool hanging(const uint64_t v[4], const uint64_t* __restrict__
 // marked cell cannot have gained a hanging vertex.
 constexpr int kCellShift = kLatBits - 6;
 constexpr int kCellWords = (64 * 64 * 64) / 32;
+// followed by a coarse map, one bit per 8^3 cells (16 words, same sense)
+constexpr int kCoarseWords = (8 * 8 * 8) / 32;
+constexpr int kMapWords = kCellWords + kCoarseWords;
 
 __device__ inline int cell_of(int32_t c) { return min(c >> kCellShift, 63); }
 
-__device__ inline void cell_mark(uint32_t* cells, uint64_t z) {
+// Marks z's cell; with coarse, also its 8^3 region (tail rounds only: the
+// coarse map has 16 words, so a bit already marked is not written again).
+__device__ inline void cell_mark(uint32_t* cells, uint64_t z, bool coarse) {
   const int x = cell_of(vx(z)), y = cell_of(vy(z)), w = cell_of(vz(z));
   const int idx = (w * 64 + y) * 64 + x;
   atomicAnd(&cells[idx >> 5], ~(1u << (idx & 31)));
+  if (coarse) {
+    const int cidx = ((w >> 3) * 8 + (y >> 3)) * 8 + (x >> 3);
+    const uint32_t cbit = 1u << (cidx & 31);
+    if (__hip_atomic_load(&cells[kCellWords + (cidx >> 5)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & cbit)
+      atomicAnd(&cells[kCellWords + (cidx >> 5)], ~cbit);
+  }
 }
 
 // True when the box of v touches a marked cell (or spans more than 64 cells).
@@ -314,6 +325,70 @@ __device__ inline void list_split(bool split, uint32_t i, uint32_t* splitc, uint
   if (split) slist[base - list0 + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = i;
 }
 
+// Tail rounds keep, per chunk of 256 leaves of the main part, a box of
+// cells holding every leaf of the chunk: min x, y, z at words 0..2 and max
+// at 4..6 of 8.  Child 0 stays inside its parent's box, so the boxes stay
+// valid while the tail rounds split leaves in place.
+constexpr int kChunk = 256;
+
+__device__ inline void cell_box(const uint64_t v[4], uint32_t c[6]) {
+  int32_t lo[3], hi[3];
+  tet_box(v, lo, hi);
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    c[a] = (uint32_t)cell_of(lo[a]);
+    c[3 + a] = (uint32_t)cell_of(hi[a]);
+  }
+}
+
+// Boxes of chunks [c0, c1) over the leaves below n (empty past n).
+__global__ void k_chunk_boxes(int64_t n, int64_t c0, int64_t c1, const uint64_t* __restrict__ verts,
+                              uint32_t* __restrict__ box) {
+  const int64_t c = c0 + blockIdx.x;
+  const int64_t i = c * kChunk + threadIdx.x;
+  uint32_t b[6] = {63, 63, 63, 0, 0, 0};
+  if (i < n) {
+    uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
+    cell_box(v, b);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      b[a] = min(b[a], (uint32_t)__shfl_xor(b[a], off, 64));
+      b[3 + a] = max(b[3 + a], (uint32_t)__shfl_xor(b[3 + a], off, 64));
+    }
+  __shared__ uint32_t sb[kChunk / 64][6];
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == 0)
+    for (int a = 0; a < 6; a++) sb[w][a] = b[a];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    uint32_t r = threadIdx.x < 3 ? 63u : 0u;
+    for (int k = 0; k < kChunk / 64; k++) {
+      if (threadIdx.x < 3) r = min(r, sb[k][threadIdx.x]);
+      else if (threadIdx.x >= 4 && threadIdx.x < 7) r = max(r, sb[k][threadIdx.x - 1]);
+    }
+    if (c < c1) box[8 * c + threadIdx.x] = r;
+  }
+}
+
+// True when the chunk's box may hold a marked cell.
+__device__ inline bool chunk_touched(const uint32_t* __restrict__ cells, const uint32_t* __restrict__ box,
+                                     int64_t c) {
+  const uint32_t x0 = box[8 * c], y0 = box[8 * c + 1], z0 = box[8 * c + 2];
+  const uint32_t x1 = box[8 * c + 4], y1 = box[8 * c + 5], z1 = box[8 * c + 6];
+  if (x0 > x1) return false;  // empty
+  if ((x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1) > 64) return true;
+  for (uint32_t z = z0; z <= z1; z++)
+    for (uint32_t y = y0; y <= y1; y++)
+      for (uint32_t x = x0; x <= x1; x++) {
+        const uint32_t idx = (z * 64 + y) * 64 + x;
+        if (!((cells[idx >> 5] >> (idx & 31)) & 1u)) return true;
+      }
+  return false;
+}
+
 // Leaves whose want predicate is settled: split only when forced.
 __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* __restrict__ flags,
                        uint32_t* __restrict__ cnt, const uint64_t* __restrict__ vset, uint64_t vmask,
@@ -322,10 +397,9 @@ __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* _
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool split = false;
   if (i < n) {
-    // both loads issued together (nearly every leaf has a settled predicate)
     const uint8_t fl = flags[i];
-    uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
     if (fl & 1) {  // new leaves (flag 0) are k_want's
+      uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
       if (fl & 2) split = cells_touched(cells, v) && hanging(v, nset, nmask);
       else split = hanging(v, vset, vmask);
       if (!split && !(fl & 2)) flags[i] = fl | 2;
@@ -333,6 +407,101 @@ __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* _
     }
   }
   if (slist) list_split(split, (uint32_t)i, splitc, list0, slist);
+}
+
+// Tail rounds: k_mark over chunks, kTailChunks per block, with the cell
+// map staged in LDS.  A chunk of the main part whose box holds no marked
+// cell is skipped whole: its leaves are all checked (flag bit 1; the tail
+// starts after a compacting round, which checks every leaf), so none can
+// split.  Chunks holding appended leaves are always read.  Each half-wave
+// tests one chunk's box, a cell per lane (boxes of more than 64 cells count
+// as touched).
+constexpr int kTailChunks = 8;
+
+__device__ inline bool cell_marked(const uint32_t* m, uint32_t x, uint32_t y, uint32_t z) {
+  const uint32_t idx = (z * 64 + y) * 64 + x;
+  return !((m[idx >> 5] >> (idx & 31)) & 1u);
+}
+
+__global__ __launch_bounds__(kChunk) void k_mark_tail(int64_t n, int64_t nmain, const uint64_t* __restrict__ verts,
+                                                      uint8_t* __restrict__ flags, const uint64_t* __restrict__ vset,
+                                                      uint64_t vmask, const uint64_t* __restrict__ nset,
+                                                      uint64_t nmask, const uint32_t* __restrict__ cells,
+                                                      const uint32_t* __restrict__ box, uint32_t* splitc,
+                                                      uint32_t list0, uint32_t* __restrict__ slist, int coarse) {
+  static_assert(kChunk == 256 && kTailChunks == 8, "two chunks per wave of the block");
+  __shared__ uint4 smap4[kCellWords / 4];
+  __shared__ int stouch[kTailChunks];
+  // coarse test first (when the last split was a tail round's, which keeps
+  // the coarse map): a block none of whose chunks meets a marked 8^3 region
+  // stages nothing
+  if (coarse) {
+    const int lane = __lane_id(), k = 2 * (threadIdx.x >> 6) + (lane >> 5), j = lane & 31;
+    const int64_t c = (int64_t)blockIdx.x * kTailChunks + k;
+    bool hit = false;
+    if (c * kChunk < n) {
+      if (c >= nmain / kChunk) {
+        hit = true;
+      } else {
+        const uint32_t x0 = box[8 * c] >> 3, y0 = box[8 * c + 1] >> 3, z0 = box[8 * c + 2] >> 3;
+        const uint32_t nx = (box[8 * c + 4] >> 3) - x0 + 1, ny = (box[8 * c + 5] >> 3) - y0 + 1;
+        const uint32_t nz = (box[8 * c + 6] >> 3) - z0 + 1;
+        for (uint32_t q = j; q < nx * ny * nz; q += 32) {
+          const uint32_t cidx = ((z0 + q / (nx * ny)) * 8 + (y0 + (q / nx) % ny)) * 8 + (x0 + q % nx);
+          hit = hit || !((cells[kCellWords + (cidx >> 5)] >> (cidx & 31)) & 1u);
+        }
+      }
+    }
+    if (!__syncthreads_or(hit)) return;
+  }
+  const uint4* c4 = reinterpret_cast<const uint4*>(cells);
+  for (int w = threadIdx.x; w < kCellWords / 4; w += kChunk) smap4[w] = c4[w];
+  __syncthreads();
+  const uint32_t* smap = reinterpret_cast<const uint32_t*>(smap4);
+  {
+    const int lane = __lane_id(), k = 2 * (threadIdx.x >> 6) + (lane >> 5), j = lane & 31;
+    const int64_t c = (int64_t)blockIdx.x * kTailChunks + k;
+    bool hit = false, all = false;
+    if (c * kChunk < n) {
+      if (c >= nmain / kChunk) {
+        all = true;
+      } else {
+        const uint32_t x0 = box[8 * c], y0 = box[8 * c + 1], z0 = box[8 * c + 2];
+        const uint32_t nx = box[8 * c + 4] - x0 + 1, ny = box[8 * c + 5] - y0 + 1, nz = box[8 * c + 6] - z0 + 1;
+        const uint32_t cnt = nx * ny * nz;
+        if (cnt > 64) all = true;
+        for (uint32_t q = j; q < cnt && q < 64; q += 32)
+          hit = hit || cell_marked(smap, x0 + q % nx, y0 + (q / nx) % ny, z0 + q / (nx * ny));
+      }
+    }
+    const unsigned long long m = __ballot(hit || all);
+    if (j == 0) stouch[k] = ((m >> (lane & 32)) & 0xFFFFFFFFull) != 0;
+  }
+  __syncthreads();
+  for (int k = 0; k < kTailChunks; k++) {
+    if (!stouch[k]) continue;
+    const int64_t i = ((int64_t)blockIdx.x * kTailChunks + k) * kChunk + threadIdx.x;
+    bool split = false;
+    if (i < n) {
+      const uint8_t fl = flags[i];
+      if (fl & 1) {
+        uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
+        if (fl & 2) {
+          uint32_t cb[6];
+          cell_box(v, cb);
+          bool t = (cb[3] - cb[0] + 1) * (cb[4] - cb[1] + 1) * (cb[5] - cb[2] + 1) > 64;
+          for (uint32_t z = cb[2]; z <= cb[5] && !t; z++)
+            for (uint32_t y = cb[1]; y <= cb[4] && !t; y++)
+              for (uint32_t x = cb[0]; x <= cb[3] && !t; x++) t = cell_marked(smap, x, y, z);
+          split = t && hanging(v, nset, nmask);
+        } else {
+          split = hanging(v, vset, vmask);
+          if (!split) flags[i] = fl | 2;
+        }
+      }
+    }
+    list_split(split, (uint32_t)i, splitc, list0, slist);
+  }
 }
 
 // The leaves made by the last split pass (a dense list, so the want
@@ -419,7 +588,7 @@ __device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_
   bool added = vset_add(vset, vmask, z);
   if (nset && added) {  // only vertices new to the mesh can hang on a checked leaf
     vset_add(nset, nmask, z);
-    cell_mark(cells, z);
+    cell_mark(cells, z, false);
   }
   return added;
 }
@@ -470,7 +639,7 @@ __global__ void k_split_append(int64_t count, const uint32_t* __restrict__ slist
     added = vset_add(vset, vmask, z);
     if (added) {
       vset_add(nset, nmask, z);
-      cell_mark(cells, z);
+      cell_mark(cells, z, true);
     }
   }
   count_new(added, vcount);
@@ -1171,9 +1340,9 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   // ns: the new-vertex set (nscap keys) followed by the cell map, both
   // cleared to all ones by one fill
   uint64_t nscap = 1024;
-  if (!ns.ensure(nscap * 8 + kCellWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
-  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kCellWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
-                     (int64_t)(nscap + kCellWords / 2),
+  if (!ns.ensure(nscap * 8 + kMapWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kMapWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
+                     (int64_t)(nscap + kMapWords / 2),
                      kEmptyKey);
   // capacities are even powers of two and grow by factors of 4, so the
   // sizes the set passes through do not depend on where it started
@@ -1203,6 +1372,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   int64_t nmain = -1;  // >= 0 once the tail rounds append (leaves below nmain stay in key order)
   uint32_t splitc = 0;  // last value read of the running split count
   Buf anc;             // leaf below nmain each appended leaf descends from
+  Buf cbox;            // tail rounds: cell box of every chunk of kChunk leaves
   if (small) {
     if (!cntb.ensure(small_cap * 4) || !bsum.ensure((size_t)small_blocks * 4))
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
@@ -1236,10 +1406,15 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   }
   while (!done) {
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
-    hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
-                       A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
-                       nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap), d_splitc, splitc,
-                       nmain < 0 ? nullptr : cntb.as<uint32_t>());
+    if (nmain < 0)
+      hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
+                         A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
+                         nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap), d_splitc, splitc, nullptr);
+    else
+      hipLaunchKernelGGL(k_mark_tail, dim3(nblocks(cur, kChunk * kTailChunks)), dim3(kChunk), 0, st, cur, nmain,
+                         A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), vs.as<uint64_t>(), vcap - 1,
+                         ns.as<uint64_t>(), nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap),
+                         cbox.as<uint32_t>(), d_splitc, splitc, cntb.as<uint32_t>(), (int)(cur > nmain));
     hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
                        A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P,
                        cc, wp, vs.as<uint64_t>(), vcap - 1, d_splitc, splitc, nmain < 0 ? nullptr : cntb.as<uint32_t>());
@@ -1267,9 +1442,10 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       vs_old.release();
       vcap = ncap;
     }
+    const bool to_tail = nmain < 0 && splits * kAppendRatio < cur;  // the rounds after this one append
     if (nmain < 0) {
-      if (!B.ensure(total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
-    } else if (!A.grow_keep(std::max<int64_t>(total, cur + cur / 16), cur, st) ||
+      if (!B.ensure(to_tail ? total + total / 16 : total)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
+    } else if (!A.grow_keep(total, cur, st) ||
                !grow_keep(anc, (size_t)(A.cap - nmain) * 4, (size_t)(cur - nmain) * 4, st)) {
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
     }
@@ -1277,9 +1453,9 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     // the new-vertex set of this pass, at most half full
     nscap = 1024;
     while ((uint64_t)splits * 2 > nscap) nscap <<= 1;
-    if (!ns.ensure(nscap * 8 + kCellWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
-    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kCellWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
-                       (int64_t)(nscap + kCellWords / 2),
+    if (!ns.ensure(nscap * 8 + kMapWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kMapWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
+                       (int64_t)(nscap + kMapWords / 2),
                        kEmptyKey);
     uint32_t* cells = (uint32_t*)(ns.as<uint64_t>() + nscap);
     if (nmain < 0) {
@@ -1290,12 +1466,18 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       A.swap_with(B);
       // the tail: once few leaves split, the rounds after this one list the
       // splitting leaves and append children instead of compacting
-      if (splits * kAppendRatio < cur) {
+      if (to_tail) {
         nmain = total;
         B.ids.release();
         B.verts.release();
         B.flags.release();
         B.cap = 0;
+        const int64_t chunks = nmain / kChunk;  // whole chunks of the main part
+        if (!cbox.ensure((size_t)std::max<int64_t>(chunks, 1) * 32))
+          return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: chunk boxes");
+        if (chunks > 0)
+          hipLaunchKernelGGL(k_chunk_boxes, dim3((unsigned)chunks), dim3(kChunk), 0, st, nmain, (int64_t)0, chunks,
+                             A.verts.as<uint64_t>(), cbox.as<uint32_t>());
       }
     } else {
       hipLaunchKernelGGL(k_split_append, dim3(nblocks(splits, 256)), dim3(256), 0, st, splits, cntb.as<uint32_t>(),
@@ -1360,6 +1542,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   offb.release();
   bsum.release();
   anc.release();
+  cbox.release();
   if (he == hipSuccess) {
     hipLaunchKernelGGL(k_keys, dim3(nblocks(cur, 1024)), dim3(1024), 0, st, cur, g->ids, g->keys, d_flag + 1);
     he = hipMemcpyAsync(&flag, d_flag + 1, 4, hipMemcpyDeviceToHost, st);
