@@ -27,8 +27,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -944,9 +947,11 @@ __device__ inline int isgn(int64_t x) { return (x > 0) - (x < 0); }
 // the point is 3 * face centroid (q3, below 2^22) plus epsilon * outward
 // normal.
 template <int K>
-__device__ inline void descend_perturbed(int32_t v[4][3], uint64_t& h, const int32_t q3[3], const int nout[3]) {
+__device__ inline void descend_perturbed(int32_t v[4][3], uint64_t& h, uint32_t& cls, const uint32_t* __restrict__ shapes,
+                                         const int32_t q3[3], const int nout[3]) {
+  const uint32_t w = shapes[cls];
   int32_t z[3], u[3];
-  bisector<K>(v, z, u);
+  shape_bisector<K>(v, w, z, u);
   int32_t side = 0, pert = 0;
 #pragma unroll
   for (int i = 0; i < 3; i++) {
@@ -954,6 +959,7 @@ __device__ inline void descend_perturbed(int32_t v[4][3], uint64_t& h, const int
     pert += __mul24(u[i], nout[i]);
   }
   bool first = side != 0 ? side > 0 : pert > 0;
+  cls = first ? (w >> 8) & 255u : (w >> 16) & 255u;
   if (first) {
 #pragma unroll
     for (int i = 0; i < 3; i++) v[K][i] = z[i];
@@ -1021,7 +1027,8 @@ __device__ inline bool face_normal(const int64_t v[4][3], int f, int un[3], int6
 
 __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
                            const uint64_t* __restrict__ keys, int dmax, Pyramid P, float scale, int majorant_mode,
-                           TetRec* __restrict__ rec, TetRec32* __restrict__ rec32, int* __restrict__ err) {
+                           const uint32_t* __restrict__ shapes, TetRec* __restrict__ rec, TetRec32* __restrict__ rec32,
+                           int* __restrict__ err) {
   int32_t ioff[4] = {0, 0, 0, 0};
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -1091,10 +1098,11 @@ __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const ui
     int32_t w[4][3], q3i[3] = {(int32_t)q3[0], (int32_t)q3[1], (int32_t)q3[2]};
     root_verts(root, w);
     uint64_t h = 8 + root;
+    uint32_t cls = shapes[kShapeWords + root];
     for (int d = 0; d < dmax; d += 3) {
-      descend_perturbed<3>(w, h, q3i, un);
-      if (d + 1 < dmax) descend_perturbed<2>(w, h, q3i, un);
-      if (d + 2 < dmax) descend_perturbed<1>(w, h, q3i, un);
+      descend_perturbed<3>(w, h, cls, shapes, q3i, un);
+      if (d + 1 < dmax) descend_perturbed<2>(w, h, cls, shapes, q3i, un);
+      if (d + 2 < dmax) descend_perturbed<1>(w, h, cls, shapes, q3i, un);
     }
     int64_t nb = search_keys(keys, n, h << (60 - dmax));
     // back face: the neighbour's vertex that is not on face f
@@ -1136,6 +1144,120 @@ __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const ui
 
 // ---------------------------------------------------------------- host
 static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- shape classes
+// The classes are found by bisecting, from the six roots, one
+// representative of each class (x_0 = 0, x_j = 4 e_j with e_j the class's
+// reduced edge vectors, so midpoints stay integral) until no new class
+// appears; normals come from exact integer cross products.
+namespace {
+struct ShapeKey {
+  std::array<int64_t, 9> e;
+  int tag;
+  bool operator<(const ShapeKey& o) const { return tag != o.tag ? tag < o.tag : e < o.e; }
+};
+
+ShapeKey shape_key(const int64_t v[4][3], int tag) {
+  ShapeKey k;
+  int64_t m = 0;
+  for (int j = 1; j < 4; j++)
+    for (int i = 0; i < 3; i++) {
+      k.e[3 * (j - 1) + i] = v[j][i] - v[0][i];
+      m |= k.e[3 * (j - 1) + i];
+    }
+  const int sh = m ? __builtin_ctzll((uint64_t)m) : 0;
+  for (auto& x : k.e) x >>= sh;
+  k.tag = tag;
+  return k;
+}
+
+bool make_shapes(std::vector<uint32_t>& tab) {
+  tab.assign(kShapeWords + 8, 0u);
+  std::map<ShapeKey, int> ids;
+  std::vector<ShapeKey> reps;
+  auto intern = [&](const int64_t v[4][3], int tag) {
+    ShapeKey k = shape_key(v, tag);
+    auto it = ids.find(k);
+    if (it != ids.end()) return it->second;
+    const int c = (int)reps.size();
+    ids.emplace(k, c);
+    reps.push_back(k);
+    return c;
+  };
+  const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1};
+  for (int r = 0; r < 6; r++) {
+    int64_t v[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {kLatS, kLatS, kLatS}};
+    v[1][p0[r]] = kLatS;
+    v[2][p0[r]] = kLatS;
+    v[2][p1[r]] = kLatS;
+    tab[kShapeWords + r] = (uint32_t)intern(v, 3);
+  }
+  for (size_t c = 0; c < reps.size(); c++) {
+    if (reps.size() > (size_t)kShapeWords) return false;
+    const ShapeKey k = reps[c];
+    const int K = k.tag, J1 = K == 1 ? 2 : 1, J2 = K == 3 ? 2 : 3;
+    int64_t v[4][3] = {{0, 0, 0}};
+    for (int j = 1; j < 4; j++)
+      for (int i = 0; i < 3; i++) v[j][i] = 4 * k.e[3 * (j - 1) + i];
+    int64_t z[3], a[3], b[3], d[3], n[3];
+    for (int i = 0; i < 3; i++) {
+      z[i] = (v[0][i] + v[K][i]) / 2;
+      a[i] = v[J1][i] - z[i];
+      b[i] = v[J2][i] - z[i];
+      d[i] = v[0][i] - z[i];
+    }
+    n[0] = a[1] * b[2] - a[2] * b[1];
+    n[1] = a[2] * b[0] - a[0] * b[2];
+    n[2] = a[0] * b[1] - a[1] * b[0];
+    const int64_t s0 = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+    if (s0 == 0) return false;
+    uint32_t w = 0;
+    for (int i = 0; i < 3; i++) {
+      int u = (n[i] > 0) - (n[i] < 0);
+      if (s0 < 0) u = -u;
+      w |= (uint32_t)(u + 1) << (2 * i);
+    }
+    // first child: x_K -> z; second child: (x_1..x_K, z, x_{K+1}..x_3)
+    const int ctag = K == 1 ? 3 : K - 1;
+    int64_t ca[4][3], cb[4][3];
+    for (int j = 0; j < 4; j++)
+      for (int i = 0; i < 3; i++) ca[j][i] = j == K ? z[i] : v[j][i];
+    for (int j = 0; j < 4; j++)
+      for (int i = 0; i < 3; i++) cb[j][i] = j < K ? v[j + 1][i] : (j == K ? z[i] : v[j][i]);
+    const int ia = intern(ca, ctag), ib = intern(cb, ctag);
+    w |= (uint32_t)ia << 8 | (uint32_t)ib << 16;
+    tab[c] = w;
+  }
+  return reps.size() <= (size_t)kShapeWords;
+}
+}  // namespace
+
+const uint32_t* shape_table() {
+  static std::once_flag once;
+  static std::vector<uint32_t> host;
+  static bool ok = false;
+  std::call_once(once, [] { ok = make_shapes(host); });
+  if (!ok) return nullptr;
+  static std::mutex mu;
+  static std::map<int, uint32_t*> dev_tab;  // one copy per device, kept until exit
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = dev_tab.find(dev);
+  if (it != dev_tab.end()) return it->second;
+  uint32_t* p = nullptr;
+  if (hipMalloc((void**)&p, host.size() * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipMemcpy(p, host.data(), host.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p);
+    return nullptr;
+  }
+  dev_tab.emplace(dev, p);
+  return p;
+}
 
 namespace {
 struct Buf {
@@ -1553,8 +1675,13 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     return fail(TET_ERR_DEVICE, std::string("leb_build: ") + hipGetErrorString(he));
   }
   g->max_depth = flag;
+  const uint32_t* shapes = shape_table();
+  if (!shapes) {
+    tet_grid_free(g);
+    return fail(TET_ERR_DEVICE, "leb_build: shape table");
+  }
   hipLaunchKernelGGL(k_finalize, dim3(nblocks(cur, 128)), dim3(128), 0, st, cur, g->ids, g->verts, g->keys,
-                     g->max_depth, P, dens->density_scale, o.majorant_mode, g->rec, g->rec32, d_flag + 2);
+                     g->max_depth, P, dens->density_scale, o.majorant_mode, shapes, g->rec, g->rec32, d_flag + 2);
   int ferr = 0;
   he = hipMemcpyAsync(&ferr, d_flag + 2, 4, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipEventRecord(e1, st);

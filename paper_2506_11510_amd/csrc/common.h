@@ -132,42 +132,24 @@ __host__ __device__ inline int id_depth(uint64_t id) {
 }
 __host__ __device__ inline int tag_of(int depth) { return 3 - depth % 3; }
 
-// Bisection plane of a Maubach tet with tag K: it holds the midpoint z of
-// the edge (v0, vK) and the two vertices off that edge.  Writes z and the
-// plane's normal as a sign vector u (components -1, 0, 1) facing v0.  The
-// shapes of Kuhn descendants repeat every three levels at half the size,
-// and at every level the vectors from z to the vertices, divided by their
-// common power of two, have components in {-1, 0, 1}: the cross product is
-// then exact in 24-bit integer products.
+// Shape classes.  Up to translation and scale every tet of these grids is
+// one of a small set of shapes (with vertex order and tag): its edge
+// vectors x_j - x_0 divided by their common power of two.  shape_table()
+// gives the current device's table: word c (c < kShapeWords) describes
+// class c: its bisection normal as a sign vector facing x_0 (bits 2i, 2i+1
+// hold u_i + 1) and the classes of its first and second child (bits 8..15,
+// 16..23); words kShapeWords + r hold the classes of the six roots.  Null
+// if the table could not be made.
+constexpr int kShapeWords = 256;
+const uint32_t* shape_table();
+
+// Midpoint z of the edge (v0, vK) and the bisection normal of class word w.
 template <int K>
-__device__ inline void bisector(const int32_t v[4][3], int32_t z[3], int32_t u[3]) {
-  constexpr int J1 = K == 1 ? 2 : 1, J2 = K == 3 ? 2 : 3;
-  int32_t a[3], b[3], c[3];
-  int32_t m = 1 << 30;  // bounds the shift (coordinates are below 2^21)
+__device__ inline void shape_bisector(const int32_t v[4][3], uint32_t w, int32_t z[3], int32_t u[3]) {
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     z[i] = (v[0][i] + v[K][i]) >> 1;
-    a[i] = v[J1][i] - z[i];
-    b[i] = v[J2][i] - z[i];
-    c[i] = v[0][i] - z[i];
-    m |= a[i] | b[i] | c[i];
-  }
-  const int sh = __builtin_ctz((uint32_t)m);
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    a[i] >>= sh;
-    b[i] >>= sh;
-    c[i] >>= sh;
-  }
-  int32_t n[3];
-  n[0] = __mul24(a[1], b[2]) - __mul24(a[2], b[1]);
-  n[1] = __mul24(a[2], b[0]) - __mul24(a[0], b[2]);
-  n[2] = __mul24(a[0], b[1]) - __mul24(a[1], b[0]);
-  const int32_t s0 = __mul24(n[0], c[0]) + __mul24(n[1], c[1]) + __mul24(n[2], c[2]);
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    const int32_t sg = (n[i] > 0) - (n[i] < 0);
-    u[i] = s0 < 0 ? -sg : sg;
+    u[i] = (int32_t)((w >> (2 * i)) & 3u) - 1;
   }
 }
 

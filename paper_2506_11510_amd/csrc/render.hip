@@ -152,15 +152,18 @@ struct Step {
 
 // ---------------------------------------------------------------- tet medium
 template <int K>
-__device__ inline void descend_point(int32_t v[4][3], uint64_t& h, const double P[3]) {
+__device__ inline void descend_point(int32_t v[4][3], uint64_t& h, uint32_t& cls, const uint32_t* __restrict__ shapes,
+                                     const double P[3]) {
+  const uint32_t w = shapes[cls];
   int32_t z[3], u[3];
-  bisector<K>(v, z, u);
+  shape_bisector<K>(v, w, z, u);
   double side = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     const double t = P[i] - (double)z[i];
     if (u[i]) side = side + (u[i] > 0 ? t : -t);
   }
+  cls = side >= 0.0 ? (w >> 8) & 255u : (w >> 16) & 255u;
   if (side >= 0.0) {
 #pragma unroll
     for (int i = 0; i < 3; i++) v[K][i] = z[i];
@@ -179,7 +182,8 @@ __device__ inline void descend_point(int32_t v[4][3], uint64_t& h, const double 
 // Tet containing p: the Kuhn root whose axis order sorts p's coordinates in
 // descending order, exact bisection-plane descent to the grid's depth, then
 // the last tet whose depth-first key is <= the key reached.
-__device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_t n, int dmax, float3 p) {
+__device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_t n, int dmax,
+                                       const uint32_t* __restrict__ shapes, float3 p) {
   const float c[3] = {p.x, p.y, p.z};
   int r = -1;
   if (c[0] >= c[1] && c[1] >= c[2]) r = 0;
@@ -201,10 +205,11 @@ __device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_
   }
   double P[3] = {(double)p.x * (double)kLatS, (double)p.y * (double)kLatS, (double)p.z * (double)kLatS};
   uint64_t h = 8 + (uint64_t)r;
+  uint32_t cls = shapes[kShapeWords + r];
   for (int d = 0; d < dmax; d += 3) {
-    descend_point<3>(v, h, P);
-    if (d + 1 < dmax) descend_point<2>(v, h, P);
-    if (d + 2 < dmax) descend_point<1>(v, h, P);
+    descend_point<3>(v, h, cls, shapes, P);
+    if (d + 1 < dmax) descend_point<2>(v, h, cls, shapes, P);
+    if (d + 2 < dmax) descend_point<1>(v, h, cls, shapes, P);
   }
   uint64_t key = h << (60 - dmax);
   int64_t lo = 0, hi = n;
@@ -222,7 +227,8 @@ struct TetMedium {
   const uint64_t* __restrict__ keys;
   int64_t n;
   int dmax;
-  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
+  const uint32_t* __restrict__ shapes;
+  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, shapes, p); }
   __device__ inline float sigma_at(uint32_t cell) const { return rec[cell].sigma; }
   // Exit of the tet along the segment whose direction-dot table is `tab`
   // (tab[N] = dir_N . d, tab[9 + N] = dir_N . o) from t: faces with
@@ -277,7 +283,8 @@ struct TetMedium32 {
   const uint64_t* __restrict__ keys;
   int64_t n;
   int dmax;
-  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, p); }
+  const uint32_t* __restrict__ shapes;
+  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, shapes, p); }
   __device__ inline float sigma_at(uint32_t cell) const { return __uint_as_float(rec[cell].w[3]); }
   __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
     const uint4* q = (const uint4*)(rec + cell);
@@ -1049,6 +1056,8 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (nrc && !(nrc->opts.sigma_ref > 0.0f))
     return fail(TET_ERR_INVALID_ARG, "render: the radiance cache has no sigma_ref yet (train it or set one)");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
+  const uint32_t* shapes = shape_table();
+  if (!shapes) return fail(TET_ERR_DEVICE, "render: shape table");
   int64_t npix = (int64_t)cam->width * cam->height;
   int tiles_x = (cam->width + 7) / 8, tiles_y = (cam->height + 7) / 8;
   int64_t slots = (int64_t)tiles_x * tiles_y * 64;
@@ -1118,12 +1127,12 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
-    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth};
+    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes};
     rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
              : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
-    TetMedium m{g->rec, g->keys, g->n, g->max_depth};
+    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes};
     rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
              : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else {
@@ -1177,6 +1186,8 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
                          uint64_t frame_seed, const tet_render_opts* opts_in, int32_t n_paths, int32_t kv, float4* vrec,
                          float4* path_l, hipStream_t st, float* ms_out) {
   if (!g) return fail(TET_ERR_INVALID_ARG, "training paths: grid is NULL");
+  const uint32_t* shapes = shape_table();
+  if (!shapes) return fail(TET_ERR_DEVICE, "training paths: shape table");
   if (int rc = check_camera(cam)) return rc;
   if (!medm || !light) return fail(TET_ERR_INVALID_ARG, "training paths: NULL medium or light");
   if (!(medm->g > -1.0f && medm->g < 1.0f) || !(medm->albedo >= 0.0f))
@@ -1218,10 +1229,10 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (g->rec32 && o.record_layout != 48) {
-    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth};
+    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes};
     rc = run_passes<TetMedium32, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
   } else {
-    TetMedium m{g->rec, g->keys, g->n, g->max_depth};
+    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes};
     rc = run_passes<TetMedium, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
   }
   if (rc) return rc;
@@ -1263,6 +1274,7 @@ struct BatchState {
   int device = 0;
   int n = 0;
   bool use32 = true;
+  const uint32_t* shapes = nullptr;
   tet_render_opts o;
   SceneDesc* pinned = nullptr;  // host staging of the scene table (page-locked)
   SceneDesc* table = nullptr;   // device scene table
@@ -1308,6 +1320,8 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
   B->n = n;
   B->o = o;
   B->use32 = use32;
+  B->shapes = shape_table();  // made here: a captured frame cannot upload it
+  if (!B->shapes) return fail(TET_ERR_DEVICE, "render batch: shape table");
   if (hipGetDevice(&B->device) != hipSuccess) return fail(TET_ERR_DEVICE, "render batch: no device");
   std::vector<SceneDesc> host((size_t)n);
   uint64_t item = 0, entry = 0, px = 0;
@@ -1384,11 +1398,11 @@ static int batch_enqueue(const BatchState* B, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)B->scratch, 64);
   hipLaunchKernelGGL(k_batch_images, dim3(pblocks), dim3(256), 0, st, (const SceneDesc*)B->table, B->n, B->total_px, 1);
   if (B->use32) {
-    TetMedium32 m{nullptr, nullptr, 0, 0};
+    TetMedium32 m{nullptr, nullptr, 0, 0, B->shapes};
     hipLaunchKernelGGL(k_raygen_batch<TetMedium32>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
     hipLaunchKernelGGL((k_render<TetMedium32, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
   } else {
-    TetMedium m{nullptr, nullptr, 0, 0};
+    TetMedium m{nullptr, nullptr, 0, 0, B->shapes};
     hipLaunchKernelGGL(k_raygen_batch<TetMedium>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
     hipLaunchKernelGGL((k_render<TetMedium, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
   }
@@ -1494,6 +1508,8 @@ int locate_points(const tet_grid* g, const float* pts, int64_t count, int64_t* o
                   hipStream_t st) {
   if (!g || count < 0 || (count && (!pts || !out))) return fail(TET_ERR_INVALID_ARG, "tet_locate: bad arguments");
   if (count == 0) return TET_OK;
+  const uint32_t* shapes = shape_table();
+  if (!shapes) return fail(TET_ERR_DEVICE, "tet_locate: shape table");
   const float* dp = pts;
   int64_t* dout = out;
   char* tmp = nullptr;
@@ -1508,7 +1524,7 @@ int locate_points(const tet_grid* g, const float* pts, int64_t count, int64_t* o
     void* p;
     ~Free() { if (p) dev_free(p); }
   } f_{tmp};
-  TetMedium m{g->rec, g->keys, g->n, g->max_depth};
+  TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes};
   hipLaunchKernelGGL(k_locate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, m, dp, count, dout);
   TV_HIP(hipGetLastError());
   if (!on_device) TV_HIP(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, st));
