@@ -927,6 +927,26 @@ __global__ void k_keys(int64_t n, const uint64_t* __restrict__ ids, uint64_t* __
   }
 }
 
+// kidx[b] = first index whose key is in bucket b or later (a lower-bound
+// search per bucket; b = key_buckets gives n).
+__global__ void k_key_index(int64_t n, const uint64_t* __restrict__ keys, int kbits, uint32_t* __restrict__ kidx) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = key_buckets(kbits);
+  if (b > nb) return;
+  if (b == nb) {
+    kidx[b] = (uint32_t)n;
+    return;
+  }
+  const uint64_t first = ((8ull << kbits) + (uint64_t)b) << (60 - kbits);
+  int64_t lo = 0, hi = n;  // first index with keys >= first
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < first) lo = mid + 1;
+    else hi = mid;
+  }
+  kidx[b] = (uint32_t)lo;
+}
+
 // Root Kuhn tets: vertex 1 = S e_p0, vertex 2 = S (e_p0 + e_p1), over the
 // axis orders (0,1,2), (0,2,1), (1,0,2), (1,2,0), (2,0,1), (2,1,0).
 __device__ inline void root_verts(int r, int32_t v[4][3]) {
@@ -975,35 +995,23 @@ __device__ inline void descend_perturbed(int32_t v[4][3], uint64_t& h, uint32_t&
   }
 }
 
-__device__ inline int64_t search_keys(const uint64_t* __restrict__ keys, int64_t n, uint64_t key) {
-  int64_t lo = 0, hi = n;  // first index with keys[i] > key
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] <= key) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo - 1;
-}
-
-// Outward unit normal of face f (opposite vertex f) and its lattice offset;
-// returns false when the normal is not one of the 18 orientations.
-__device__ inline bool face_normal(const int64_t v[4][3], int f, int un[3], int64_t& off) {
-  int idx[3], q = 0;
-#pragma unroll
-  for (int j = 0; j < 4; j++)
-    if (j != f) idx[q++] = j;
+// Outward unit normal of the face (a, b, c) opposite vertex o and its
+// lattice offset; returns false when the normal is not one of the 18
+// orientations.
+__device__ inline bool face_normal(const int64_t a[3], const int64_t b[3], const int64_t c[3], const int64_t o[3],
+                                   int un[3], int64_t& off) {
   int64_t e1[3], e2[3], n[3];
 #pragma unroll
   for (int i = 0; i < 3; i++) {
-    e1[i] = v[idx[1]][i] - v[idx[0]][i];
-    e2[i] = v[idx[2]][i] - v[idx[0]][i];
+    e1[i] = b[i] - a[i];
+    e2[i] = c[i] - a[i];
   }
   n[0] = e1[1] * e2[2] - e1[2] * e2[1];
   n[1] = e1[2] * e2[0] - e1[0] * e2[2];
   n[2] = e1[0] * e2[1] - e1[1] * e2[0];
   int64_t s = 0;
 #pragma unroll
-  for (int i = 0; i < 3; i++) s += n[i] * (v[f][i] - v[idx[0]][i]);
+  for (int i = 0; i < 3; i++) s += n[i] * (o[i] - a[i]);
   if (s == 0) return false;
   int64_t m = 0;
 #pragma unroll
@@ -1021,14 +1029,39 @@ __device__ inline bool face_normal(const int64_t v[4][3], int f, int un[3], int6
   }
   int nz = (un[0] != 0) + (un[1] != 0) + (un[2] != 0);
   if (nz > 2) ok = false;
-  off = un[0] * v[idx[0]][0] + un[1] * v[idx[0]][1] + un[2] * v[idx[0]][2];
+  off = un[0] * a[0] + un[1] * a[1] + un[2] * a[2];
   return ok;
 }
 
+// Element i of a 4-array held in registers (selects, no indexed access).
+template <class T>
+__device__ inline T pick4(const T x[4], int i) {
+  return i == 0 ? x[0] : (i == 1 ? x[1] : (i == 2 ? x[2] : x[3]));
+}
+
+// Kuhn root whose axis order sorts the point (q3, perturbed along un) in
+// descending order: pairwise comparisons of (q3, un), lexicographic; -1 on
+// a tie.
+__device__ inline int root_of(const int64_t q3[3], const int un[3]) {
+  auto cmp = [&](int a, int b) {
+    const int c = isgn(q3[a] - q3[b]);
+    return c ? c : isgn((int64_t)un[a] - un[b]);
+  };
+  const int c01 = cmp(0, 1), c02 = cmp(0, 2), c12 = cmp(1, 2);
+  if (!c01 || !c02 || !c12) return -1;
+  // axis orders (0,1,2), (0,2,1), (1,0,2), (1,2,0), (2,0,1), (2,1,0)
+  if (c01 > 0 && c12 > 0) return 0;
+  if (c02 > 0 && c12 < 0) return c01 > 0 ? 1 : -1;
+  if (c01 < 0 && c02 > 0) return 2;
+  if (c12 > 0 && c02 < 0) return c01 < 0 ? 3 : -1;
+  if (c02 < 0 && c01 > 0) return 4;
+  return 5;
+}
+
 __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
-                           const uint64_t* __restrict__ keys, int dmax, Pyramid P, float scale, int majorant_mode,
-                           const uint32_t* __restrict__ shapes, TetRec* __restrict__ rec, TetRec32* __restrict__ rec32,
-                           int* __restrict__ err) {
+                           const uint64_t* __restrict__ keys, const uint32_t* __restrict__ kidx, int kbits, int dmax,
+                           Pyramid P, float scale, int majorant_mode, const uint32_t* __restrict__ shapes,
+                           TetRec* __restrict__ rec, TetRec32* __restrict__ rec32, int* __restrict__ err) {
   int32_t ioff[4] = {0, 0, 0, 0};
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -1052,77 +1085,86 @@ __global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const ui
   r.majorant = majorant_mode == 1 ? (float)((double)scale * (double)mx) : r.sigma;
   r.codes = 0;
   r.pad = 0;
+  uint32_t nbr[4];
+  float offs[4];
 #pragma unroll 1
   for (int f = 0; f < 4; f++) {
+    // face f: the vertices other than f, in order (selects keep the arrays
+    // in registers)
+    const int i0 = f == 0 ? 1 : 0, i1 = f <= 1 ? 2 : 1, i2 = f <= 2 ? 3 : 2;
+    int64_t fa3[3], fb3[3], fc3[3], fo3[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const int64_t col[4] = {v[0][a], v[1][a], v[2][a], v[3][a]};
+      fa3[a] = pick4(col, i0);
+      fb3[a] = pick4(col, i1);
+      fc3[a] = pick4(col, i2);
+      fo3[a] = pick4(col, f);
+    }
     int un[3];
     int64_t off;
     int code = -1;
-    if (face_normal(v, f, un, off)) code = dir_code(un);
+    if (face_normal(fa3, fb3, fc3, fo3, un, off)) code = dir_code(un);
     if (code < 0) {
       atomicOr(err, 2);
       code = 0;
     }
-    r.off[f] = ldexpf((float)off, -kLatBits);
+    const float offw = ldexpf((float)off, -kLatBits);
     r.codes |= (uint32_t)code << (8 * f);
-    ioff[f] = (int32_t)off;
+    uint32_t link = kBoundary;
     // boundary face: its three vertices share a coordinate equal to 0 or S
-    int idx[3], q = 0;
-    for (int j = 0; j < 4; j++)
-      if (j != f) idx[q++] = j;
     bool bnd = false;
+#pragma unroll
     for (int a = 0; a < 3; a++) {
-      int64_t x = v[idx[0]][a];
-      if (v[idx[1]][a] == x && v[idx[2]][a] == x && (x == 0 || x == kLatS)) bnd = true;
+      const int64_t x = fa3[a];
+      if (fb3[a] == x && fc3[a] == x && (x == 0 || x == kLatS)) bnd = true;
     }
-    if (bnd) {
-      r.nbr[f] = kBoundary;
-      continue;
-    }
-    int64_t q3[3];
-    for (int a = 0; a < 3; a++) q3[a] = v[idx[0]][a] + v[idx[1]][a] + v[idx[2]][a];
-    // root: coordinates in descending order along its axis order
-    const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1}, p2[6] = {2, 1, 2, 0, 1, 0};
-    int root = -1;
-    for (int rr = 0; rr < 6 && root < 0; rr++) {
-      int c01 = isgn(q3[p0[rr]] - q3[p1[rr]]);
-      if (!c01) c01 = isgn(un[p0[rr]] - un[p1[rr]]);
-      int c12 = isgn(q3[p1[rr]] - q3[p2[rr]]);
-      if (!c12) c12 = isgn(un[p1[rr]] - un[p2[rr]]);
-      if (c01 > 0 && c12 > 0) root = rr;
-    }
-    if (root < 0) {
-      atomicOr(err, 4);
-      r.nbr[f] = kBoundary;
-      continue;
-    }
-    int32_t w[4][3], q3i[3] = {(int32_t)q3[0], (int32_t)q3[1], (int32_t)q3[2]};
-    root_verts(root, w);
-    uint64_t h = 8 + root;
-    uint32_t cls = shapes[kShapeWords + root];
-    for (int d = 0; d < dmax; d += 3) {
-      descend_perturbed<3>(w, h, cls, shapes, q3i, un);
-      if (d + 1 < dmax) descend_perturbed<2>(w, h, cls, shapes, q3i, un);
-      if (d + 2 < dmax) descend_perturbed<1>(w, h, cls, shapes, q3i, un);
-    }
-    int64_t nb = search_keys(keys, n, h << (60 - dmax));
-    // back face: the neighbour's vertex that is not on face f
-    uint64_t fa = pv[idx[0]], fb = pv[idx[1]], fc = pv[idx[2]];
-    int bf = -1, hits = 0;
-    if (nb >= 0) {
-      for (int j = 0; j < 4; j++) {
-        uint64_t x = verts[4 * nb + j];
-        if (x == fa || x == fb || x == fc)
-          hits++;
-        else
-          bf = j;
+    if (!bnd) {
+      int64_t q3[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) q3[a] = fa3[a] + fb3[a] + fc3[a];
+      const int root = root_of(q3, un);
+      if (root < 0) {
+        atomicOr(err, 4);
+      } else {
+        int32_t w[4][3], q3i[3] = {(int32_t)q3[0], (int32_t)q3[1], (int32_t)q3[2]};
+        root_verts(root, w);
+        uint64_t h = 8 + root;
+        uint32_t cls = shapes[kShapeWords + root];
+        for (int d = 0; d < dmax; d += 3) {
+          descend_perturbed<3>(w, h, cls, shapes, q3i, un);
+          if (d + 1 < dmax) descend_perturbed<2>(w, h, cls, shapes, q3i, un);
+          if (d + 2 < dmax) descend_perturbed<1>(w, h, cls, shapes, q3i, un);
+        }
+        const int64_t nb = search_keys_idx(keys, kidx, kbits, h << (60 - dmax));
+        // back face: the neighbour's vertex that is not on face f
+        const uint64_t fa = pick4(pv, i0), fb = pick4(pv, i1), fc = pick4(pv, i2);
+        int bf = -1, hits = 0;
+        if (nb >= 0) {
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            uint64_t x = verts[4 * nb + j];
+            if (x == fa || x == fb || x == fc) hits++;
+            else bf = j;
+          }
+        }
+        if (nb < 0 || nb == t || hits != 3 || bf < 0) atomicOr(err, 1);
+        else link = ((uint32_t)nb << 2) | (uint32_t)bf;
       }
     }
-    if (nb < 0 || nb == t || hits != 3 || bf < 0) {
-      atomicOr(err, 1);
-      r.nbr[f] = kBoundary;
-    } else {
-      r.nbr[f] = ((uint32_t)nb << 2) | (uint32_t)bf;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (k == f) {
+        nbr[k] = link;
+        offs[k] = offw;
+        ioff[k] = (int32_t)off;
+      }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    r.nbr[k] = nbr[k];
+    r.off[k] = offs[k];
   }
   rec[t] = r;
   if (rec32) {
@@ -1680,8 +1722,19 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     tet_grid_free(g);
     return fail(TET_ERR_DEVICE, "leb_build: shape table");
   }
-  hipLaunchKernelGGL(k_finalize, dim3(nblocks(cur, 128)), dim3(128), 0, st, cur, g->ids, g->verts, g->keys,
-                     g->max_depth, P, dens->density_scale, o.majorant_mode, shapes, g->rec, g->rec32, d_flag + 2);
+  // bucket index of the keys: about 4 tets per bucket
+  g->kbits = 4;
+  while (g->kbits < 24 && (key_buckets(g->kbits + 1) << 2) <= cur) g->kbits++;
+  g->kidx = (uint32_t*)dev_alloc((size_t)(key_buckets(g->kbits) + 1) * 4);
+  if (!g->kidx) {
+    tet_grid_free(g);
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: key index");
+  }
+  hipLaunchKernelGGL(k_key_index, dim3(nblocks(key_buckets(g->kbits) + 1, 256)), dim3(256), 0, st, cur, g->keys,
+                     g->kbits, g->kidx);
+  hipLaunchKernelGGL(k_finalize, dim3(nblocks(cur, 128)), dim3(128), 0, st, cur, g->ids, g->verts, g->keys, g->kidx,
+                     g->kbits, g->max_depth, P, dens->density_scale, o.majorant_mode, shapes, g->rec, g->rec32,
+                     d_flag + 2);
   int ferr = 0;
   he = hipMemcpyAsync(&ferr, d_flag + 2, 4, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipEventRecord(e1, st);

@@ -294,6 +294,7 @@ void tet_grid_free(tet_grid* g) {
   if (!g) return;
   dev_free(g->ids);
   dev_free(g->keys);
+  dev_free(g->kidx);
   dev_free(g->verts);
   dev_free(g->rec);
   dev_free(g->rec32);

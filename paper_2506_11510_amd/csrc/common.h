@@ -132,6 +132,25 @@ __host__ __device__ inline int id_depth(uint64_t id) {
 }
 __host__ __device__ inline int tag_of(int depth) { return 3 - depth % 3; }
 
+// Depth-first keys are id << (60 - depth), so a key's top 4 bits are its
+// root (8..13).  Bucket b of the key index holds the keys whose bits
+// 63..60-kbits, less 8 << kbits, equal b (6 << kbits buckets); kidx[b] is
+// the first index whose key is in bucket b or later, kidx[6 << kbits] = n.
+__host__ __device__ inline int64_t key_buckets(int kbits) { return 6ll << kbits; }
+
+// Last index whose key is <= key (-1 if none), searched within key's bucket.
+__device__ inline int64_t search_keys_idx(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ kidx,
+                                          int kbits, uint64_t key) {
+  const uint64_t b = (key >> (60 - kbits)) - (8ull << kbits);
+  int64_t lo = (int64_t)kidx[b] - 1, hi = kidx[b + 1];
+  while (hi - lo > 1) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] <= key) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Shape classes.  Up to translation and scale every tet of these grids is
 // one of a small set of shapes (with vertex order and tag): its edge
 // vectors x_j - x_0 divided by their common power of two.  shape_table()
@@ -313,6 +332,8 @@ struct tet_grid {
   tet_build_stats stats;
   uint64_t* ids;    // heap ids, depth-first order
   uint64_t* keys;   // depth-first keys (sorted ascending)
+  uint32_t* kidx;   // bucket index of the keys (key_bucket_index)
+  int32_t kbits;
   uint64_t* verts;  // 4 packed lattice vertices per tet
   tv::TetRec* rec;      // traversal records
   tv::TetRec32* rec32;  // compact records (NULL when the grid cannot use them)

@@ -72,8 +72,9 @@ struct SceneDesc {
   uint64_t pix0;     // first pixel in the concatenated images
   const void* rec;   // traversal records (TetRec32 or TetRec)
   const uint64_t* keys;
+  const uint32_t* kidx;
   int64_t n;
-  int32_t dmax, pad1;
+  int32_t dmax, kbits;
   float* out;
 };
 
@@ -182,8 +183,8 @@ __device__ inline void descend_point(int32_t v[4][3], uint64_t& h, uint32_t& cls
 // Tet containing p: the Kuhn root whose axis order sorts p's coordinates in
 // descending order, exact bisection-plane descent to the grid's depth, then
 // the last tet whose depth-first key is <= the key reached.
-__device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_t n, int dmax,
-                                       const uint32_t* __restrict__ shapes, float3 p) {
+__device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ kidx, int kbits,
+                                       int dmax, const uint32_t* __restrict__ shapes, float3 p) {
   const float c[3] = {p.x, p.y, p.z};
   int r = -1;
   if (c[0] >= c[1] && c[1] >= c[2]) r = 0;
@@ -211,14 +212,7 @@ __device__ inline int64_t locate_point(const uint64_t* __restrict__ keys, int64_
     if (d + 1 < dmax) descend_point<2>(v, h, cls, shapes, P);
     if (d + 2 < dmax) descend_point<1>(v, h, cls, shapes, P);
   }
-  uint64_t key = h << (60 - dmax);
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] <= key) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo - 1;
+  return search_keys_idx(keys, kidx, kbits, h << (60 - dmax));
 }
 
 struct TetMedium {
@@ -228,7 +222,9 @@ struct TetMedium {
   int64_t n;
   int dmax;
   const uint32_t* __restrict__ shapes;
-  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, shapes, p); }
+  const uint32_t* __restrict__ kidx;
+  int kbits;
+  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, kidx, kbits, dmax, shapes, p); }
   __device__ inline float sigma_at(uint32_t cell) const { return rec[cell].sigma; }
   // Exit of the tet along the segment whose direction-dot table is `tab`
   // (tab[N] = dir_N . d, tab[9 + N] = dir_N . o) from t: faces with
@@ -284,7 +280,9 @@ struct TetMedium32 {
   int64_t n;
   int dmax;
   const uint32_t* __restrict__ shapes;
-  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, n, dmax, shapes, p); }
+  const uint32_t* __restrict__ kidx;
+  int kbits;
+  __device__ inline int64_t locate(float3 p) const { return locate_point(keys, kidx, kbits, dmax, shapes, p); }
   __device__ inline float sigma_at(uint32_t cell) const { return __uint_as_float(rec[cell].w[3]); }
   __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
     const uint4* q = (const uint4*)(rec + cell);
@@ -466,6 +464,8 @@ __global__ __launch_bounds__(256) void k_raygen_batch(RenderArgs A, Med med, Ray
   Med m = med;
   m.rec = (decltype(m.rec))S.rec;
   m.keys = S.keys;
+  m.kidx = S.kidx;
+  m.kbits = S.kbits;
   m.n = S.n;
   m.dmax = S.dmax;
   entries[e] = camera_entry(S.fr, S.seed, m, px, py, (uint32_t)(py * S.fr.w + px), s);
@@ -1127,12 +1127,12 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
-    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes};
+    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
              : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
-    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes};
+    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
              : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else {
@@ -1229,10 +1229,10 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (g->rec32 && o.record_layout != 48) {
-    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes};
+    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = run_passes<TetMedium32, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
   } else {
-    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes};
+    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = run_passes<TetMedium, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
   }
   if (rc) return rc;
@@ -1348,6 +1348,8 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
     const tet_grid* g = grids[i];
     S.rec = use32 ? (const void*)g->rec32 : (const void*)g->rec;
     S.keys = g->keys;
+    S.kidx = g->kidx;
+    S.kbits = g->kbits;
     S.n = g->n;
     S.dmax = g->max_depth;
     S.out = outs[i];
@@ -1398,11 +1400,11 @@ static int batch_enqueue(const BatchState* B, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)B->scratch, 64);
   hipLaunchKernelGGL(k_batch_images, dim3(pblocks), dim3(256), 0, st, (const SceneDesc*)B->table, B->n, B->total_px, 1);
   if (B->use32) {
-    TetMedium32 m{nullptr, nullptr, 0, 0, B->shapes};
+    TetMedium32 m{nullptr, nullptr, 0, 0, B->shapes, nullptr, 0};
     hipLaunchKernelGGL(k_raygen_batch<TetMedium32>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
     hipLaunchKernelGGL((k_render<TetMedium32, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
   } else {
-    TetMedium m{nullptr, nullptr, 0, 0, B->shapes};
+    TetMedium m{nullptr, nullptr, 0, 0, B->shapes, nullptr, 0};
     hipLaunchKernelGGL(k_raygen_batch<TetMedium>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
     hipLaunchKernelGGL((k_render<TetMedium, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
   }
@@ -1524,7 +1526,7 @@ int locate_points(const tet_grid* g, const float* pts, int64_t count, int64_t* o
     void* p;
     ~Free() { if (p) dev_free(p); }
   } f_{tmp};
-  TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes};
+  TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
   hipLaunchKernelGGL(k_locate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, m, dp, count, dout);
   TV_HIP(hipGetLastError());
   if (!on_device) TV_HIP(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, st));
