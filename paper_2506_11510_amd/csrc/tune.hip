@@ -29,6 +29,10 @@ int render_grid(const tet_grid*, const tet_camera*, const tet_medium*, const tet
 
 namespace {
 
+// A candidate replaces the current choice only when its probe is faster by
+// more than this fraction: smaller differences are within the probes' noise.
+constexpr double kMinGain = 0.005;
+
 const char* kFields[5] = {"waves_per_simd", "event_wait", "batch_items", "block_size", "record_layout"};
 
 int32_t* field(tet_render_opts& o, int i) {
@@ -189,8 +193,11 @@ int autotune(const tet_grid* g, const tet_camera* cam, const tet_medium* med, co
     *ms = best;
     return TET_OK;
   };
+  {  // warm-up (first-launch costs), not recorded: the defaults are timed warm like every other candidate
+    tet_render_stats s;
+    if (int rc = render_grid(g, cam, med, light, ao.probe_spp, 0x7E57ull, &cur, out, 1, st, &s)) return rc;
+  }
   double cur_ms = 0.0;
-  if (int rc = probe(cur, &cur_ms)) return rc;  // warm-up of the defaults, then their timing
   if (int rc = probe(cur, &cur_ms)) return rc;
   for (int sweep = 0; sweep < 2; sweep++) {
     bool changed = false;
@@ -201,7 +208,7 @@ int autotune(const tet_grid* g, const tet_camera* cam, const tet_medium* med, co
         *field(t, i) = v;
         double ms = 0.0;
         if (int rc = probe(t, &ms)) return rc;
-        if (ms < cur_ms) {
+        if (ms < cur_ms * (1.0 - kMinGain)) {
           cur = t;
           cur_ms = ms;
           changed = true;
