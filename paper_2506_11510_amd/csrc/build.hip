@@ -208,11 +208,27 @@ __device__ inline bool vset_add(uint64_t* tab, uint64_t mask, uint64_t key) {
   }
 }
 
-// One atomic per wave for the number of new keys (called by every lane of
-// the wave, in uniform control flow).
+// One atomic per wave for a running count (called by every lane of the
+// wave, in uniform control flow).
 __device__ inline void count_new(bool added, uint32_t* count) {
   unsigned long long m = __ballot(added);
   if (m && __lane_id() == (int)__builtin_ctzll(m)) atomicAdd(count, (uint32_t)__popcll(m));
+}
+
+// The vertex count lives in kCountSlots words that the host sums: a block
+// adds its total once, to the slot of its index, so the atomics of a large
+// pass spread over kCountSlots addresses (on one address they serialise).
+// Called by every thread of the block, in uniform control flow.
+constexpr int kCountSlots = 16;
+
+__device__ inline void block_count(bool x, uint32_t* slots) {
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const unsigned long long m = __ballot(x);
+  if (m && __lane_id() == 0) atomicAdd(&s_n, (uint32_t)__popcll(m));
+  __syncthreads();
+  if (threadIdx.x == 0 && s_n) atomicAdd(&slots[blockIdx.x % kCountSlots], s_n);
 }
 
 __device__ inline void vset_insert(uint64_t* tab, uint64_t mask, uint64_t key, uint32_t* count) {
@@ -228,7 +244,7 @@ __global__ void k_vset_rehash(const uint64_t* __restrict__ old, int64_t ocap, ui
                               uint32_t* count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool added = i < ocap && old[i] != kEmptyKey && vset_add(tab, mask, old[i]);
-  count_new(added, count);
+  block_count(added, count);
 }
 
 __global__ void k_vset_seed(const uint64_t* __restrict__ verts, int64_t n, uint64_t* tab, uint64_t mask,
@@ -606,7 +622,7 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
   if (i < n)
     added = split_one(i, offs[i], cnt[i] != 1u, ids, verts, flags, nids, nverts, nflags, vset, vmask, nset, nmask,
                       cells, work);
-  count_new(added, vcount);
+  block_count(added, vcount);
 }
 
 
@@ -645,7 +661,7 @@ __global__ void k_split_append(int64_t count, const uint32_t* __restrict__ slist
       cell_mark(cells, z, true);
     }
   }
-  count_new(added, vcount);
+  block_count(added, vcount);
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
@@ -886,7 +902,7 @@ __global__ __launch_bounds__(256) void k_small_rounds(SmallRounds S, Pyramid P, 
       if (i < hi)
         added = split_one(i, (int64_t)carry + ex, x != 1u, ids, verts, flags, S.ids[src ^ 1], S.verts[src ^ 1],
                           S.flags[src ^ 1], S.vset, S.vmask, nullptr, 0, nullptr, S.work);
-      count_new(added, S.vcount);
+      block_count(added, S.vcount);
       carry += t;
     }
     if (!grid_barrier(&S.state[4], &S.state[5], ++nbar, &s_ok)) return;
@@ -1419,14 +1435,16 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     TV_HIP(hipMemcpyAsync(dcopy.p, dens->data, nvox * 4, hipMemcpyHostToDevice, st));
     d_dens = dcopy.as<float>();
   }
-  // small device scratch: [0] density flag, [1] max depth, [2] finalize error, [4..] counters
+  // small device scratch (32-bit words): [0] density flag, [1] max depth,
+  // [2] finalize error, [4] scan total, [5] running count of marked splits,
+  // [6, 6 + kCountSlots) vertex count slots, [24, 30) small-round state
   Buf misc;
-  if (!misc.ensure(64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scratch");
-  TV_HIP(hipMemsetAsync(misc.p, 0, 64, st));
+  if (!misc.ensure(128)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scratch");
+  TV_HIP(hipMemsetAsync(misc.p, 0, 128, st));
   int* d_flag = misc.as<int>();
   uint32_t* d_total = misc.as<uint32_t>() + 4;
-  uint32_t* d_vcount = misc.as<uint32_t>() + 5;
-  uint32_t* d_splitc = misc.as<uint32_t>() + 6;  // running count of marked splits
+  uint32_t* d_splitc = misc.as<uint32_t>() + 5;
+  uint32_t* d_vcount = misc.as<uint32_t>() + 6;
   hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d_dens, nvox, d_flag);
 
   // pyramid
@@ -1526,7 +1544,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   }
   int64_t nwork = 6;
   uint32_t* hbuf = nullptr;
-  TV_HIP(hipHostMalloc((void**)&hbuf, 64, hipHostMallocDefault));
+  TV_HIP(hipHostMalloc((void**)&hbuf, 128, hipHostMallocDefault));
   struct HostFree {
     uint32_t* p;
     ~HostFree() { if (p) (void)hipHostFree(p); }
@@ -1553,19 +1571,19 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     S.vset = vs.as<uint64_t>();
     S.vmask = vcap - 1;
     S.vcount = d_vcount;
-    S.state = misc.as<uint32_t>() + 8;
+    S.state = misc.as<uint32_t>() + 24;
     S.cur0 = cur;
     S.cap = small_cap;
     void* args[] = {&S, &P, &cc, &wp};
     TV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_small_rounds), dim3(small_blocks), dim3(256),
                                       args, 0, st));
-    TV_HIP(hipMemcpyAsync(hbuf + 4, S.state, 24, hipMemcpyDeviceToHost, st));
+    TV_HIP(hipMemcpyAsync(hbuf + 24, S.state, 24, hipMemcpyDeviceToHost, st));
     TV_HIP(hipStreamSynchronize(st));
-    if (hbuf[9]) return fail(TET_ERR_INTERNAL, "leb_build: grid barrier of the small rounds timed out");
-    cur = hbuf[4];
-    rounds = (int)hbuf[5];
-    nwork = 2 * (int64_t)hbuf[6];
-    done = hbuf[7] != 0;
+    if (hbuf[29]) return fail(TET_ERR_INTERNAL, "leb_build: grid barrier of the small rounds timed out");
+    cur = hbuf[24];
+    rounds = (int)hbuf[25];
+    nwork = 2 * (int64_t)hbuf[26];
+    done = hbuf[27] != 0;
     if (rounds & 1) A.swap_with(B);
   }
   while (!done) {
@@ -1584,11 +1602,12 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
                        cc, wp, vs.as<uint64_t>(), vcap - 1, d_splitc, splitc, nmain < 0 ? nullptr : cntb.as<uint32_t>());
     if (nmain < 0 && scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scan");
-    TV_HIP(hipMemcpyAsync(hbuf, d_total, 12, hipMemcpyDeviceToHost, st));
+    TV_HIP(hipMemcpyAsync(hbuf, d_total, (2 + kCountSlots) * 4, hipMemcpyDeviceToHost, st));
     TV_HIP(hipStreamSynchronize(st));
-    const int64_t total = nmain < 0 ? (int64_t)hbuf[0] : cur + (int64_t)(hbuf[2] - splitc);
-    const uint64_t vcount = hbuf[1];
-    splitc = hbuf[2];
+    const int64_t total = nmain < 0 ? (int64_t)hbuf[0] : cur + (int64_t)(hbuf[1] - splitc);
+    uint64_t vcount = 0;
+    for (int k = 0; k < kCountSlots; k++) vcount += hbuf[2 + k];
+    splitc = hbuf[1];
     if (total == cur) break;
     rounds++;
     if (total > o.max_tets) return fail(TET_ERR_CAPACITY, "leb_build: grid exceeds max_tets");
@@ -1600,7 +1619,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       if (!vs.ensure(ncap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
       hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(ncap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)ncap,
                          kEmptyKey);
-      TV_HIP(hipMemsetAsync(d_vcount, 0, 4, st));
+      TV_HIP(hipMemsetAsync(d_vcount, 0, kCountSlots * 4, st));
       hipLaunchKernelGGL(k_vset_rehash, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs_old.as<uint64_t>(),
                          (int64_t)vcap, vs.as<uint64_t>(), ncap - 1, d_vcount);
       vs_old.release();
