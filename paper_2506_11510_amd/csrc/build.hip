@@ -1074,130 +1074,204 @@ __device__ inline int root_of(const int64_t q3[3], const int un[3]) {
   return 5;
 }
 
-__global__ void k_finalize(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
-                           const uint64_t* __restrict__ keys, const uint32_t* __restrict__ kidx, int kbits, int dmax,
-                           Pyramid P, float scale, int majorant_mode, const uint32_t* __restrict__ shapes,
-                           TetRec* __restrict__ rec, TetRec32* __restrict__ rec32, int* __restrict__ err) {
-  int32_t ioff[4] = {0, 0, 0, 0};
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  uint64_t pv[4] = {verts[4 * t], verts[4 * t + 1], verts[4 * t + 2], verts[4 * t + 3]};
-  int64_t v[4][3];
+// Face f of the tet v: its three vertices (the others, in order) and the
+// opposite vertex (selects keep the arrays in registers).
+__device__ inline void face_of(const int64_t v[4][3], int f, int64_t fa[3], int64_t fb[3], int64_t fc[3],
+                               int64_t fo[3]) {
+  const int i0 = f == 0 ? 1 : 0, i1 = f <= 1 ? 2 : 1, i2 = f <= 2 ? 3 : 2;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const int64_t col[4] = {v[0][a], v[1][a], v[2][a], v[3][a]};
+    fa[a] = pick4(col, i0);
+    fb[a] = pick4(col, i1);
+    fc[a] = pick4(col, i2);
+    fo[a] = pick4(col, f);
+  }
+}
+
+__device__ inline void unpack_tet(const uint64_t* __restrict__ verts, int64_t t, uint64_t pv[4], int64_t v[4][3]) {
 #pragma unroll
   for (int j = 0; j < 4; j++) {
+    pv[j] = verts[4 * t + j];
     v[j][0] = vx(pv[j]);
     v[j][1] = vy(pv[j]);
     v[j][2] = vz(pv[j]);
   }
-  TetRec r;
-  // medium: extinction = scale * mean(D), majorant tight or scale * max(D)
-  int32_t lo[3], hi[3];
-  tet_box(pv, lo, hi);
-  float mn, mx;
-  double s, c;
-  box_stats(P, lo, hi, mn, mx, s, c);
-  double mean = s / c;
-  r.sigma = (float)((double)scale * mean);
-  r.majorant = majorant_mode == 1 ? (float)((double)scale * (double)mx) : r.sigma;
-  r.codes = 0;
-  r.pad = 0;
-  uint32_t nbr[4];
-  float offs[4];
+}
+
+// Records, first pass (one thread per tet): extinction, majorant, face
+// planes and codes, boundary links.  Interior faces are linked from one
+// side only: the two tets on a face see it with opposite outward normals,
+// and the tet that sees +dir_N (orientation bit 0) lists the face as
+// (t << 2 | f) for k_links, so every face is searched once and the
+// searches run on full waves.  One atomic per block for the list positions.
+constexpr int kRecordsBlock = 1024;
+
+__global__ __launch_bounds__(kRecordsBlock) void k_records(int64_t n, const uint64_t* __restrict__ verts, Pyramid P,
+                                                           float scale, int majorant_mode, TetRec* __restrict__ rec,
+                                                           TetRec32* __restrict__ rec32, uint32_t* __restrict__ items,
+                                                           int64_t item_cap, uint32_t* item_count,
+                                                           int* __restrict__ err) {
+  __shared__ uint32_t s_wave[kRecordsBlock / 64], s_base;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t owned = 0;  // bit f: this tet links face f
+  if (t < n) {
+    uint64_t pv[4];
+    int64_t v[4][3];
+    unpack_tet(verts, t, pv, v);
+    // medium: extinction = scale * mean(D), majorant tight or scale * max(D)
+    int32_t lo[3], hi[3];
+    tet_box(pv, lo, hi);
+    float mn, mx;
+    double s, c;
+    box_stats(P, lo, hi, mn, mx, s, c);
+    const double mean = s / c;
+    const float sigma = (float)((double)scale * mean);
+    const float majorant = majorant_mode == 1 ? (float)((double)scale * (double)mx) : sigma;
+    uint32_t codes = 0;
+    float offs[4];
+    int32_t ioff[4];
+#pragma unroll 1
+    for (int f = 0; f < 4; f++) {
+      int64_t fa3[3], fb3[3], fc3[3], fo3[3];
+      face_of(v, f, fa3, fb3, fc3, fo3);
+      int un[3];
+      int64_t off;
+      int code = -1;
+      if (face_normal(fa3, fb3, fc3, fo3, un, off)) code = dir_code(un);
+      if (code < 0) {
+        atomicOr(err, 2);
+        code = 0;
+      }
+      codes |= (uint32_t)code << (8 * f);
+      // boundary face: its three vertices share a coordinate equal to 0 or S
+      bool bnd = false;
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        const int64_t x = fa3[a];
+        if (fb3[a] == x && fc3[a] == x && (x == 0 || x == kLatS)) bnd = true;
+      }
+      if (bnd) {
+        rec[t].nbr[f] = kBoundary;
+        if (rec32) rec32[t].w[4 + f] = kLink27Boundary | ((uint32_t)code << 27);
+      } else if (!(code & 1)) {
+        owned |= 1u << f;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (k == f) {
+          offs[k] = ldexpf((float)off, -kLatBits);
+          ioff[k] = (int32_t)off;
+        }
+      }
+    }
+    // the record's other words (link words: above, or by k_links)
+    reinterpret_cast<float4*>(&rec[t])[0] = make_float4(offs[0], offs[1], offs[2], offs[3]);
+    reinterpret_cast<uint4*>(&rec[t])[2] =
+        make_uint4(codes, __float_as_uint(sigma), __float_as_uint(majorant), 0u);
+    if (rec32) {
+      uint64_t lo64 = ((uint64_t)(ioff[0] & 0x7FFFFF)) | ((uint64_t)(ioff[1] & 0x7FFFFF) << 23) |
+                      ((uint64_t)(ioff[2] & 0x3FFFF) << 46);
+      uint64_t hi64 = ((uint64_t)(ioff[2] & 0x7FFFFF) >> 18) | ((uint64_t)(ioff[3] & 0x7FFFFF) << 5);
+      reinterpret_cast<uint4*>(&rec32[t])[0] =
+          make_uint4((uint32_t)lo64, (uint32_t)(lo64 >> 32), (uint32_t)hi64, __float_as_uint(sigma));
+    }
+  }
+  // list positions: block prefix of the counts, one atomic per block
+  const uint32_t x = __popc(owned);
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_wave[wid] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < kRecordsBlock / 64; w++) {
+      const uint32_t c = s_wave[w];
+      s_wave[w] = run;
+      run += c;
+    }
+    s_base = run ? atomicAdd(item_count, run) : 0u;
+  }
+  __syncthreads();
+  int64_t pos = (int64_t)s_base + s_wave[wid] + (inc - x);
 #pragma unroll 1
   for (int f = 0; f < 4; f++) {
-    // face f: the vertices other than f, in order (selects keep the arrays
-    // in registers)
+    if (!((owned >> f) & 1u)) continue;
+    if (pos < item_cap) items[pos] = ((uint32_t)t << 2) | (uint32_t)f;
+    else atomicOr(err, 8);  // more interior faces than a conforming grid has
+    pos++;
+  }
+}
+
+// Records, second pass (one thread per listed face): the neighbour across
+// face f of tet t, from the tet holding a point just outside the face (the
+// face centroid pushed outward by a symbolic epsilon: exact descent, then
+// the key search), checked to share the face; writes both link words.
+__global__ void k_links(const uint32_t* __restrict__ items, const uint32_t* __restrict__ item_count, int64_t item_cap,
+                        int64_t n,
+                        const uint64_t* __restrict__ verts, const uint64_t* __restrict__ keys,
+                        const uint32_t* __restrict__ kidx, int kbits, int dmax, const uint32_t* __restrict__ shapes,
+                        TetRec* __restrict__ rec, TetRec32* __restrict__ rec32, int* __restrict__ err) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= min((int64_t)*item_count, item_cap)) return;
+  const uint32_t it = items[s];
+  const int64_t t = it >> 2;
+  const int f = (int)(it & 3u);
+  uint64_t pv[4];
+  int64_t v[4][3];
+  unpack_tet(verts, t, pv, v);
+  int64_t fa3[3], fb3[3], fc3[3], fo3[3];
+  face_of(v, f, fa3, fb3, fc3, fo3);
+  int un[3];
+  int64_t off;
+  int code = 0;
+  if (face_normal(fa3, fb3, fc3, fo3, un, off)) code = max(dir_code(un), 0);
+  uint32_t link = kBoundary;
+  int64_t q3[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) q3[a] = fa3[a] + fb3[a] + fc3[a];
+  const int root = root_of(q3, un);
+  if (root < 0) {
+    atomicOr(err, 4);
+  } else {
+    int32_t w[4][3], q3i[3] = {(int32_t)q3[0], (int32_t)q3[1], (int32_t)q3[2]};
+    root_verts(root, w);
+    uint64_t h = 8 + root;
+    uint32_t cls = shapes[kShapeWords + root];
+    for (int d = 0; d < dmax; d += 3) {
+      descend_perturbed<3>(w, h, cls, shapes, q3i, un);
+      if (d + 1 < dmax) descend_perturbed<2>(w, h, cls, shapes, q3i, un);
+      if (d + 2 < dmax) descend_perturbed<1>(w, h, cls, shapes, q3i, un);
+    }
+    const int64_t nb = search_keys_idx(keys, kidx, kbits, h << (60 - dmax));
+    // back face: the neighbour's vertex that is not on face f
     const int i0 = f == 0 ? 1 : 0, i1 = f <= 1 ? 2 : 1, i2 = f <= 2 ? 3 : 2;
-    int64_t fa3[3], fb3[3], fc3[3], fo3[3];
+    const uint64_t fa = pick4(pv, i0), fb = pick4(pv, i1), fc = pick4(pv, i2);
+    int bf = -1, hits = 0;
+    if (nb >= 0 && nb < n) {
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-      const int64_t col[4] = {v[0][a], v[1][a], v[2][a], v[3][a]};
-      fa3[a] = pick4(col, i0);
-      fb3[a] = pick4(col, i1);
-      fc3[a] = pick4(col, i2);
-      fo3[a] = pick4(col, f);
-    }
-    int un[3];
-    int64_t off;
-    int code = -1;
-    if (face_normal(fa3, fb3, fc3, fo3, un, off)) code = dir_code(un);
-    if (code < 0) {
-      atomicOr(err, 2);
-      code = 0;
-    }
-    const float offw = ldexpf((float)off, -kLatBits);
-    r.codes |= (uint32_t)code << (8 * f);
-    uint32_t link = kBoundary;
-    // boundary face: its three vertices share a coordinate equal to 0 or S
-    bool bnd = false;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-      const int64_t x = fa3[a];
-      if (fb3[a] == x && fc3[a] == x && (x == 0 || x == kLatS)) bnd = true;
-    }
-    if (!bnd) {
-      int64_t q3[3];
-#pragma unroll
-      for (int a = 0; a < 3; a++) q3[a] = fa3[a] + fb3[a] + fc3[a];
-      const int root = root_of(q3, un);
-      if (root < 0) {
-        atomicOr(err, 4);
-      } else {
-        int32_t w[4][3], q3i[3] = {(int32_t)q3[0], (int32_t)q3[1], (int32_t)q3[2]};
-        root_verts(root, w);
-        uint64_t h = 8 + root;
-        uint32_t cls = shapes[kShapeWords + root];
-        for (int d = 0; d < dmax; d += 3) {
-          descend_perturbed<3>(w, h, cls, shapes, q3i, un);
-          if (d + 1 < dmax) descend_perturbed<2>(w, h, cls, shapes, q3i, un);
-          if (d + 2 < dmax) descend_perturbed<1>(w, h, cls, shapes, q3i, un);
-        }
-        const int64_t nb = search_keys_idx(keys, kidx, kbits, h << (60 - dmax));
-        // back face: the neighbour's vertex that is not on face f
-        const uint64_t fa = pick4(pv, i0), fb = pick4(pv, i1), fc = pick4(pv, i2);
-        int bf = -1, hits = 0;
-        if (nb >= 0) {
-#pragma unroll
-          for (int j = 0; j < 4; j++) {
-            uint64_t x = verts[4 * nb + j];
-            if (x == fa || x == fb || x == fc) hits++;
-            else bf = j;
-          }
-        }
-        if (nb < 0 || nb == t || hits != 3 || bf < 0) atomicOr(err, 1);
-        else link = ((uint32_t)nb << 2) | (uint32_t)bf;
+      for (int j = 0; j < 4; j++) {
+        const uint64_t x = verts[4 * nb + j];
+        if (x == fa || x == fb || x == fc) hits++;
+        else bf = j;
       }
     }
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      if (k == f) {
-        nbr[k] = link;
-        offs[k] = offw;
-        ioff[k] = (int32_t)off;
-      }
+    if (nb < 0 || nb >= n || nb == t || hits != 3 || bf < 0) {
+      atomicOr(err, 1);
+    } else {
+      link = ((uint32_t)nb << 2) | (uint32_t)bf;
+      // the neighbour sees this face as -dir_N across its face bf
+      rec[nb].nbr[bf] = ((uint32_t)t << 2) | (uint32_t)f;
+      if (rec32) rec32[nb].w[4 + bf] = (uint32_t)t | ((uint32_t)(code ^ 1) << 27);
     }
   }
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    r.nbr[k] = nbr[k];
-    r.off[k] = offs[k];
-  }
-  rec[t] = r;
-  if (rec32) {
-    TetRec32 c;
-    uint64_t lo = ((uint64_t)(ioff[0] & 0x7FFFFF)) | ((uint64_t)(ioff[1] & 0x7FFFFF) << 23) |
-                  ((uint64_t)(ioff[2] & 0x3FFFF) << 46);
-    uint64_t hi = ((uint64_t)(ioff[2] & 0x7FFFFF) >> 18) | ((uint64_t)(ioff[3] & 0x7FFFFF) << 5);
-    c.w[0] = (uint32_t)lo;
-    c.w[1] = (uint32_t)(lo >> 32);
-    c.w[2] = (uint32_t)hi;
-    c.w[3] = __float_as_uint(r.sigma);
-    for (int f = 0; f < 4; f++) {
-      uint32_t l = r.nbr[f] == kBoundary ? kLink27Boundary : (r.nbr[f] >> 2);
-      c.w[4 + f] = l | (((r.codes >> (8 * f)) & 31u) << 27);
-    }
-    rec32[t] = c;
-  }
+  rec[t].nbr[f] = link;
+  if (rec32) rec32[t].w[4 + f] = (link == kBoundary ? kLink27Boundary : (link >> 2)) | ((uint32_t)code << 27);
 }
 
 // ---------------------------------------------------------------- host
@@ -1436,7 +1510,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     d_dens = dcopy.as<float>();
   }
   // small device scratch (32-bit words): [0] density flag, [1] max depth,
-  // [2] finalize error, [4] scan total, [5] running count of marked splits,
+  // [2] finalize error, [3] listed faces, [4] scan total, [5] running count of marked splits,
   // [6, 6 + kCountSlots) vertex count slots, [24, 30) small-round state
   Buf misc;
   if (!misc.ensure(128)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: scratch");
@@ -1751,9 +1825,20 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   }
   hipLaunchKernelGGL(k_key_index, dim3(nblocks(key_buckets(g->kbits) + 1, 256)), dim3(256), 0, st, cur, g->keys,
                      g->kbits, g->kidx);
-  hipLaunchKernelGGL(k_finalize, dim3(nblocks(cur, 128)), dim3(128), 0, st, cur, g->ids, g->verts, g->keys, g->kidx,
-                     g->kbits, g->max_depth, P, dens->density_scale, o.majorant_mode, shapes, g->rec, g->rec32,
+  // records, then the links of the listed faces (at most 2 per tet in a
+  // conforming grid)
+  Buf items;
+  const int64_t item_cap = 2 * cur + 64;
+  if (!items.ensure((size_t)item_cap * 4)) {
+    tet_grid_free(g);
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: face list");
+  }
+  uint32_t* d_items = misc.as<uint32_t>() + 3;
+  hipLaunchKernelGGL(k_records, dim3(nblocks(cur, kRecordsBlock)), dim3(kRecordsBlock), 0, st, cur, g->verts, P,
+                     dens->density_scale, o.majorant_mode, g->rec, g->rec32, items.as<uint32_t>(), item_cap, d_items,
                      d_flag + 2);
+  hipLaunchKernelGGL(k_links, dim3(nblocks(item_cap, 128)), dim3(128), 0, st, items.as<uint32_t>(), d_items, item_cap,
+                     cur, g->verts, g->keys, g->kidx, g->kbits, g->max_depth, shapes, g->rec, g->rec32, d_flag + 2);
   int ferr = 0;
   he = hipMemcpyAsync(&ferr, d_flag + 2, 4, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipEventRecord(e1, st);
