@@ -419,7 +419,9 @@ __global__ void k_mark(int64_t n, const uint64_t* __restrict__ verts, uint8_t* _
     const uint8_t fl = flags[i];
     if (fl & 1) {  // new leaves (flag 0) are k_want's
       uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
-      if (fl & 2) split = cells_touched(cells, v) && hanging(v, nset, nmask);
+      // checked leaves: the last pass's new vertices (after a dense pass,
+      // nset is the whole vertex set and there is no cell map)
+      if (fl & 2) split = (!cells || cells_touched(cells, v)) && hanging(v, nset, nmask);
       else split = hanging(v, vset, vmask);
       if (!split && !(fl & 2)) flags[i] = fl | 2;
       if (!slist) cnt[i] = split ? 2u : 1u;
@@ -1626,6 +1628,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   int rounds = 0;
   bool done = false;
   int64_t nmain = -1;  // >= 0 once the tail rounds append (leaves below nmain stay in key order)
+  bool dense_last = false;  // the last split pass kept no new-vertex set
   uint32_t splitc = 0;  // last value read of the running split count
   Buf anc;             // leaf below nmain each appended leaf descends from
   Buf cbox;            // tail rounds: cell box of every chunk of kChunk leaves
@@ -1664,8 +1667,10 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
     if (nmain < 0)
       hipLaunchKernelGGL(k_mark, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.verts.as<uint64_t>(),
-                         A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, ns.as<uint64_t>(),
-                         nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap), d_splitc, splitc, nullptr);
+                         A.flags.as<uint8_t>(), cntb.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1,
+                         dense_last ? vs.as<uint64_t>() : ns.as<uint64_t>(), dense_last ? vcap - 1 : nscap - 1,
+                         dense_last ? nullptr : (const uint32_t*)(ns.as<uint64_t>() + nscap), d_splitc, splitc,
+                         nullptr);
     else
       hipLaunchKernelGGL(k_mark_tail, dim3(nblocks(cur, kChunk * kTailChunks)), dim3(kChunk), 0, st, cur, nmain,
                          A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), vs.as<uint64_t>(), vcap - 1,
@@ -1707,19 +1712,27 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
     }
     if (!wk.ensure((size_t)splits * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
-    // the new-vertex set of this pass, at most half full
-    nscap = 1024;
-    while ((uint64_t)splits * 2 > nscap) nscap <<= 1;
-    if (!ns.ensure(nscap * 8 + kMapWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
-    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kMapWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
-                       (int64_t)(nscap + kMapWords / 2),
-                       kEmptyKey);
+    // A dense pass (more than leaves/8 splits: nearly every cell would be
+    // marked) keeps no new-vertex set or cell map; the next round's checked
+    // leaves probe the whole vertex set instead, which gives the same answer
+    // (they can only have gained new vertices).  Otherwise: the new-vertex
+    // set of this pass, at most half full, and its cell maps.
+    const bool dense = nmain < 0 && splits * 8 > cur;
+    dense_last = dense;
+    if (!dense) {
+      nscap = 1024;
+      while ((uint64_t)splits * 2 > nscap) nscap <<= 1;
+      if (!ns.ensure(nscap * 8 + kMapWords * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: new-vertex set");
+      hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(nscap + kMapWords / 2, 256)), dim3(256), 0, st, ns.as<uint64_t>(),
+                         (int64_t)(nscap + kMapWords / 2), kEmptyKey);
+    }
     uint32_t* cells = (uint32_t*)(ns.as<uint64_t>() + nscap);
     if (nmain < 0) {
       hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
                          A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
                          B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
-                         vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1, cells, wk.as<uint32_t>());
+                         vcap - 1, d_vcount, dense ? nullptr : ns.as<uint64_t>(), nscap - 1, cells,
+                         wk.as<uint32_t>());
       A.swap_with(B);
       // the tail: once few leaves split, the rounds after this one list the
       // splitting leaves and append children instead of compacting

@@ -93,6 +93,20 @@ def test_build_phases_bitexact(tv, tiny_density, max_tets):
         assert e.value.status == -3
 
 
+def test_build_host_rounds_only(tv, tiny_density):
+    """max_tets below 12 leaves no room for the cooperative rounds, so every
+    round runs from the host (the path of devices without cooperative
+    launch): the 6 roots bit-exact, and depth 1 (12 tets) a capacity error."""
+    say("case build host rounds only")
+    b = dict(TINY["build"], uniform_depth=0, max_tets=6)
+    g = gpu_build(tv, tiny_density, 64, TINY["camera"], b)
+    o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
+    assert_grids_equal(g.export(), o.export(), "host rounds depth 0")
+    with pytest.raises(tv.TetError) as e:
+        gpu_build(tv, tiny_density, 64, TINY["camera"], dict(TINY["build"], uniform_depth=1, max_tets=11))
+    assert e.value.status == -3
+
+
 def test_locate_matches_oracle(tv, tiny_density):
     say("case locate")
     b = dict(TINY["build"], want_mode=2, max_depth=15, rand_seed=7, rand_thresh=40000)
