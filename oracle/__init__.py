@@ -54,7 +54,8 @@ class OBuildOpts(ctypes.Structure):
 
 class ORenderOpts(ctypes.Structure):
     _fields_ = [("max_bounces", ctypes.c_int32), ("transmittance", ctypes.c_int32),
-                ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32)]
+                ("max_steps_per_path", ctypes.c_int64), ("sample_offset", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("emission", ctypes.c_float * 3)]
 
 
 class ORenderStats(ctypes.Structure):
@@ -91,6 +92,8 @@ def lib():
         L.oracle_grid_num_tets.restype = ctypes.c_int64
         L.oracle_grid_max_depth.argtypes = [vp]
         L.oracle_grid_export.argtypes = [vp] * 8
+        L.oracle_grid_set_channels.argtypes = [vp, vp, vp, vp, ctypes.c_int32]
+        L.oracle_grid_export_channels.argtypes = [vp, vp, vp, vp]
         L.oracle_grid_free.argtypes = [vp]
         L.oracle_grid_free.restype = None
         L.oracle_box_stats.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
@@ -192,8 +195,11 @@ def make_build_opts(b: dict) -> OBuildOpts:
 
 
 def make_render_opts(r: dict) -> ORenderOpts:
-    return ORenderOpts(int(r.get("max_bounces", 8)), int(r.get("transmittance", 0)),
-                       int(r.get("max_steps_per_path", 1 << 20)), int(r.get("sample_offset", 0)))
+    o = ORenderOpts(int(r.get("max_bounces", 8)), int(r.get("transmittance", 0)),
+                    int(r.get("max_steps_per_path", 1 << 20)), int(r.get("sample_offset", 0)),
+                    int(r.get("channels", 0)))
+    o.emission[:] = [float(x) for x in r.get("emission", (0.0, 0.0, 0.0))]
+    return o
 
 
 class Grid:
@@ -223,6 +229,24 @@ class Grid:
         _check(lib().oracle_grid_export(self._h, _vp(out["ids"]), _vp(out["verts"]), _vp(out["nbr"]),
                                         _vp(out["sigma"]), _vp(out["majorant"]), _vp(out["codes"]),
                                         _vp(out["offsets"])), "oracle_grid_export")
+        return out
+
+    def set_channels(self, n: int, temperature=None, albedo=None, g=None):
+        """Per-tet means of extra channel grids (n^3 FP32 each, x fastest;
+        None = absent), leb.c item 8."""
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32).reshape(-1) for a in (temperature, albedo, g)]
+        for a in arrs:
+            assert a is None or a.size == n ** 3
+        _check(lib().oracle_grid_set_channels(self._h, _vp(arrs[0]), _vp(arrs[1]), _vp(arrs[2]), int(n)),
+               "oracle_grid_set_channels")
+        self._channels = tuple(a is not None for a in arrs)
+
+    def export_channels(self) -> dict:
+        n = self.num_tets
+        have = getattr(self, "_channels", (False, False, False))
+        out = {k: (np.empty(n, np.float32) if h else None) for k, h in zip(("temperature", "albedo", "g"), have)}
+        _check(lib().oracle_grid_export_channels(self._h, _vp(out["temperature"]), _vp(out["albedo"]), _vp(out["g"])),
+               "oracle_grid_export_channels")
         return out
 
     def locate(self, pts: np.ndarray) -> np.ndarray:

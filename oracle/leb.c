@@ -34,6 +34,11 @@
  *   7. Face orientation codes: the outward normal of every face is one of 18
  *      directions (+-axes, +-face diagonals); code = 2 * (direction index) +
  *      sign, with the plane offset n_f . v in lattice units.
+ *   8. Extra channels (the paper's implementation also carries e.g.
+ *      temperature, albedo and phase-function parameters per tet).  Reading:
+ *      each channel given on its own n^3 voxel grid is reduced per tet like
+ *      the density, to the mean over the voxels of the tet's box (same box
+ *      rule and summation order), stored FP32.
  *
  * Coordinates: world = unit cube; lattice = world * 2^20 (integers, exact).
  * Heap ids: roots 8..13; children of h are 2h and 2h+1; depth = bits - 4.
@@ -776,6 +781,64 @@ int oracle_leb_build(const float* density, int32_t n, const ocam* cam, const obu
 int64_t oracle_grid_num_tets(const ogrid* g) { return g ? g->n : -1; }
 int32_t oracle_grid_max_depth(const ogrid* g) { return g ? g->max_depth : -1; }
 
+/* Item 8: per-tet means of up to three channel grids (temperature >= 0,
+ * albedo in [0, 1], g in (-1, 1); NULL = absent), each n^3 FP32, x
+ * fastest, covering the unit cube.  Replaces the grid's channels. */
+int oracle_grid_set_channels(ogrid* g, const float* temperature, const float* albedo, const float* gch, int32_t n) {
+  if (!g || n < 1 || n > (1 << 12) || (n & (n - 1))) return -1;
+  const float* src[3] = {temperature, albedo, gch};
+  int L = 0;
+  while ((1 << L) < n) L++;
+  int64_t nv = (int64_t)n * n * n;
+  for (int k = 0; k < 3; k++) {
+    if (!src[k]) continue;
+    for (int64_t i = 0; i < nv; i++) {
+      float x = src[k][i];
+      int ok = k == 0 ? (x >= 0.0f && !isinf(x)) : (k == 1 ? (x >= 0.0f && x <= 1.0f) : (x > -1.0f && x < 1.0f));
+      if (!ok) return -5;
+    }
+  }
+  for (int k = 0; k < 3; k++) {
+    free(g->ch[k]);
+    g->ch[k] = NULL;
+    if (!src[k]) continue;
+    bctx c;
+    memset(&c, 0, sizeof(c));
+    c.dens = src[k];
+    c.n = n;
+    c.L = L;
+    float* out = (float*)malloc((size_t)g->n * sizeof(float));
+    int rc = out ? build_pyramid(&c) : -2;
+    if (rc) {
+      free(out);
+      free_pyramid(&c);
+      return -2;
+    }
+    for (int64_t t = 0; t < g->n; t++) {
+      int32_t lo[3], hi[3];
+      tet_box((const int32_t(*)[3])(g->verts + 12 * t), lo, hi);
+      float mn, mx;
+      double sum, cnt;
+      box_stats(&c, lo, hi, &mn, &mx, &sum, &cnt);
+      out[t] = (float)(sum / cnt);
+    }
+    free_pyramid(&c);
+    g->ch[k] = out;
+  }
+  return 0;
+}
+
+int oracle_grid_export_channels(const ogrid* g, float* temperature, float* albedo, float* gch) {
+  if (!g) return -1;
+  float* dst[3] = {temperature, albedo, gch};
+  for (int k = 0; k < 3; k++) {
+    if (!dst[k]) continue;
+    if (!g->ch[k]) return -1;
+    memcpy(dst[k], g->ch[k], (size_t)g->n * sizeof(float));
+  }
+  return 0;
+}
+
 int oracle_grid_export(const ogrid* g, uint64_t* ids, int32_t* verts, uint32_t* nbr, float* sigma,
                        float* majorant, uint8_t* codes, int32_t* offsets) {
   if (!g) return -1;
@@ -801,6 +864,7 @@ void oracle_grid_free(ogrid* g) {
   free(g->offsets);
   free(g->hkeys);
   free(g->hvals);
+  for (int k = 0; k < 3; k++) free(g->ch[k]);
   free(g);
 }
 

@@ -87,6 +87,10 @@ int  oracle_locate(const ogrid* g, int64_t count, const float* pts, int64_t* out
 
 /* One walk of a straight segment (origin o, direction d, start tet) until the
  * boundary or max_out steps: tet sequence, exit faces and exit distances. */
+/* Extra channels per tet (leb.c item 8); NULL channel = absent. */
+int  oracle_grid_set_channels(ogrid* g, const float* temperature, const float* albedo, const float* gch, int32_t n);
+int  oracle_grid_export_channels(const ogrid* g, float* temperature, float* albedo, float* gch);
+
 int  oracle_walk(const ogrid* g, const float o[3], const float d[3], int64_t start,
                  int32_t max_out, int64_t* tets, int32_t* faces, float* texit, int32_t* n_out);
 
@@ -95,6 +99,8 @@ typedef struct {
   int32_t transmittance;      /* 0 analytic, 1 ratio tracking, 2 delta tracking */
   int64_t max_steps_per_path;
   int32_t sample_offset;
+  int32_t channels;           /* 1: use the grid's extra channels (transport.c) */
+  float emission[3];          /* radiance emitted per unit temperature (RGB) */
 } orender_opts;
 
 typedef struct { int64_t tet_steps, null_collisions, real_collisions, escapes, truncated; } orender_stats;

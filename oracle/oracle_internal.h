@@ -19,6 +19,9 @@ struct ogrid {
   float* majorant;        /* per-tet majorant (>= sigma) */
   uint8_t* codes;         /* 4 per tet: outward face orientation code */
   int32_t* offsets;       /* 4 per tet: lattice plane offset */
+  /* optional extra channels per tet (NULL = absent): temperature, albedo,
+   * phase parameter g -- each the mean over the tet's voxel box */
+  float* ch[3];
   /* id -> canonical index (open addressing) */
   uint64_t* hkeys;
   int64_t* hvals;

@@ -20,7 +20,15 @@
  *     environment added when the path leaves the grid; a camera ray that
  *     misses the grid sees the environment;
  *   - a path stops after max_bounces real collisions (after the light
- *     estimate at the last one); there is no Russian roulette.
+ *     estimate at the last one); there is no Russian roulette;
+ *   - extra channels (the paper's implementation carries e.g. temperature,
+ *     albedo and phase-function parameters per tet; it gives no formulas).
+ *     Reading: with channels on, a real collision in tet c first adds the
+ *     emitted radiance by the collision estimator, beta * (1 - a_c) * T_c *
+ *     emission (the absorbed fraction of the collision, FP32 in this order),
+ *     then uses the tet's albedo a_c and phase parameter g_c in place of the
+ *     medium's for the throughput, the light estimate and the phase sample.
+ *     Absent channels keep the medium's values (temperature: no emission).
  * Cell marching ("at most 4 ray/tetrahedron intersections per cell"; stored
  * normals let the direction rule faces out, leaving at most 3): for a face
  * with outward normal n (entries -1, 0, 1) and offset o_f,
@@ -539,19 +547,33 @@ static void trace_path(const medium_t* m, const frame32* fr, const omedium* med,
         q[7] = beta[0];
         *n_rec = (int32_t)rng.bounce;
       }
-      for (int c = 0; c < 3; c++) beta[c] = beta[c] * med->albedo;
+      /* extra channels of the collision's tet: emission (absorbed part of
+       * the collision: (1 - albedo) * temperature * emission colour, the
+       * collision estimator of the emitted radiance), then its albedo and
+       * phase parameter in place of the medium's */
+      float alb = med->albedo, gg = med->g;
+      if (op->channels) {
+        const ogrid* gr = m->g;
+        if (gr->ch[1]) alb = gr->ch[1][cell];
+        if (gr->ch[2]) gg = gr->ch[2][cell];
+        if (gr->ch[0]) {
+          float e = (1.0f - alb) * gr->ch[0][cell];
+          for (int c = 0; c < 3; c++) L[c] = L[c] + beta[c] * (e * op->emission[c]);
+        }
+      }
+      for (int c = 0; c < 3; c++) beta[c] = beta[c] * alb;
       float tr = shadow(m, cell, x, lt->sun_dir, op->transmittance, &rng, &b);
       if (tr < 0.0f) {
         st->truncated++;
         return;
       }
       float mu = (d[0] * lt->sun_dir[0] + d[1] * lt->sun_dir[1]) + d[2] * lt->sun_dir[2];
-      float ph = oracle_hg_eval(med->g, mu);
+      float ph = oracle_hg_eval(gg, mu);
       for (int c = 0; c < 3; c++) L[c] = L[c] + ((beta[c] * ph) * lt->sun_irradiance[c]) * tr;
       if ((int32_t)rng.bounce >= op->max_bounces) return;
       float v1 = rnd(&rng, ST_PHASE), v2 = rnd(&rng, ST_PHASE);
       float nd[3];
-      oracle_hg_direction(d, med->g, v1, v2, nd);
+      oracle_hg_direction(d, gg, v1, v2, nd);
       memcpy(d, nd, sizeof(d));
       memcpy(o, x, sizeof(o));
       t = 0.0f;
@@ -587,6 +609,11 @@ static int render_common(const medium_t* m, const ocam* cam, const omedium* med,
                          float* out, orender_stats* stats, int32_t threads, const nrc_hook* hk) {
   int rc = check_render_args(cam, med, lt, spp, op, pixels, pixels ? n_pixels : 0, out);
   if (rc) return rc;
+  if (op->channels) { /* tet grids that carry channels; not with a radiance cache */
+    if (m->kind != 0 || hk || (!m->g->ch[0] && !m->g->ch[1] && !m->g->ch[2])) return -1;
+    for (int c = 0; c < 3; c++)
+      if (!(op->emission[c] >= 0.0f) || isinf(op->emission[c])) return -1;
+  }
   frame32 fr;
   make_frame(cam, &fr);
   int64_t np = pixels ? n_pixels : (int64_t)cam->width * cam->height;
