@@ -111,6 +111,11 @@ typedef struct {
                                  this frame (frame seed = seed XOR 0x6A09E667F3BCC909), then the cache takes
                                  its Adam steps; the image uses the weights from before the call.  The
                                  cache is modified: no other call may use it meanwhile. */
+  int32_t channels;           /* 1: use the grid's extra channels (tet_grid_set_channels): a real collision
+                                 in tet c adds beta (1 - a_c) T_c emission, then takes the tet's albedo a_c
+                                 and phase parameter g_c in place of the medium's (absent channels: the
+                                 medium's values, no emission).  Single tet-grid renders without a cache. */
+  float emission[3];          /* radiance emitted per unit temperature (RGB, >= 0), with channels */
 } tet_render_opts;
 
 typedef struct {
@@ -219,6 +224,27 @@ void tet_autotune_opts_defaults(tet_autotune_opts* o);
 int tet_autotune(const tet_grid* grid, const tet_camera* camera, const tet_medium* medium, const tet_light* light,
                  const tet_autotune_opts* aopts /* NULL = defaults */, tet_render_opts* inout, void* hip_stream,
                  double* best_ms);
+
+/* Extra channels per tet (paper, "Volumetric Path Tracing": the
+ * implementation also carries e.g. temperature, albedo and phase-function
+ * parameters per tet).  Each given channel -- n^3 FP32 voxels, x fastest,
+ * over the unit cube, n a power of two <= 4096, any n -- is reduced per tet
+ * to the mean over the voxels of the tet's bounding box, the rule and
+ * summation order of the extinction.  temperature >= 0, albedo in [0, 1],
+ * g in (-1, 1), else TET_ERR_NUMERIC and the grid is unchanged; NULL =
+ * absent.  Replaces the grid's channels.  Buffers are the caller's. */
+typedef struct {
+  const float* temperature;
+  const float* albedo;
+  const float* g;
+  int32_t n;
+  int32_t on_device;
+} tet_channels;
+
+int tet_grid_set_channels(tet_grid* grid, const tet_channels* channels, void* hip_stream);
+/* Per-tet values (num_tets each; NULL = skip; TET_ERR_INVALID_ARG for a
+ * channel the grid does not have). */
+int tet_grid_export_channels(const tet_grid* grid, float* temperature, float* albedo, float* g, int32_t on_device);
 
 /* Point location (the grid-entry step of Algorithm 1): canonical index of
  * the tet containing each point (3 FP32 per point, inside [0,1]^3), or -1.

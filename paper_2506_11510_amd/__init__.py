@@ -84,6 +84,39 @@ class Grid:
                                     ptr.get("verts"), int(device), _stream()), "tet_grid_export")
         return out
 
+    def set_channels(self, n: int, temperature=None, albedo=None, g=None):
+        """Extra per-tet channels from n^3 FP32 grids (x fastest; numpy
+        arrays or CUDA tensors, all on one side; None = absent): each tet
+        gets the mean over its voxel box.  Renders use them with
+        render option channels=1 (emission = per-unit-temperature RGB)."""
+        arrs = [temperature, albedo, g]
+        dev = any(a is not None and not isinstance(a, np.ndarray) for a in arrs)
+        keep, ptrs = [], []
+        for a in arrs:
+            if a is None:
+                ptrs.append(None)
+                continue
+            if dev:
+                a = a.contiguous().float().reshape(-1)
+                ptrs.append(a.data_ptr())
+            else:
+                a = np.ascontiguousarray(a, np.float32).reshape(-1)
+                ptrs.append(a.ctypes.data)
+            assert a.shape[0] == n ** 3
+            keep.append(a)
+        c = _abi.TetChannels(ptrs[0], ptrs[1], ptrs[2], int(n), int(dev))
+        check(lib().tet_grid_set_channels(self._h, ctypes.byref(c), _stream()), "tet_grid_set_channels")
+        self._channels = tuple(a is not None for a in arrs)
+
+    def export_channels(self) -> dict:
+        """Per-tet channel values (numpy float32; None for absent ones)."""
+        n = self.num_tets
+        have = getattr(self, "_channels", (False, False, False))
+        out = {k: (np.empty(n, np.float32) if h else None) for k, h in zip(("temperature", "albedo", "g"), have)}
+        ptr = [None if v is None else ctypes.c_void_p(v.ctypes.data) for v in out.values()]
+        check(lib().tet_grid_export_channels(self._h, ptr[0], ptr[1], ptr[2], 0), "tet_grid_export_channels")
+        return out
+
     def locate(self, pts):
         """Tet index of each point (torch CUDA tensor (N,3) float32 -> int64
         tensor, or numpy on the host)."""

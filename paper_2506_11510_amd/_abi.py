@@ -54,7 +54,13 @@ class TetRenderOpts(ctypes.Structure):
                 ("samples_per_item", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("record_layout", ctypes.c_int32), ("batch_items", ctypes.c_int32), ("event_wait", ctypes.c_int32),
-                ("nrc", ctypes.c_void_p), ("nrc_train", ctypes.c_int32)]
+                ("nrc", ctypes.c_void_p), ("nrc_train", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("emission", ctypes.c_float * 3)]
+
+
+class TetChannels(ctypes.Structure):
+    _fields_ = [("temperature", ctypes.c_void_p), ("albedo", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("on_device", ctypes.c_int32)]
 
 
 class TetRenderStats(ctypes.Structure):
@@ -107,6 +113,8 @@ SIGNATURES = {
     "tet_grid_info": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(TetBuildStats)]),
     "tet_grid_export": (ctypes.c_int, [VP, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),
+    "tet_grid_set_channels": (ctypes.c_int, [VP, ctypes.POINTER(TetChannels), VP]),
+    "tet_grid_export_channels": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int32]),
     "tet_render": (ctypes.c_int, [VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium), ctypes.POINTER(TetLight),
                                   ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32,
                                   VP, ctypes.POINTER(TetRenderStats)]),
@@ -211,6 +219,8 @@ def make_render_opts(r: dict | None) -> TetRenderOpts:
     for k, v in (r or {}).items():
         if k == "nrc":
             o.nrc = v.handle if v is not None else None
+        elif k == "emission":
+            o.emission[:] = [float(x) for x in v]
         elif hasattr(o, k) and k != "reserved":
             setattr(o, k, type(getattr(o, k))(v))
     return o

@@ -82,6 +82,17 @@ __global__ void k_check_density(const float* __restrict__ d, int64_t n, int* __r
   }
 }
 
+// Extra channels: value ranges (kind 0 temperature >= 0 and finite, 1
+// albedo in [0, 1], 2 phase parameter g in (-1, 1)).
+__global__ void k_check_channel(const float* __restrict__ d, int64_t n, int kind, int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float v = d[i];
+    const bool ok = kind == 0 ? (v >= 0.0f && !isinf(v)) : (kind == 1 ? (v >= 0.0f && v <= 1.0f) : (v > -1.0f && v < 1.0f));
+    if (!ok) atomicOr(bad, 1);
+  }
+}
+
 // Statistics D(box) of the voxels overlapping the open lattice box (lo, hi):
 // voxel range [lo / vs, ceil(hi / vs)) per axis, summarised at the coarsest
 // pyramid level whose cells tile that range, cells combined in ascending
@@ -183,6 +194,20 @@ __device__ inline bool want(const Pyramid& P, const CamCrit& cc, const WantParam
   if (!(mean > 0.0)) return false;
   if (!(((double)mx - (double)mn) > wp.tau * mean)) return false;
   return want_camera(cc, v, depth);
+}
+
+// Per-tet value of a channel: the mean over the voxels of the tet's box
+// (the extinction's rule and summation order).
+__global__ void k_channel_means(int64_t n, const uint64_t* __restrict__ verts, Pyramid P, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint64_t v[4] = {verts[4 * t], verts[4 * t + 1], verts[4 * t + 2], verts[4 * t + 3]};
+  int32_t lo[3], hi[3];
+  tet_box(v, lo, hi);
+  float mn, mx;
+  double s, c;
+  box_stats(P, lo, hi, mn, mx, s, c);
+  out[t] = (float)(s / c);
 }
 
 // ---------------------------------------------------------------- vertex set
@@ -1455,6 +1480,29 @@ struct Leaves {
   }
 };
 
+// Min / max / FP64-sum pyramid of an n^3 grid (n = 2^L) on the device,
+// levels 1..L in lv; false when out of memory.
+static bool make_pyramid(const float* d, int32_t n, int L, Pyramid& P, std::vector<Buf>& lv, hipStream_t st) {
+  memset(&P, 0, sizeof(P));
+  P.dens = d;
+  P.n = n;
+  P.L = L;
+  lv = std::vector<Buf>(3 * (L + 1));
+  for (int l = 1; l <= L; l++) {
+    int64_t m = (int64_t)n >> l, cells = m * m * m;
+    if (!lv[3 * l].ensure(cells * 4) || !lv[3 * l + 1].ensure(cells * 4) || !lv[3 * l + 2].ensure(cells * 8))
+      return false;
+    P.mn[l] = lv[3 * l].as<float>();
+    P.mx[l] = lv[3 * l + 1].as<float>();
+    P.sum[l] = lv[3 * l + 2].as<double>();
+    hipLaunchKernelGGL(k_pyramid_level, dim3(nblocks(cells, 256)), dim3(256), 0, st, l == 1 ? d : nullptr,
+                       l == 1 ? nullptr : P.mn[l - 1], l == 1 ? nullptr : P.mx[l - 1],
+                       l == 1 ? nullptr : P.sum[l - 1], (int32_t)m, (float*)P.mn[l], (float*)P.mx[l],
+                       (double*)P.sum[l]);
+  }
+  return true;
+}
+
 // A device buffer grown keeping its first `keep` bytes.
 static bool grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t st) {
   if (bytes <= b.bytes) return true;
@@ -1525,23 +1573,8 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
 
   // pyramid
   Pyramid P;
-  memset(&P, 0, sizeof(P));
-  P.dens = d_dens;
-  P.n = n;
-  P.L = L;
-  std::vector<Buf> lv(3 * (L + 1));
-  for (int l = 1; l <= L; l++) {
-    int64_t m = (int64_t)n >> l, cells = m * m * m;
-    if (!lv[3 * l].ensure(cells * 4) || !lv[3 * l + 1].ensure(cells * 4) || !lv[3 * l + 2].ensure(cells * 8))
-      return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: pyramid");
-    P.mn[l] = lv[3 * l].as<float>();
-    P.mx[l] = lv[3 * l + 1].as<float>();
-    P.sum[l] = lv[3 * l + 2].as<double>();
-    hipLaunchKernelGGL(k_pyramid_level, dim3(nblocks(cells, 256)), dim3(256), 0, st, l == 1 ? d_dens : nullptr,
-                       l == 1 ? nullptr : P.mn[l - 1], l == 1 ? nullptr : P.mx[l - 1],
-                       l == 1 ? nullptr : P.sum[l - 1], (int32_t)m, (float*)P.mn[l], (float*)P.mx[l],
-                       (double*)P.sum[l]);
-  }
+  std::vector<Buf> lv;
+  if (!make_pyramid(d_dens, n, L, P, lv, st)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: pyramid");
   int flag = 0;
   TV_HIP(hipMemcpyAsync(&flag, d_flag, 4, hipMemcpyDeviceToHost, st));
   TV_HIP(hipStreamSynchronize(st));
@@ -1652,16 +1685,21 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
     S.cur0 = cur;
     S.cap = small_cap;
     void* args[] = {&S, &P, &cc, &wp};
-    TV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_small_rounds), dim3(small_blocks), dim3(256),
-                                      args, 0, st));
-    TV_HIP(hipMemcpyAsync(hbuf + 24, S.state, 24, hipMemcpyDeviceToHost, st));
-    TV_HIP(hipStreamSynchronize(st));
-    if (hbuf[29]) return fail(TET_ERR_INTERNAL, "leb_build: grid barrier of the small rounds timed out");
-    cur = hbuf[24];
-    rounds = (int)hbuf[25];
-    nwork = 2 * (int64_t)hbuf[26];
-    done = hbuf[27] != 0;
-    if (rounds & 1) A.swap_with(B);
+    // a refused cooperative launch (its blocks could not all be resident)
+    // changed nothing: the host-driven rounds below then do all the work
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_small_rounds), dim3(small_blocks), dim3(256), args,
+                                   0, st) != hipSuccess) {
+      (void)hipGetLastError();
+    } else {
+      TV_HIP(hipMemcpyAsync(hbuf + 24, S.state, 24, hipMemcpyDeviceToHost, st));
+      TV_HIP(hipStreamSynchronize(st));
+      if (hbuf[29]) return fail(TET_ERR_INTERNAL, "leb_build: grid barrier of the small rounds timed out");
+      cur = hbuf[24];
+      rounds = (int)hbuf[25];
+      nwork = 2 * (int64_t)hbuf[26];
+      done = hbuf[27] != 0;
+      if (rounds & 1) A.swap_with(B);
+    }
   }
   while (!done) {
     if (!cntb.ensure(cur * 4) || !offb.ensure(cur * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: counts");
@@ -1873,6 +1911,76 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   g->stats.num_tets = cur;
   g->stats.ms = ms;
   *out = g;
+  return TET_OK;
+}
+
+// Extra channels: checked first (all of them), then reduced per tet; the
+// grid's channels are replaced only when everything succeeded.
+int grid_set_channels(tet_grid* g, const tet_channels* ch, hipStream_t st) {
+  if (!g || !ch) return fail(TET_ERR_INVALID_ARG, "tet_grid_set_channels: NULL argument");
+  const int32_t n = ch->n;
+  if (n < 1 || n > 4096 || (n & (n - 1)))
+    return fail(TET_ERR_INVALID_ARG, "tet_grid_set_channels: n must be a power of two <= 4096");
+  int L = 0;
+  while ((1 << L) < n) L++;
+  const int64_t nvox = (int64_t)n * n * n;
+  const float* src[3] = {ch->temperature, ch->albedo, ch->g};
+  Buf copy[3], flag;
+  const float* d[3] = {nullptr, nullptr, nullptr};
+  if (!flag.ensure(4)) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_channels: scratch");
+  TV_HIP(hipMemsetAsync(flag.p, 0, 4, st));
+  for (int k = 0; k < 3; k++) {
+    if (!src[k]) continue;
+    d[k] = src[k];
+    if (!ch->on_device) {
+      if (!copy[k].ensure(nvox * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_channels: channel copy");
+      TV_HIP(hipMemcpyAsync(copy[k].p, src[k], nvox * 4, hipMemcpyHostToDevice, st));
+      d[k] = copy[k].as<float>();
+    }
+    hipLaunchKernelGGL(k_check_channel, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d[k], nvox, k, flag.as<int>());
+  }
+  int bad = 0;
+  TV_HIP(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  if (bad)
+    return fail(TET_ERR_NUMERIC, "tet_grid_set_channels: temperature < 0 or not finite, albedo outside [0, 1] or g "
+                                 "outside (-1, 1)");
+  float* out[3] = {nullptr, nullptr, nullptr};
+  struct Owned {
+    float** o;
+    bool keep = false;
+    ~Owned() {
+      if (!keep)
+        for (int k = 0; k < 3; k++) dev_free(o[k]);
+    }
+  } own{out};
+  for (int k = 0; k < 3; k++) {
+    if (!d[k]) continue;
+    out[k] = (float*)dev_alloc((size_t)g->n * 4);
+    Pyramid P;
+    std::vector<Buf> lv;
+    if (!out[k] || !make_pyramid(d[k], n, L, P, lv, st))
+      return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_channels: per-tet values");
+    hipLaunchKernelGGL(k_channel_means, dim3(nblocks(g->n, 256)), dim3(256), 0, st, g->n, g->verts, P, out[k]);
+    TV_HIP(hipGetLastError());
+    TV_HIP(hipStreamSynchronize(st));  // before the pyramid returns to the pool
+  }
+  for (int k = 0; k < 3; k++) {
+    dev_free(g->ch[k]);
+    g->ch[k] = out[k];
+  }
+  own.keep = true;
+  return TET_OK;
+}
+
+int grid_export_channels(const tet_grid* g, float* temperature, float* albedo, float* gch, int32_t on_device) {
+  if (!g) return fail(TET_ERR_INVALID_ARG, "tet_grid_export_channels: grid is NULL");
+  float* dst[3] = {temperature, albedo, gch};
+  for (int k = 0; k < 3; k++)
+    if (dst[k] && !g->ch[k]) return fail(TET_ERR_INVALID_ARG, "tet_grid_export_channels: the grid has no such channel");
+  for (int k = 0; k < 3; k++)
+    if (dst[k])
+      TV_HIP(hipMemcpy(dst[k], g->ch[k], (size_t)g->n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
   return TET_OK;
 }
 

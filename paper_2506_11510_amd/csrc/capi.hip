@@ -14,6 +14,8 @@
 namespace tv {
 
 int build_grid(const tet_density*, const tet_camera*, float, const tet_build_opts*, hipStream_t, tet_grid**);
+int grid_set_channels(tet_grid*, const tet_channels*, hipStream_t);
+int grid_export_channels(const tet_grid*, float*, float*, float*, int32_t);
 int render_grid(const tet_grid*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
                 const tet_render_opts*, float*, int32_t, hipStream_t, tet_render_stats*);
 int render_voxels(const tet_density*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
@@ -273,6 +275,14 @@ int tet_grid_export(const tet_grid* g, uint64_t* ids, uint32_t* nbr4, float* sig
   TV_GUARD(export_grid(g, ids, nbr4, sigma, majorant, verts12, on_device, (hipStream_t)hip_stream));
 }
 
+int tet_grid_set_channels(tet_grid* g, const tet_channels* channels, void* hip_stream) {
+  TV_GUARD(grid_set_channels(g, channels, (hipStream_t)hip_stream));
+}
+
+int tet_grid_export_channels(const tet_grid* g, float* temperature, float* albedo, float* gch, int32_t on_device) {
+  TV_GUARD(grid_export_channels(g, temperature, albedo, gch, on_device));
+}
+
 int tet_render(const tet_grid* g, const tet_camera* camera, const tet_medium* medium, const tet_light* light,
                int32_t spp, uint64_t seed, const tet_render_opts* opts, float* out_rgb, int32_t on_device,
                void* hip_stream, tet_render_stats* stats) {
@@ -298,6 +308,7 @@ void tet_grid_free(tet_grid* g) {
   dev_free(g->verts);
   dev_free(g->rec);
   dev_free(g->rec32);
+  for (int k = 0; k < 3; k++) dev_free(g->ch[k]);
   delete g;
 }
 

@@ -337,4 +337,5 @@ struct tet_grid {
   uint64_t* verts;  // 4 packed lattice vertices per tet
   tv::TetRec* rec;      // traversal records
   tv::TetRec32* rec32;  // compact records (NULL when the grid cannot use them)
+  float* ch[3];         // extra channels per tet: temperature, albedo, g (NULL = absent)
 };

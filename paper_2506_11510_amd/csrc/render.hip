@@ -128,6 +128,12 @@ struct RenderArgs {
   const SceneDesc* scenes;
   int32_t nscenes;
   uint64_t total_entries;
+  // extra channels per tet (null = absent) and the emitted radiance per
+  // unit temperature
+  const float* ch_t;
+  const float* ch_a;
+  const float* ch_g;
+  float emission[3];
 };
 
 // Pixel of training path j: floor(w npix / 2^24), w = the upper 24 bits of
@@ -616,7 +622,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         }
         jf = 0;
         jn = 0;
-        beta = beta * TV_ALBEDO;
+        // extra channels of the collision's tet: the emitted radiance by
+        // the collision estimator (absorbed part of the collision), then the
+        // tet's albedo in place of the medium's
+        float alb = TV_ALBEDO;
+        if (!BATCH && A.ch_a) alb = A.ch_a[cell];
+        if (!BATCH && A.ch_t) {
+          const float e = (1.0f - alb) * A.ch_t[cell];
+          L.x = L.x + beta * (e * A.emission[0]);
+          L.y = L.y + beta * (e * A.emission[1]);
+          L.z = L.z + beta * (e * A.emission[2]);
+        }
+        beta = beta * alb;
         dsave = d;
         o = x;
         d = TV_SUN;
@@ -630,7 +647,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
         float Tr = A.transmittance == 0 ? exp_neg(od) : od;
         float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
-        float ph = hg_pdf(TV_G, mu);
+        const float gg = (!BATCH && A.ch_g) ? A.ch_g[cell_x] : TV_G;  // the collision tet's phase parameter
+        float ph = hg_pdf(gg, mu);
         L.x = L.x + ((beta * ph) * TV_E(0)) * Tr;
         L.y = L.y + ((beta * ph) * TV_E(1)) * Tr;
         L.z = L.z + ((beta * ph) * TV_E(2)) * Tr;
@@ -638,7 +656,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           mode = M_FINISH;
         } else {
           uint2 v = uniform01x2(TV_SEED, pix, (uint32_t)s, bounce, kStreamPhase, 0);
-          d = hg_scatter(dsave, TV_G, u01(v.x), u01(v.y));
+          d = hg_scatter(dsave, gg, u01(v.x), u01(v.y));
           t = 0.0f;
           cell = cell_x;
           tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamFlight, jf++));
@@ -1056,6 +1074,14 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (nrc && !(nrc->opts.sigma_ref > 0.0f))
     return fail(TET_ERR_INVALID_ARG, "render: the radiance cache has no sigma_ref yet (train it or set one)");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
+  if (o.channels) {
+    if (o.channels != 1) return fail(TET_ERR_INVALID_ARG, "render: channels must be 0 or 1");
+    if (kind != 0 || nrc) return fail(TET_ERR_UNSUPPORTED, "render: channels need a tet grid and no radiance cache");
+    if (!g->ch[0] && !g->ch[1] && !g->ch[2]) return fail(TET_ERR_INVALID_ARG, "render: the grid has no channels");
+    for (int c = 0; c < 3; c++)
+      if (!(o.emission[c] >= 0.0f) || std::isinf(o.emission[c]))
+        return fail(TET_ERR_INVALID_ARG, "render: emission must be finite and >= 0");
+  }
   const uint32_t* shapes = shape_table();
   if (!shapes) return fail(TET_ERR_DEVICE, "render: shape table");
   int64_t npix = (int64_t)cam->width * cam->height;
@@ -1070,6 +1096,12 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   RenderArgs A;
   memset(&A, 0, sizeof(A));
   set_scene(A, cam, medm, light);
+  if (o.channels) {
+    A.ch_t = g->ch[0];
+    A.ch_a = g->ch[1];
+    A.ch_g = g->ch[2];
+    for (int c = 0; c < 3; c++) A.emission[c] = o.emission[c];
+  }
   A.spp = spp;
   A.pass_start = o.sample_offset;
   A.per_item = per_item;
@@ -1305,6 +1337,7 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
   else tet_render_opts_defaults(&o);
   if (int rc = check_render_opts(o)) return rc;
   if (o.nrc) return fail(TET_ERR_UNSUPPORTED, "render batch: no radiance cache in batches");
+  if (o.channels) return fail(TET_ERR_UNSUPPORTED, "render batch: no extra channels in batches");
   bool use32 = o.record_layout != 48;
   for (int i = 0; i < n; i++) {
     if (!grids[i] || !outs[i]) return fail(TET_ERR_INVALID_ARG, "render batch: NULL grid or output");

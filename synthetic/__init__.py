@@ -85,6 +85,20 @@ def plume(seed: int, n: int = 1024, keep_fraction: float = 0.05, peak: float = 5
     return raw
 
 
+def channels(seed: int, n: int) -> dict:
+    """Seeded extra-channel fields on an n^3 grid (float32, x fastest):
+    temperature >= 0 (a few hot blobs, peak ~4), albedo in [0.35, 1] and
+    phase parameter g in [-0.4, 0.85], both varying smoothly through the
+    cube."""
+    hot = blobs(seed, n, 4)
+    temperature = (4.0 * hot / max(float(hot.max()), 1e-6)).astype(np.float32)
+    a = blobs(seed + 1, n, 6)
+    albedo = (0.35 + 0.65 * a / max(float(a.max()), 1e-6)).astype(np.float32)
+    b = blobs(seed + 2, n, 6)
+    g = (-0.4 + 1.25 * b / max(float(b.max()), 1e-6)).astype(np.float32)
+    return dict(temperature=temperature, albedo=np.clip(albedo, 0.0, 1.0), g=np.clip(g, -0.4, 0.85))
+
+
 def _unit(v):
     l = math.sqrt(sum(x * x for x in v))
     return [x / l for x in v]

@@ -1,0 +1,110 @@
+"""GPU parity of the extra per-tet channels (temperature -> emission, per-tet
+albedo and phase parameter g) against the oracle: per-tet values bit-exact,
+images within the pixel bar, the constant-channel reduction exact, and the
+argument errors."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from parity import assert_image_parity
+
+pytestmark = pytest.mark.gpu
+
+EMISSION = [1.5, 0.9, 0.4]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tv():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_2506_11510_amd as tv
+    tv.lib()
+    return tv
+
+
+def both_grids(tv, name, ch_n, ch_seed):
+    import torch
+    sc = synthetic.scene(name)
+    d = sc["density_fn"]()
+    g = tv.leb_build(torch.from_numpy(d).cuda(), sc["n"], sc["camera"], build=sc["build"])
+    o = oracle.leb_build(d, sc["n"], sc["camera"], sc["build"])
+    ch = synthetic.channels(ch_seed, ch_n)
+    g.set_channels(ch_n, **ch)
+    o.set_channels(ch_n, **ch)
+    return sc, g, o
+
+
+@pytest.mark.parametrize("name,ch_n", [("tiny", 32), ("blobs_adaptive", 64)])
+def test_channel_values_bitexact(tv, name, ch_n):
+    say(f"case channels {name}: per-tet values, {ch_n}^3 channel grids")
+    sc, g, o = both_grids(tv, name, ch_n, 11)
+    a, b = g.export_channels(), o.export_channels()
+    for k in ("temperature", "albedo", "g"):
+        assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), k
+
+
+@pytest.mark.parametrize("name,layout", [("tiny", 32), ("tiny", 48), ("blobs_adaptive", 0)])
+def test_channels_render_parity(tv, name, layout):
+    say(f"case channels {name}: render, {layout}-byte records")
+    import torch
+    sc, g, o = both_grids(tv, name, 32, 21)
+    r = dict(sc["render"], channels=1, emission=EMISSION, record_layout=layout)
+    cam = sc["camera"]
+    spp = 16
+    img, st = tv.render(g, cam, sc["medium"], sc["light"], spp, 4321, r)
+    torch.cuda.synchronize()
+    ref, rst = o.render(cam, sc["medium"], sc["light"], spp, 4321, r, threads=8)
+    assert_image_parity(img.cpu().numpy(), ref, f"channels {name}")
+    assert st["real_collisions"] > 0
+    # the channels matter: the plain image differs
+    plain, _ = tv.render(g, cam, sc["medium"], sc["light"], spp, 4321, dict(sc["render"], record_layout=layout))
+    assert not np.allclose(plain.cpu().numpy(), img.cpu().numpy(), rtol=1e-3)
+
+
+def test_constant_channels_are_the_plain_tracer(tv):
+    say("case channels: constant channels = plain tracer")
+    import torch
+    sc = synthetic.scene("tiny")
+    g = tv.leb_build(torch.from_numpy(sc["density_fn"]()).cuda(), sc["n"], sc["camera"], build=sc["build"])
+    n = 16
+    g.set_channels(n, temperature=np.zeros(n ** 3, np.float32), albedo=np.full(n ** 3, 0.55, np.float32),
+                   g=np.full(n ** 3, -0.5, np.float32))
+    a, _ = tv.render(g, sc["camera"], dict(albedo=0.55, g=-0.5), sc["light"], 8, 99, sc["render"])
+    b, _ = tv.render(g, sc["camera"], dict(albedo=0.9, g=0.3), sc["light"], 8, 99,
+                     dict(sc["render"], channels=1, emission=EMISSION))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_channel_errors(tv):
+    say("case channels: errors")
+    import torch
+    sc = synthetic.scene("tiny")
+    g = tv.leb_build(torch.from_numpy(sc["density_fn"]()).cuda(), sc["n"], sc["camera"], build=sc["build"])
+    r = dict(sc["render"], channels=1, emission=EMISSION)
+    with pytest.raises(tv.TetError) as e:  # no channels yet
+        tv.render(g, sc["camera"], sc["medium"], sc["light"], 1, 1, r)
+    assert e.value.status == -1
+    n = 8
+    good = np.full(n ** 3, 0.5, np.float32)
+    g.set_channels(n, albedo=good)
+    for k, v in (("albedo", 1.25), ("g", -1.0), ("temperature", float("nan"))):
+        bad = good.copy()
+        bad[7] = v
+        with pytest.raises(tv.TetError) as e:
+            g.set_channels(n, **{k: bad})
+        assert e.value.status == -5
+    # the failed calls left the grid's channels as they were
+    assert np.all(g.export_channels()["albedo"] == np.float32(0.5))
+    with pytest.raises(tv.TetError):  # negative emission
+        tv.render(g, sc["camera"], sc["medium"], sc["light"], 1, 1, dict(r, emission=[1.0, -1.0, 0.0]))
+    with pytest.raises(tv.TetError):  # batches carry no channels
+        tv.render_batch([g], [sc["camera"]], [sc["medium"]], [sc["light"]], [1], [1], r)
