@@ -181,6 +181,35 @@ def dda_leg(tv, dev, sc, steps: int = 3) -> dict:
             "voxel_steps_per_s": round(st["tet_steps"] / (st["trace_ms"] / 1e3), 1)}
 
 
+def channels_leg(tv, torch, grid, sc, plain_ms: float, steps: int = 3) -> dict:
+    """Extra per-tet channels on the benchmark frame: temperature, albedo
+    and phase g grids at the density's resolution (seeded blobs), reduced
+    to per-tet box means on the device, then the frame rendered with
+    emission at real collisions and per-tet albedo and g."""
+    cam, spp = sc["camera"], sc["render"]["spp"]
+    import numpy as np
+    import synthetic
+    ch = {k: torch.from_numpy(v).cuda() for k, v in synthetic.channels(7, sc["n"]).items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.set_channels(sc["n"], **ch)
+    torch.cuda.synchronize()
+    set_ms = (time.perf_counter() - t0) * 1e3
+    ro = dict(sc["render"], channels=1, emission=[0.6, 0.35, 0.15])
+    tv.render(grid, cam, sc["medium"], sc["light"], spp, 3, ro)
+    ms, trace, st = [], [], None
+    for i in range(steps):
+        _, st = tv.render(grid, cam, sc["medium"], sc["light"], spp, 40 + i, ro)
+        ms.append(st["ms"])
+        trace.append(st["trace_ms"])
+    m = float(np.mean(ms))
+    samples = cam["width"] * cam["height"] * spp
+    return {"channels": "temperature, albedo, g (%d^3 each)" % sc["n"], "set_channels_ms": round(set_ms, 3),
+            "ms": round(m, 3), "trace_ms": round(float(np.mean(trace)), 3),
+            "msamples_per_s": round(samples / (m / 1e3) / 1e6, 3), "overhead_vs_plain": round(m / plain_ms, 3),
+            "tet_steps_per_frame": int(st["tet_steps"]), "real_collisions": int(st["real_collisions"])}
+
+
 def plume_leg(tv, torch) -> dict:
     """The production-scale configuration: 1024^3 plume density resident in
     HBM, adaptive LEB build (~86 M tets), 1024^2 renders at 32 and 1024 spp
@@ -368,6 +397,7 @@ def main():
                     help="JSON launch options for the tracing kernel (skips the autotuner), e.g. the ones a "
                          "previous run chose")
     ap.add_argument("--no-dda", action="store_true", help="skip the regular-grid (DDA) leg")
+    ap.add_argument("--no-channels", action="store_true", help="skip the extra-channel leg")
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 1024^3 plume leg (the radiance-cache leg then runs on the cloud)")
     ap.add_argument("--nrc-frames", type=int, default=100)
@@ -490,6 +520,8 @@ def main():
         res["batch"] = batch_leg(tv, torch, 64)
     if grid is None:
         grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+    if not args.no_channels:
+        res["channels"] = channels_leg(tv, torch, grid, sc, mean_render_ms)
     del dev
     plume = None
     if not args.no_plume:

@@ -94,6 +94,8 @@ def lib():
         L.oracle_grid_export.argtypes = [vp] * 8
         L.oracle_grid_set_channels.argtypes = [vp, vp, vp, vp, ctypes.c_int32]
         L.oracle_grid_export_channels.argtypes = [vp, vp, vp, vp]
+        L.oracle_grid_set_density_model.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_int32]
+        L.oracle_grid_export_density_model.argtypes = [vp, vp, vp]
         L.oracle_grid_free.argtypes = [vp]
         L.oracle_grid_free.restype = None
         L.oracle_box_stats.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
@@ -247,6 +249,24 @@ class Grid:
         out = {k: (np.empty(n, np.float32) if h else None) for k, h in zip(("temperature", "albedo", "g"), have)}
         _check(lib().oracle_grid_export_channels(self._h, _vp(out["temperature"]), _vp(out["albedo"]), _vp(out["g"])),
                "oracle_grid_export_channels")
+        return out
+
+    def set_density_model(self, model: int, density=None, n: int = 0, scale: float = 1.0):
+        """Extinction inside each tet (leb.c item 9): 0 constant, 1 linear
+        between trilinear vertex samples, 2 voxel lookup."""
+        d = None if density is None else np.ascontiguousarray(density, np.float32).reshape(-1)
+        assert d is None or d.size == n ** 3
+        _check(lib().oracle_grid_set_density_model(self._h, _vp(d), int(n), float(scale), int(model)),
+               "oracle_grid_set_density_model")
+        self._model = int(model)
+
+    def export_density_model(self) -> dict:
+        """Per-tet majorant and (linear model) coefficients (c0, gx, gy, gz)."""
+        n = self.num_tets
+        model = getattr(self, "_model", 0)
+        out = dict(majorant=np.empty(n, np.float32), coef=np.empty((n, 4), np.float32) if model == 1 else None)
+        _check(lib().oracle_grid_export_density_model(self._h, _vp(out["majorant"]), _vp(out["coef"])),
+               "oracle_grid_export_density_model")
         return out
 
     def locate(self, pts: np.ndarray) -> np.ndarray:

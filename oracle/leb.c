@@ -39,6 +39,17 @@
  *      each channel given on its own n^3 voxel grid is reduced per tet like
  *      the density, to the mean over the voxels of the tet's box (same box
  *      rule and summation order), stored FP32.
+ *   9. Density inside a tet (an extension: the paper keeps one value per
+ *      tet).  Model 1, linear: the density is sampled at each vertex by
+ *      trilinear interpolation of the volume (values at voxel centres
+ *      (i + 1/2) / n, indices clamped at the cube's faces; FP64, x then y
+ *      then z), times the scale, and interpolated linearly inside the tet;
+ *      the majorant is the largest vertex value, which bounds a linear
+ *      function on the tet.  Model 2, voxel lookup: the extinction at a
+ *      point is the scale times the voxel containing it; the majorant is
+ *      the scale times the largest voxel of the tet's box (the rule of
+ *      item 4; every interior point lies in that box).  Both make the null
+ *      collisions of delta tracking real ones rather than no-ops.
  *
  * Coordinates: world = unit cube; lattice = world * 2^20 (integers, exact).
  * Heap ids: roots 8..13; children of h are 2h and 2h+1; depth = bits - 4.
@@ -839,6 +850,140 @@ int oracle_grid_export_channels(const ogrid* g, float* temperature, float* albed
   return 0;
 }
 
+/* Item 9, model 1: the trilinear sample of the volume at lattice point v
+ * (FP64; unscaled). */
+static double trilinear_at(const float* dens, int32_t n, const int32_t v[3]) {
+  int64_t i0[3], i1[3];
+  double f[3];
+  for (int a = 0; a < 3; a++) {
+    double u = (double)v[a] * (double)n / (double)OR_LAT_S - 0.5; /* voxel-centre coordinates */
+    double fl = floor(u);
+    f[a] = u - fl;
+    int64_t lo = (int64_t)fl, hi = lo + 1;
+    i0[a] = lo < 0 ? 0 : (lo > n - 1 ? n - 1 : lo);
+    i1[a] = hi < 0 ? 0 : (hi > n - 1 ? n - 1 : hi);
+  }
+  double cz[2];
+  for (int c = 0; c < 2; c++) {
+    int64_t z = c ? i1[2] : i0[2];
+    double cy[2];
+    for (int b = 0; b < 2; b++) {
+      int64_t y = b ? i1[1] : i0[1];
+      double d0 = (double)dens[i0[0] + (int64_t)n * (y + (int64_t)n * z)];
+      double d1 = (double)dens[i1[0] + (int64_t)n * (y + (int64_t)n * z)];
+      cy[b] = (1.0 - f[0]) * d0 + f[0] * d1;
+    }
+    cz[c] = (1.0 - f[1]) * cy[0] + f[1] * cy[1];
+  }
+  return (1.0 - f[2]) * cz[0] + f[2] * cz[1];
+}
+
+/* Item 9, model 1: the affine function through the four vertex values rho
+ * (world units): gradient by Cramer's rule on the edge vectors e_k = v_k -
+ * v_0 (lattice integers; cross products and the determinant exact in int64),
+ * g = (dr1 (e2 x e3) + dr2 (e3 x e1) + dr3 (e1 x e2)) / det * 2^20 with
+ * dr_k = rho_k - rho_0, and c0 = rho_0 - g . v_0 (FP64, rounded to FP32). */
+static void linear_coefficients(const int32_t v[4][3], const double rho[4], float out[4]) {
+  int64_t e[3][3];
+  for (int k = 0; k < 3; k++)
+    for (int a = 0; a < 3; a++) e[k][a] = (int64_t)v[k + 1][a] - (int64_t)v[0][a];
+  int64_t c[3][3]; /* c[k] = e[k+1] x e[k+2] */
+  for (int k = 0; k < 3; k++) {
+    const int64_t* p = e[(k + 1) % 3];
+    const int64_t* q = e[(k + 2) % 3];
+    c[k][0] = p[1] * q[2] - p[2] * q[1];
+    c[k][1] = p[2] * q[0] - p[0] * q[2];
+    c[k][2] = p[0] * q[1] - p[1] * q[0];
+  }
+  int64_t det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+  double dr[3] = {rho[1] - rho[0], rho[2] - rho[0], rho[3] - rho[0]};
+  double g[3];
+  for (int a = 0; a < 3; a++)
+    g[a] = ((dr[0] * (double)c[0][a] + dr[1] * (double)c[1][a]) + dr[2] * (double)c[2][a]) / (double)det *
+           (double)OR_LAT_S;
+  double p0[3] = {(double)v[0][0] / OR_LAT_S, (double)v[0][1] / OR_LAT_S, (double)v[0][2] / OR_LAT_S};
+  double c0 = rho[0] - ((g[0] * p0[0] + g[1] * p0[1]) + g[2] * p0[2]);
+  out[0] = (float)c0;
+  out[1] = (float)g[0];
+  out[2] = (float)g[1];
+  out[3] = (float)g[2];
+}
+
+int oracle_grid_set_density_model(ogrid* g, const float* density, int32_t n, float scale, int32_t model) {
+  if (!g || model < 0 || model > 2) return -1;
+  if (model != 0) {
+    if (!density || n < 1 || n > (1 << 12) || (n & (n - 1)) || !(scale > 0.0f) || isinf(scale)) return -1;
+    int64_t nv = (int64_t)n * n * n;
+    for (int64_t i = 0; i < nv; i++)
+      if (!(density[i] >= 0.0f) || isinf(density[i])) return -5;
+  }
+  free(g->mmaj);
+  free(g->mcoef);
+  free(g->mdens);
+  g->mmaj = g->mcoef = g->mdens = NULL;
+  g->model = 0;
+  if (model == 0) return 0;
+  int64_t nv = (int64_t)n * n * n;
+  float* maj = (float*)malloc((size_t)g->n * sizeof(float));
+  float* coef = model == 1 ? (float*)malloc((size_t)g->n * 4 * sizeof(float)) : NULL;
+  float* dcopy = model == 2 ? (float*)malloc((size_t)nv * sizeof(float)) : NULL;
+  if (!maj || (model == 1 && !coef) || (model == 2 && !dcopy)) {
+    free(maj);
+    free(coef);
+    free(dcopy);
+    return -2;
+  }
+  int64_t vs = (int64_t)OR_LAT_S / n;
+  for (int64_t t = 0; t < g->n; t++) {
+    const int32_t(*v)[3] = (const int32_t(*)[3])(g->verts + 12 * t);
+    if (model == 1) {
+      double rho[4], mx = 0.0;
+      for (int j = 0; j < 4; j++) {
+        rho[j] = (double)scale * trilinear_at(density, n, v[j]);
+        if (j == 0 || rho[j] > mx) mx = rho[j];
+      }
+      maj[t] = (float)mx;
+      linear_coefficients(v, rho, coef + 4 * t);
+    } else {
+      /* largest voxel over the open bounding box, by direct scan */
+      int32_t lo[3], hi[3];
+      tet_box(v, lo, hi);
+      int64_t r0[3], r1[3];
+      for (int a = 0; a < 3; a++) {
+        r0[a] = lo[a] / vs;
+        r1[a] = (hi[a] + vs - 1) / vs;
+      }
+      float mx = 0.0f;
+      for (int64_t k = r0[2]; k < r1[2]; k++)
+        for (int64_t j = r0[1]; j < r1[1]; j++)
+          for (int64_t i = r0[0]; i < r1[0]; i++) {
+            float x = density[i + (int64_t)n * (j + (int64_t)n * k)];
+            if (x > mx) mx = x;
+          }
+      maj[t] = (float)((double)scale * (double)mx);
+    }
+  }
+  if (dcopy) memcpy(dcopy, density, (size_t)nv * sizeof(float));
+  g->mmaj = maj;
+  g->mcoef = coef;
+  g->mdens = dcopy;
+  g->mn = n;
+  g->mscale = scale;
+  g->model = model;
+  return 0;
+}
+
+int oracle_grid_export_density_model(const ogrid* g, float* majorant, float* coef) {
+  if (!g) return -1;
+  if (g->model == 0) return -1;
+  if (majorant) memcpy(majorant, g->mmaj, (size_t)g->n * sizeof(float));
+  if (coef) {
+    if (g->model != 1) return -1;
+    memcpy(coef, g->mcoef, (size_t)g->n * 4 * sizeof(float));
+  }
+  return 0;
+}
+
 int oracle_grid_export(const ogrid* g, uint64_t* ids, int32_t* verts, uint32_t* nbr, float* sigma,
                        float* majorant, uint8_t* codes, int32_t* offsets) {
   if (!g) return -1;
@@ -865,6 +1010,9 @@ void oracle_grid_free(ogrid* g) {
   free(g->hkeys);
   free(g->hvals);
   for (int k = 0; k < 3; k++) free(g->ch[k]);
+  free(g->mmaj);
+  free(g->mcoef);
+  free(g->mdens);
   free(g);
 }
 

@@ -91,6 +91,14 @@ int  oracle_locate(const ogrid* g, int64_t count, const float* pts, int64_t* out
 int  oracle_grid_set_channels(ogrid* g, const float* temperature, const float* albedo, const float* gch, int32_t n);
 int  oracle_grid_export_channels(const ogrid* g, float* temperature, float* albedo, float* gch);
 
+/* Density model inside the tets (leb.c item 9): model 0 constant per tet,
+ * 1 linear between trilinear vertex samples of `density` (n^3, x fastest),
+ * 2 the voxel of `density` containing the point; `scale` multiplies the
+ * density.  Export: per-tet majorant, and for model 1 the coefficients
+ * (c0, gx, gy, gz) of sigma(x) = ((c0 + gx x) + gy y) + gz z. */
+int  oracle_grid_set_density_model(ogrid* g, const float* density, int32_t n, float scale, int32_t model);
+int  oracle_grid_export_density_model(const ogrid* g, float* majorant, float* coef);
+
 int  oracle_walk(const ogrid* g, const float o[3], const float d[3], int64_t start,
                  int32_t max_out, int64_t* tets, int32_t* faces, float* texit, int32_t* n_out);
 

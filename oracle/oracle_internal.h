@@ -22,6 +22,15 @@ struct ogrid {
   /* optional extra channels per tet (NULL = absent): temperature, albedo,
    * phase parameter g -- each the mean over the tet's voxel box */
   float* ch[3];
+  /* density model inside each tet (leb.c item 9): 0 constant (sigma above),
+   * 1 linear, 2 voxel lookup; per-tet majorant; model 1: 4 coefficients per
+   * tet (c0, gx, gy, gz); model 2: a copy of the n^3 volume and its scale */
+  int32_t model;
+  float* mmaj;
+  float* mcoef;
+  float* mdens;
+  int32_t mn;
+  float mscale;
   /* id -> canonical index (open addressing) */
   uint64_t* hkeys;
   int64_t* hvals;

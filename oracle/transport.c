@@ -29,6 +29,10 @@
  *     then uses the tet's albedo a_c and phase parameter g_c in place of the
  *     medium's for the throughput, the light estimate and the phase sample.
  *     Absent channels keep the medium's values (temperature: no emission).
+ *   - density models inside a tet (leb.c item 9, an extension): the tet's
+ *     majorant comes from the model and each tentative collision evaluates
+ *     the extinction at its point; the analytic light transmittance of the
+ *     linear model integrates it exactly per segment (trapezoid rule).
  * Cell marching ("at most 4 ray/tetrahedron intersections per cell"; stored
  * normals let the direction rule faces out, leaving at most 3): for a face
  * with outward normal n (entries -1, 0, 1) and offset o_f,
@@ -381,6 +385,30 @@ static float cell_majorant(const medium_t* m, int64_t cell) {
   return m->kind == 0 ? m->g->majorant[cell] : m->scale * m->dens[cell];
 }
 
+/* Density models (leb.c item 9).  With a model on, a tet's majorant is the
+ * model's and the extinction is evaluated at each tentative collision point
+ * x (FP32): model 1 ((c0 + gx x) + gy y) + gz z, model 2 the scale times
+ * the voxel floor(x n) (indices clamped to the volume). */
+static int has_model(const medium_t* m) { return m->kind == 0 && m->g->model != 0; }
+
+static float model_majorant(const medium_t* m, int64_t cell) {
+  return has_model(m) ? m->g->mmaj[cell] : cell_majorant(m, cell);
+}
+
+static float point_sigma(const medium_t* m, int64_t cell, const float x[3]) {
+  const ogrid* g = m->g;
+  if (g->model == 1) {
+    const float* c = g->mcoef + 4 * cell;
+    return ((c[0] + c[1] * x[0]) + c[2] * x[1]) + c[3] * x[2];
+  }
+  int64_t n = g->mn, idx[3];
+  for (int a = 0; a < 3; a++) {
+    int64_t i = (int64_t)floorf(x[a] * (float)n);
+    idx[a] = i < 0 ? 0 : (i >= n ? n - 1 : i);
+  }
+  return g->mscale * g->mdens[idx[0] + n * (idx[1] + n * idx[2])];
+}
+
 static int64_t locate_cell(const medium_t* m, const float p[3]) {
   if (m->kind == 0) return or_locate_point(m->g, p);
   int64_t idx[3];
@@ -416,14 +444,28 @@ static float shadow(const medium_t* m, int64_t cell, const float x[3], const flo
     b->steps++;
     b->st->tet_steps++;
     if (f < 0) break;
-    if (mode == 0) {
+    if (mode == 0 && has_model(m)) {
+      /* linear model: the exact integral of a linear function over the
+       * segment, its length times the mean of the end values */
+      float xa[3], xb[3];
+      for (int i = 0; i < 3; i++) {
+        xa[i] = x[i] + t * w[i];
+        xb[i] = x[i] + te * w[i];
+      }
+      od = od + (0.5f * (point_sigma(m, cell, xa) + point_sigma(m, cell, xb))) * (te - t);
+    } else if (mode == 0) {
       od = od + cell_sigma(m, cell) * (te - t);
     } else {
-      float s = cell_sigma(m, cell), sb = cell_majorant(m, cell);
+      float s = cell_sigma(m, cell), sb = model_majorant(m, cell);
       if (sb > 0.0f) {
         float dtau = sb * (te - t);
         while (tau < dtau) {
           t = t + tau / sb;
+          if (has_model(m)) {
+            float xt[3];
+            for (int i = 0; i < 3; i++) xt[i] = x[i] + t * w[i];
+            s = point_sigma(m, cell, xt);
+          }
           if (mode == 1) {
             tr = tr * (1.0f - s / sb);
           } else {
@@ -504,13 +546,18 @@ static void trace_path(const medium_t* m, const frame32* fr, const omedium* med,
       st->escapes++;
       return;
     }
-    float s = cell_sigma(m, cell), sb = cell_majorant(m, cell);
+    float s = cell_sigma(m, cell), sb = model_majorant(m, cell);
     int collided = 0;
     float tc = 0.0f;
     if (sb > 0.0f) {
       float dtau = sb * (te - t);
       while (tau < dtau) {
         tc = t + tau / sb;
+        if (has_model(m)) { /* the extinction at the tentative collision */
+          float xt[3];
+          for (int i = 0; i < 3; i++) xt[i] = o[i] + tc * d[i];
+          s = point_sigma(m, cell, xt);
+        }
         int real = 1;
         if (s < sb) real = rnd(&rng, ST_FLIGHT) < s / sb;
         if (real) {
@@ -609,6 +656,9 @@ static int render_common(const medium_t* m, const ocam* cam, const omedium* med,
                          float* out, orender_stats* stats, int32_t threads, const nrc_hook* hk) {
   int rc = check_render_args(cam, med, lt, spp, op, pixels, pixels ? n_pixels : 0, out);
   if (rc) return rc;
+  if (has_model(m)) { /* no radiance cache; voxel lookups have no analytic light transmittance */
+    if (hk || (m->g->model == 2 && op->transmittance == 0)) return -1;
+  }
   if (op->channels) { /* tet grids that carry channels; not with a radiance cache */
     if (m->kind != 0 || hk || (!m->g->ch[0] && !m->g->ch[1] && !m->g->ch[2])) return -1;
     for (int c = 0; c < 3; c++)
@@ -730,7 +780,7 @@ int oracle_nrc_collect(const ogrid* g, const ocam* cam, const omedium* med, cons
                        float* sigma, float* target, int32_t* tag, int64_t* count, int32_t* path_pixel, float* path_L,
                        int32_t threads) {
   if (!g || n_paths < 0 || n_paths > (1 << 26) || max_vertices < 1 || max_vertices > 16 || !pos || !dir || !sigma ||
-      !target || !tag || !count)
+      !target || !tag || !count || g->model != 0 || opts->channels)
     return -1;
   int rc = check_render_args(cam, med, light, 1, opts, NULL, 0, target);
   if (rc) return rc;
