@@ -84,7 +84,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"])
-            if "k_render<" in r["Kernel_Name"] and ", 0, false>" in r["Kernel_Name"]:
+            if "k_render<" in r["Kernel_Name"] and ", 0, false, false>" in r["Kernel_Name"]:
                 trace.append(v)
             elif "copyBuffer" in r["Kernel_Name"]:
                 copies.append(v)
@@ -208,6 +208,53 @@ def channels_leg(tv, torch, grid, sc, plain_ms: float, steps: int = 3) -> dict:
             "ms": round(m, 3), "trace_ms": round(float(np.mean(trace)), 3),
             "msamples_per_s": round(samples / (m / 1e3) / 1e6, 3), "overhead_vs_plain": round(m / plain_ms, 3),
             "tet_steps_per_frame": int(st["tet_steps"]), "real_collisions": int(st["real_collisions"])}
+
+
+def density_model_leg(tv, torch, dev, sc, plain_ms: float, steps: int = 3) -> dict:
+    """Density models inside the tets on the benchmark frame: linear between
+    trilinear vertex samples (analytic light transmittance, as the plain
+    frame, and ratio-tracked) and voxel lookup (ratio-tracked light), on a
+    fresh grid of the same build; the voxel model is set beside the
+    regular-grid tracer with the same light estimator (equal in
+    expectation: image RMSE against it next to the RMSE between two
+    regular-grid renders)."""
+    import numpy as np
+    cam, spp = sc["camera"], sc["render"]["spp"]
+    scale = sc["build"]["density_scale"]
+    g = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+    out = {}
+    imgs = {}
+    for name, model, trans in (("linear", 1, 0), ("linear_ratio_light", 1, 1), ("voxel", 2, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.set_density_model(model, dev, sc["n"], scale)
+        torch.cuda.synchronize()
+        set_ms = (time.perf_counter() - t0) * 1e3
+        ro = dict(sc["render"], transmittance=trans)
+        tv.render(g, cam, sc["medium"], sc["light"], spp, 3, ro)
+        ms, trace, st = [], [], None
+        for i in range(steps):
+            img, st = tv.render(g, cam, sc["medium"], sc["light"], spp, 50 + i, ro)
+            ms.append(st["ms"])
+            trace.append(st["trace_ms"])
+        imgs[name] = img.cpu().numpy()
+        m = float(np.mean(ms))
+        out[name] = {"transmittance": ["analytic", "ratio tracking"][trans], "set_model_ms": round(set_ms, 3),
+                     "ms": round(m, 3), "trace_ms": round(float(np.mean(trace)), 3),
+                     "msamples_per_s": round(cam["width"] * cam["height"] * spp / (m / 1e3) / 1e6, 3),
+                     "vs_plain_ms": round(m / plain_ms, 3), "tet_steps_per_frame": int(st["tet_steps"]),
+                     "null_collisions": int(st["null_collisions"]), "real_collisions": int(st["real_collisions"])}
+    ro = dict(sc["render"], transmittance=1)
+    d1, sd = tv.dda_render(dev, sc["n"], scale, cam, sc["medium"], sc["light"], spp, 60, ro)
+    d2, _ = tv.dda_render(dev, sc["n"], scale, cam, sc["medium"], sc["light"], spp, 61, ro)
+    d1, d2 = d1.cpu().numpy(), d2.cpu().numpy()
+    out["voxel_vs_regular_grid"] = {
+        "image_mean_tet_voxel": float(imgs["voxel"].mean()), "image_mean_regular_grid": float(d1.mean()),
+        "rmse_tet_voxel_vs_regular_grid": float(np.sqrt(((imgs["voxel"] - d1) ** 2).mean())),
+        "rmse_regular_grid_two_seeds": float(np.sqrt(((d2 - d1) ** 2).mean())),
+        "regular_grid_ms": round(sd["ms"], 3)}
+    del g
+    return out
 
 
 def plume_leg(tv, torch) -> dict:
@@ -398,6 +445,7 @@ def main():
                          "previous run chose")
     ap.add_argument("--no-dda", action="store_true", help="skip the regular-grid (DDA) leg")
     ap.add_argument("--no-channels", action="store_true", help="skip the extra-channel leg")
+    ap.add_argument("--no-density-models", action="store_true", help="skip the density-model leg")
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 1024^3 plume leg (the radiance-cache leg then runs on the cloud)")
     ap.add_argument("--nrc-frames", type=int, default=100)
@@ -506,7 +554,7 @@ def main():
         "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated")},
         "image_mean": float(img.mean()),
         "roofline": {"bound": "hbm",
-                     "kernel": "k_render<TetMedium%s, %d, 0>" % ("32" if sc["render"]["record_layout"] == 32 else "",
+                     "kernel": "k_render<TetMedium%s, %d, 0, false, false>" % ("32" if sc["render"]["record_layout"] == 32 else "",
                                                                  sc["render"]["waves_per_simd"]), "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
@@ -522,6 +570,8 @@ def main():
         grid = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
     if not args.no_channels:
         res["channels"] = channels_leg(tv, torch, grid, sc, mean_render_ms)
+    if not args.no_density_models:
+        res["density_models"] = density_model_leg(tv, torch, dev, sc, mean_render_ms)
     del dev
     plume = None
     if not args.no_plume:

@@ -246,6 +246,38 @@ int tet_grid_set_channels(tet_grid* grid, const tet_channels* channels, void* hi
  * channel the grid does not have). */
 int tet_grid_export_channels(const tet_grid* grid, float* temperature, float* albedo, float* g, int32_t on_device);
 
+/* Density inside a tet (an extension of the paper's one density value per
+ * tet, "Volumetric Path Tracing"; delta tracking against per-tet majorants
+ * with true null collisions).  model:
+ *   0  constant per tet (the build's extinction; density may be NULL);
+ *   1  linear: the volume is sampled at each vertex by trilinear
+ *      interpolation (values at voxel centres (i + 1/2) / n, indices clamped
+ *      at the cube's faces; FP64, x then y then z) times density_scale, and
+ *      interpolated linearly inside the tet, evaluated at a point as
+ *      ((c0 + gx x) + gy y) + gz z in FP32 from per-tet coefficients
+ *      rounded from FP64; majorant = the largest vertex value;
+ *   2  voxel lookup: extinction at a point = density_scale * the voxel
+ *      floor(x n) (indices clamped); majorant = density_scale * the largest
+ *      voxel overlapping the tet's open bounding box.  The library keeps a
+ *      device copy of the volume (n^3 * 4 bytes).
+ * The volume is any n^3 FP32 grid (n a power of two <= 4096, values finite
+ * and >= 0, else TET_ERR_NUMERIC and the grid unchanged), normally the one
+ * the grid was built from; the caller's buffer is only read.  Renders of
+ * the grid then use the model (each tentative collision evaluates the
+ * extinction at its point; the analytic light transmittance of model 1
+ * integrates it exactly per segment); model 2 needs ratio or delta
+ * tracking for the light (transmittance 1 or 2, else TET_ERR_INVALID_ARG),
+ * and neither model renders in batches or with a radiance cache
+ * (TET_ERR_UNSUPPORTED).  Device memory beyond the grid: copies of its
+ * records carrying the model's majorant (48 bytes per tet, plus 32 with
+ * compact records), 4 bytes per tet of majorant, and 16 bytes per tet of
+ * coefficients (model 1) or the volume (model 2). */
+int tet_grid_set_density_model(tet_grid* grid, const tet_density* density, int32_t model, void* hip_stream);
+/* The model's per-tet majorant (num_tets floats) and, for model 1, the
+ * coefficients (num_tets x {c0, gx, gy, gz}); NULL = skip.
+ * TET_ERR_INVALID_ARG when the grid has no model (or coef for model 2). */
+int tet_grid_export_density_model(const tet_grid* grid, float* majorant, float* coef, int32_t on_device);
+
 /* Point location (the grid-entry step of Algorithm 1): canonical index of
  * the tet containing each point (3 FP32 per point, inside [0,1]^3), or -1.
  * pts and out live on the same side (on_device). */

@@ -117,6 +117,34 @@ class Grid:
         check(lib().tet_grid_export_channels(self._h, ptr[0], ptr[1], ptr[2], 0), "tet_grid_export_channels")
         return out
 
+    def set_density_model(self, model: int, density=None, n: int = 0, scale: float = 1.0):
+        """Extinction inside each tet: 0 constant (the build's), 1 linear
+        between trilinear vertex samples of `density` (n^3, x fastest;
+        numpy or CUDA tensor), 2 voxel lookup in it; `scale` multiplies
+        the density."""
+        if model == 0 and density is None:
+            ds = None
+        else:
+            if not isinstance(density, np.ndarray):
+                density = density.contiguous().float().reshape(-1)
+            else:
+                density = np.ascontiguousarray(density, np.float32).reshape(-1)
+            assert density.shape[0] == n ** 3
+            ds = density_struct(density, n, scale)
+        check(lib().tet_grid_set_density_model(self._h, ctypes.byref(ds) if ds is not None else None, int(model),
+                                               _stream()), "tet_grid_set_density_model")
+        self._model = int(model)
+
+    def export_density_model(self) -> dict:
+        """Per-tet majorant and (linear model) coefficients (c0, gx, gy, gz),
+        numpy float32."""
+        n = self.num_tets
+        model = getattr(self, "_model", 0)
+        out = dict(majorant=np.empty(n, np.float32), coef=np.empty((n, 4), np.float32) if model == 1 else None)
+        ptr = [None if v is None else ctypes.c_void_p(v.ctypes.data) for v in out.values()]
+        check(lib().tet_grid_export_density_model(self._h, ptr[0], ptr[1], 0), "tet_grid_export_density_model")
+        return out
+
     def locate(self, pts):
         """Tet index of each point (torch CUDA tensor (N,3) float32 -> int64
         tensor, or numpy on the host)."""

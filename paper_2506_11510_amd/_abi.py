@@ -115,6 +115,8 @@ SIGNATURES = {
     "tet_grid_export": (ctypes.c_int, [VP, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),
     "tet_grid_set_channels": (ctypes.c_int, [VP, ctypes.POINTER(TetChannels), VP]),
     "tet_grid_export_channels": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int32]),
+    "tet_grid_set_density_model": (ctypes.c_int, [VP, ctypes.POINTER(TetDensity), ctypes.c_int32, VP]),
+    "tet_grid_export_density_model": (ctypes.c_int, [VP, VP, VP, ctypes.c_int32]),
     "tet_render": (ctypes.c_int, [VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium), ctypes.POINTER(TetLight),
                                   ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32,
                                   VP, ctypes.POINTER(TetRenderStats)]),

@@ -1984,4 +1984,238 @@ int grid_export_channels(const tet_grid* g, float* temperature, float* albedo, f
   return TET_OK;
 }
 
+// ---------------------------------------------------------------- density models
+// Trilinear sample (FP64, unscaled) of the volume at lattice point (x, y, z):
+// voxel-centre coordinates u = v n / 2^20 - 1/2, indices clamped to the
+// volume, interpolated along x, then y, then z.
+__device__ inline double trilinear_at(const float* __restrict__ d, int32_t n, const int64_t p[3]) {
+  int64_t i0[3], i1[3];
+  double f[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const double u = (double)p[a] * (double)n / (double)kLatS - 0.5;
+    const double fl = floor(u);
+    f[a] = u - fl;
+    const int64_t lo = (int64_t)fl, hi = lo + 1;
+    i0[a] = lo < 0 ? 0 : (lo > n - 1 ? n - 1 : lo);
+    i1[a] = hi < 0 ? 0 : (hi > n - 1 ? n - 1 : hi);
+  }
+  double cz[2];
+#pragma unroll
+  for (int c = 0; c < 2; c++) {
+    const int64_t z = c ? i1[2] : i0[2];
+    double cy[2];
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int64_t y = b ? i1[1] : i0[1];
+      const double d0 = (double)d[i0[0] + (int64_t)n * (y + (int64_t)n * z)];
+      const double d1 = (double)d[i1[0] + (int64_t)n * (y + (int64_t)n * z)];
+      cy[b] = (1.0 - f[0]) * d0 + f[0] * d1;
+    }
+    cz[c] = (1.0 - f[1]) * cy[0] + f[1] * cy[1];
+  }
+  return (1.0 - f[2]) * cz[0] + f[2] * cz[1];
+}
+
+// Model 1 (one thread per tet): vertex values rho_j = scale * trilinear
+// sample; majorant = max rho_j; the affine function through them, gradient
+// by Cramer's rule on the lattice edge vectors e_k = v_k - v_0 (cross
+// products and determinant exact in int64), g = (dr_1 (e_2 x e_3) + dr_2
+// (e_3 x e_1) + dr_3 (e_1 x e_2)) / det * 2^20 (world units), c0 = rho_0 -
+// g . v_0; FP64, rounded to FP32.
+__global__ void k_model_linear(int64_t n, const uint64_t* __restrict__ verts, const float* __restrict__ d,
+                               int32_t nv, double scale, float* __restrict__ maj, float4* __restrict__ coef) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int64_t v[4][3];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const uint64_t pv = verts[4 * t + j];
+    v[j][0] = vx(pv);
+    v[j][1] = vy(pv);
+    v[j][2] = vz(pv);
+  }
+  double rho[4], mx = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    rho[j] = scale * trilinear_at(d, nv, v[j]);
+    if (j == 0 || rho[j] > mx) mx = rho[j];
+  }
+  int64_t e[3][3], c[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; k++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) e[k][a] = v[k + 1][a] - v[0][a];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const int64_t* p = e[(k + 1) % 3];
+    const int64_t* q = e[(k + 2) % 3];
+    c[k][0] = p[1] * q[2] - p[2] * q[1];
+    c[k][1] = p[2] * q[0] - p[0] * q[2];
+    c[k][2] = p[0] * q[1] - p[1] * q[0];
+  }
+  const int64_t det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+  const double dr[3] = {rho[1] - rho[0], rho[2] - rho[0], rho[3] - rho[0]};
+  double g[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+    g[a] = ((dr[0] * (double)c[0][a] + dr[1] * (double)c[1][a]) + dr[2] * (double)c[2][a]) / (double)det *
+           (double)kLatS;
+  const double p0[3] = {(double)v[0][0] / kLatS, (double)v[0][1] / kLatS, (double)v[0][2] / kLatS};
+  const double c0 = rho[0] - ((g[0] * p0[0] + g[1] * p0[1]) + g[2] * p0[2]);
+  maj[t] = (float)mx;
+  coef[t] = make_float4((float)c0, (float)g[0], (float)g[1], (float)g[2]);
+}
+
+// Model 2 (one thread per tet): majorant = scale * the largest voxel of the
+// tet's open bounding box (the pyramid's exact maxima).
+__global__ void k_model_voxel(int64_t n, const uint64_t* __restrict__ verts, Pyramid P, double scale,
+                              float* __restrict__ maj) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint64_t v[4] = {verts[4 * t], verts[4 * t + 1], verts[4 * t + 2], verts[4 * t + 3]};
+  int32_t lo[3], hi[3];
+  tet_box(v, lo, hi);
+  float mn, mx;
+  double s, c;
+  box_stats(P, lo, hi, mn, mx, s, c);
+  maj[t] = (float)(scale * (double)mx);
+}
+
+// Model records: the grid's records with the model's majorant as the
+// extinction (and majorant) every walk step reads.
+__global__ void k_model_records(int64_t n, const TetRec* __restrict__ rec, const TetRec32* __restrict__ rec32,
+                                const float* __restrict__ maj, TetRec* __restrict__ mrec, TetRec32* __restrict__ mrec32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float m = maj[t];
+  TetRec r = rec[t];
+  r.sigma = m;
+  r.majorant = m;
+  mrec[t] = r;
+  if (rec32) {
+    TetRec32 q = rec32[t];
+    q.w[3] = __float_as_uint(m);
+    mrec32[t] = q;
+  }
+}
+
+// Checked first (the grid is unchanged on any error), then built whole and
+// swapped in.
+int grid_set_density_model(tet_grid* g, const tet_density* dens, int32_t model, hipStream_t st) {
+  if (!g) return fail(TET_ERR_INVALID_ARG, "tet_grid_set_density_model: grid is NULL");
+  if (model < 0 || model > 2) return fail(TET_ERR_INVALID_ARG, "tet_grid_set_density_model: model must be 0, 1 or 2");
+  auto drop = [&]() {
+    dev_free(g->mmaj);
+    dev_free(g->mcoef);
+    dev_free(g->mdens);
+    dev_free(g->mrec);
+    dev_free(g->mrec32);
+    g->mmaj = nullptr;
+    g->mcoef = nullptr;
+    g->mdens = nullptr;
+    g->mrec = nullptr;
+    g->mrec32 = nullptr;
+    g->model = 0;
+  };
+  if (model == 0) {
+    drop();
+    return TET_OK;
+  }
+  if (!dens || !dens->data) return fail(TET_ERR_INVALID_ARG, "tet_grid_set_density_model: no volume");
+  const int32_t n = dens->n;
+  if (n < 1 || n > 4096 || (n & (n - 1)))
+    return fail(TET_ERR_INVALID_ARG, "tet_grid_set_density_model: n must be a power of two <= 4096");
+  if (!(dens->density_scale > 0.0f) || std::isinf(dens->density_scale))
+    return fail(TET_ERR_INVALID_ARG, "tet_grid_set_density_model: density_scale must be finite and > 0");
+  int L = 0;
+  while ((1 << L) < n) L++;
+  const int64_t nvox = (int64_t)n * n * n;
+  // the volume on the device: the model's own copy for voxel lookups, else
+  // a temporary one for host input
+  float* vol = nullptr;
+  Buf tmp, flag;
+  const float* d = dens->data;
+  if (model == 2) {
+    vol = (float*)dev_alloc((size_t)nvox * 4);
+    if (!vol) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_density_model: volume copy");
+    TV_HIP(hipMemcpyAsync(vol, d, (size_t)nvox * 4, dens->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          st));
+    d = vol;
+  } else if (!dens->on_device) {
+    if (!tmp.ensure((size_t)nvox * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_density_model: volume copy");
+    TV_HIP(hipMemcpyAsync(tmp.p, d, (size_t)nvox * 4, hipMemcpyHostToDevice, st));
+    d = tmp.as<float>();
+  }
+  struct Owned {
+    float* vol;
+    float* maj = nullptr;
+    float4* coef = nullptr;
+    TetRec* rec = nullptr;
+    TetRec32* rec32 = nullptr;
+    bool keep = false;
+    ~Owned() {
+      if (keep) return;
+      dev_free(vol);
+      dev_free(maj);
+      dev_free(coef);
+      dev_free(rec);
+      dev_free(rec32);
+    }
+  } own{vol};
+  if (!flag.ensure(4)) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_density_model: scratch");
+  TV_HIP(hipMemsetAsync(flag.p, 0, 4, st));
+  hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d, nvox, flag.as<int>());
+  int bad = 0;
+  TV_HIP(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  if (bad) return fail(TET_ERR_NUMERIC, "tet_grid_set_density_model: density values must be finite and >= 0");
+  own.maj = (float*)dev_alloc((size_t)g->n * 4);
+  own.rec = (TetRec*)dev_alloc((size_t)g->n * sizeof(TetRec));
+  if (g->rec32) own.rec32 = (TetRec32*)dev_alloc((size_t)g->n * sizeof(TetRec32));
+  if (model == 1) own.coef = (float4*)dev_alloc((size_t)g->n * sizeof(float4));
+  if (!own.maj || !own.rec || (g->rec32 && !own.rec32) || (model == 1 && !own.coef))
+    return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_density_model: per-tet model");
+  const unsigned blocks = nblocks(g->n, 256);
+  if (model == 1) {
+    hipLaunchKernelGGL(k_model_linear, dim3(blocks), dim3(256), 0, st, g->n, g->verts, d, n,
+                       (double)dens->density_scale, own.maj, own.coef);
+    TV_HIP(hipGetLastError());
+  } else {
+    Pyramid P;
+    std::vector<Buf> lv;
+    if (!make_pyramid(d, n, L, P, lv, st)) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_set_density_model: pyramid");
+    hipLaunchKernelGGL(k_model_voxel, dim3(blocks), dim3(256), 0, st, g->n, g->verts, P, (double)dens->density_scale,
+                       own.maj);
+    TV_HIP(hipGetLastError());
+    TV_HIP(hipStreamSynchronize(st));  // before the pyramid returns to the pool
+  }
+  hipLaunchKernelGGL(k_model_records, dim3(blocks), dim3(256), 0, st, g->n, g->rec, g->rec32, own.maj, own.rec,
+                     own.rec32);
+  TV_HIP(hipGetLastError());
+  TV_HIP(hipStreamSynchronize(st));
+  drop();
+  g->mmaj = own.maj;
+  g->mcoef = own.coef;
+  g->mdens = own.vol;
+  g->mrec = own.rec;
+  g->mrec32 = own.rec32;
+  g->mn = n;
+  g->mscale = dens->density_scale;
+  g->model = model;
+  own.keep = true;
+  return TET_OK;
+}
+
+int grid_export_density_model(const tet_grid* g, float* majorant, float* coef, int32_t on_device) {
+  if (!g) return fail(TET_ERR_INVALID_ARG, "tet_grid_export_density_model: grid is NULL");
+  if (g->model == 0) return fail(TET_ERR_INVALID_ARG, "tet_grid_export_density_model: the grid has no density model");
+  if (coef && g->model != 1)
+    return fail(TET_ERR_INVALID_ARG, "tet_grid_export_density_model: coefficients exist for the linear model only");
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (majorant) TV_HIP(hipMemcpy(majorant, g->mmaj, (size_t)g->n * 4, kind));
+  if (coef) TV_HIP(hipMemcpy(coef, g->mcoef, (size_t)g->n * 16, kind));
+  return TET_OK;
+}
+
 }  // namespace tv

@@ -16,6 +16,8 @@ namespace tv {
 int build_grid(const tet_density*, const tet_camera*, float, const tet_build_opts*, hipStream_t, tet_grid**);
 int grid_set_channels(tet_grid*, const tet_channels*, hipStream_t);
 int grid_export_channels(const tet_grid*, float*, float*, float*, int32_t);
+int grid_set_density_model(tet_grid*, const tet_density*, int32_t, hipStream_t);
+int grid_export_density_model(const tet_grid*, float*, float*, int32_t);
 int render_grid(const tet_grid*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
                 const tet_render_opts*, float*, int32_t, hipStream_t, tet_render_stats*);
 int render_voxels(const tet_density*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
@@ -283,6 +285,14 @@ int tet_grid_export_channels(const tet_grid* g, float* temperature, float* albed
   TV_GUARD(grid_export_channels(g, temperature, albedo, gch, on_device));
 }
 
+int tet_grid_set_density_model(tet_grid* g, const tet_density* density, int32_t model, void* hip_stream) {
+  TV_GUARD(grid_set_density_model(g, density, model, (hipStream_t)hip_stream));
+}
+
+int tet_grid_export_density_model(const tet_grid* g, float* majorant, float* coef, int32_t on_device) {
+  TV_GUARD(grid_export_density_model(g, majorant, coef, on_device));
+}
+
 int tet_render(const tet_grid* g, const tet_camera* camera, const tet_medium* medium, const tet_light* light,
                int32_t spp, uint64_t seed, const tet_render_opts* opts, float* out_rgb, int32_t on_device,
                void* hip_stream, tet_render_stats* stats) {
@@ -309,6 +319,11 @@ void tet_grid_free(tet_grid* g) {
   dev_free(g->rec);
   dev_free(g->rec32);
   for (int k = 0; k < 3; k++) dev_free(g->ch[k]);
+  dev_free(g->mmaj);
+  dev_free(g->mcoef);
+  dev_free(g->mdens);
+  dev_free(g->mrec);
+  dev_free(g->mrec32);
   delete g;
 }
 

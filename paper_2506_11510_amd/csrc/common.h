@@ -338,4 +338,15 @@ struct tet_grid {
   tv::TetRec* rec;      // traversal records
   tv::TetRec32* rec32;  // compact records (NULL when the grid cannot use them)
   float* ch[3];         // extra channels per tet: temperature, albedo, g (NULL = absent)
+  // density model inside the tets: 0 constant (the records' extinction),
+  // 1 linear (coefficients c0, gx, gy, gz per tet), 2 voxel lookup (a copy
+  // of the volume); model records carry the model's majorant as extinction
+  int32_t model;
+  float* mmaj;
+  float4* mcoef;
+  float* mdens;
+  int32_t mn;
+  float mscale;
+  tv::TetRec* mrec;
+  tv::TetRec32* mrec32;
 };

@@ -38,6 +38,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "nrc.h"
@@ -134,7 +135,32 @@ struct RenderArgs {
   const float* ch_a;
   const float* ch_g;
   float emission[3];
+  // density model inside the tets (0 = constant): 1 linear coefficients,
+  // 2 voxel lookup in an n^3 volume times a scale
+  int32_t model;
+  const float4* mcoef;
+  const float* mdens;
+  int32_t mn;
+  float mscale;
 };
+
+// Extinction at o + t d inside tet `cell` under the grid's density model:
+// linear ((c0 + gx x) + gy y) + gz z, or the scale times the voxel
+// floor(x n) (indices clamped); FP32.
+__device__ inline float model_sigma(const RenderArgs& A, uint32_t cell, float3 o, float3 d, float t) {
+  const float x0 = o.x + t * d.x, x1 = o.y + t * d.y, x2 = o.z + t * d.z;
+  if (A.model == 1) {
+    const float4 c = A.mcoef[cell];
+    return ((c.x + c.y * x0) + c.z * x1) + c.w * x2;
+  }
+  const int32_t n = A.mn;
+  const float fn = (float)n;
+  int64_t i = (int64_t)floorf(x0 * fn), j = (int64_t)floorf(x1 * fn), k = (int64_t)floorf(x2 * fn);
+  i = i < 0 ? 0 : (i >= n ? n - 1 : i);
+  j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+  k = k < 0 ? 0 : (k >= n ? n - 1 : k);
+  return A.mscale * A.mdens[i + (int64_t)n * (j + (int64_t)n * k)];
+}
 
 // Pixel of training path j: floor(w npix / 2^24), w = the upper 24 bits of
 // word 0 of Philox(counter (j, 0, 4, 0)).
@@ -555,7 +581,9 @@ __device__ inline void set_segment(float* tab, float3 o, float3 d, float oscale)
 // BATCH: the lanes' samples come from a batch of scenes (A.scenes); each
 // lane keeps its sample's scene index and that grid's record pointer, and
 // reads the scene's light, medium, seed and image from the table at events.
-template <class Med, int W, int NRC, bool BATCH = false>
+// EXT: the variant that reads the extra channels and the density model
+// (the plain variant carries none of that code).
+template <class Med, int W, int NRC, bool BATCH = false, bool EXT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_render(RenderArgs A, Med med) {
   __shared__ float s_tab[256 * kTabStride];
   float* tab = s_tab + threadIdx.x * kTabStride;
@@ -626,8 +654,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         // the collision estimator (absorbed part of the collision), then the
         // tet's albedo in place of the medium's
         float alb = TV_ALBEDO;
-        if (!BATCH && A.ch_a) alb = A.ch_a[cell];
-        if (!BATCH && A.ch_t) {
+        if (EXT && A.ch_a) alb = A.ch_a[cell];
+        if (EXT && A.ch_t) {
           const float e = (1.0f - alb) * A.ch_t[cell];
           L.x = L.x + beta * (e * A.emission[0]);
           L.y = L.y + beta * (e * A.emission[1]);
@@ -647,7 +675,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
         float Tr = A.transmittance == 0 ? exp_neg(od) : od;
         float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
-        const float gg = (!BATCH && A.ch_g) ? A.ch_g[cell_x] : TV_G;  // the collision tet's phase parameter
+        const float gg = (EXT && A.ch_g) ? A.ch_g[cell_x] : TV_G;  // the collision tet's phase parameter
         float ph = hg_pdf(gg, mu);
         L.x = L.x + ((beta * ph) * TV_E(0)) * Tr;
         L.y = L.y + ((beta * ph) * TV_E(1)) * Tr;
@@ -825,6 +853,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
               float dtau = sb * (st.te - t);
               while (tau < dtau) {
                 tc = t + tau / sb;
+                if (EXT && A.model) sg = model_sigma(A, cell, o, d, tc);  // extinction at the tentative point
                 bool real = true;
                 if (sg < sb) real = uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
                 if (real) {
@@ -850,12 +879,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         } else {  // light ray: od holds the optical depth (analytic) or the transmittance
           bool done = !st.ok;
           if (st.ok) {
-            if (A.transmittance == 0) {
+            if (A.transmittance == 0 && EXT && A.model) {
+              // linear model: exact integral over the segment (trapezoid)
+              od = od + (0.5f * (model_sigma(A, cell, o, d, t) + model_sigma(A, cell, o, d, st.te))) * (st.te - t);
+            } else if (A.transmittance == 0) {
               od = od + sg * (st.te - t);
             } else if (sb > 0.0f) {
               float dtau = sb * (st.te - t);
               while (tau < dtau) {
                 t = t + tau / sb;
+                if (EXT && A.model) sg = model_sigma(A, cell, o, d, t);
                 if (A.transmittance == 1) {
                   od = od * (1.0f - sg / sb);
                 } else {
@@ -948,6 +981,7 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
                       float* ms_trace, float* ms_cache) {
   int bs = o.block_size ? o.block_size : 256;
   int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
+  const bool ext = A.model != 0 || A.ch_t || A.ch_a || A.ch_g;
   hipEvent_t e0, e1, e2, t0, t1;
   TV_HIP(hipEventCreate(&e0));
   TV_HIP(hipEventCreate(&e1));
@@ -1000,6 +1034,15 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     TV_HIP(hipEventRecord(t0, st));
     if (NRC != 0) {
       hipLaunchKernelGGL((k_render<Med, 5, NRC>), dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+    } else if (ext) {
+      if constexpr (!std::is_same<Med, VoxelMedium>::value) {
+        switch (o.waves_per_simd) {
+          case 4: hipLaunchKernelGGL((k_render<Med, 4, 0, false, true>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+          case 6: hipLaunchKernelGGL((k_render<Med, 6, 0, false, true>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+          case 8: hipLaunchKernelGGL((k_render<Med, 8, 0, false, true>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+          default: hipLaunchKernelGGL((k_render<Med, 5, 0, false, true>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
+        }
+      }
     } else {
       switch (o.waves_per_simd) {
         case 4: hipLaunchKernelGGL((k_render<Med, 4, 0>), dim3((unsigned)grid), dim3(bs), 0, st, P, med); break;
@@ -1082,6 +1125,10 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
       if (!(o.emission[c] >= 0.0f) || std::isinf(o.emission[c]))
         return fail(TET_ERR_INVALID_ARG, "render: emission must be finite and >= 0");
   }
+  const bool model = kind == 0 && g->model != 0;
+  if (model && nrc) return fail(TET_ERR_UNSUPPORTED, "render: density models do not render with a radiance cache");
+  if (model && g->model == 2 && o.transmittance == 0)
+    return fail(TET_ERR_INVALID_ARG, "render: the voxel-lookup model needs ratio or delta tracking for the light");
   const uint32_t* shapes = shape_table();
   if (!shapes) return fail(TET_ERR_DEVICE, "render: shape table");
   int64_t npix = (int64_t)cam->width * cam->height;
@@ -1101,6 +1148,13 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     A.ch_a = g->ch[1];
     A.ch_g = g->ch[2];
     for (int c = 0; c < 3; c++) A.emission[c] = o.emission[c];
+  }
+  if (model) {
+    A.model = g->model;
+    A.mcoef = g->mcoef;
+    A.mdens = g->mdens;
+    A.mn = g->mn;
+    A.mscale = g->mscale;
   }
   A.spp = spp;
   A.pass_start = o.sample_offset;
@@ -1159,12 +1213,12 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
-    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
+    TetMedium32 m{model ? g->mrec32 : g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
              : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
-    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
+    TetMedium m{model ? g->mrec : g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
              : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
   } else {
@@ -1218,6 +1272,7 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
                          uint64_t frame_seed, const tet_render_opts* opts_in, int32_t n_paths, int32_t kv, float4* vrec,
                          float4* path_l, hipStream_t st, float* ms_out) {
   if (!g) return fail(TET_ERR_INVALID_ARG, "training paths: grid is NULL");
+  if (g->model) return fail(TET_ERR_UNSUPPORTED, "training paths: density models do not train a radiance cache");
   const uint32_t* shapes = shape_table();
   if (!shapes) return fail(TET_ERR_DEVICE, "training paths: shape table");
   if (int rc = check_camera(cam)) return rc;
@@ -1341,6 +1396,7 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
   bool use32 = o.record_layout != 48;
   for (int i = 0; i < n; i++) {
     if (!grids[i] || !outs[i]) return fail(TET_ERR_INVALID_ARG, "render batch: NULL grid or output");
+    if (grids[i]->model) return fail(TET_ERR_UNSUPPORTED, "render batch: no density models in batches");
     if (int rc = check_camera(&cams[i])) return rc;
     if (!(media[i].g > -1.0f && media[i].g < 1.0f) || !(media[i].albedo >= 0.0f))
       return fail(TET_ERR_INVALID_ARG, "render batch: medium needs albedo >= 0 and -1 < g < 1");
