@@ -257,6 +257,33 @@ def density_model_leg(tv, torch, dev, sc, plain_ms: float, steps: int = 3) -> di
     return out
 
 
+def sparse_build_leg(tv, torch, dev, sc, dense_grid) -> dict:
+    """The same build from the volume's 8^3 bricks (OpenVDB-like leaves
+    holding a nonzero voxel, extracted on the device): time, input and
+    pyramid sizes against the dense build, and whether the grid is the
+    dense build's (ids and neighbour links compared on the device)."""
+    n = sc["n"]
+    nb = n // 8
+    v = dev.view(nb, 8, nb, 8, nb, 8).permute(0, 2, 4, 1, 3, 5).reshape(nb ** 3, 512)
+    pick = torch.nonzero(v.ne(0).any(dim=1)).flatten()
+    values = v.index_select(0, pick).contiguous()
+    del v
+    coords = torch.stack([pick % nb, (pick // nb) % nb, pick // (nb * nb)], dim=1).to(torch.int32).contiguous()
+    ms = []
+    for _ in range(2):
+        g = tv.leb_build_sparse(coords, values, n, sc["camera"], build=sc["build"])
+        ms.append(g.info()["ms"])
+    a, b = g.export(device=True, fields=("ids", "nbr")), dense_grid.export(device=True, fields=("ids", "nbr"))
+    same = bool(torch.equal(a["ids"], b["ids"]) and torch.equal(a["nbr"], b["nbr"]))
+    nbr = int(pick.numel())
+    dense_pyr = sum(((n >> l) ** 3) * 16 for l in range(1, 11) if (n >> l) > 0)
+    sparse_pyr = nbr * 72 * 16 + sum(((n >> l) ** 3) * 16 for l in range(3, 11) if (n >> l) > 0) + nb ** 3 * 4
+    del g, a, b, values, coords
+    return {"bricks": nbr, "brick_positions": nb ** 3, "input_bytes": nbr * (512 * 4 + 12),
+            "dense_input_bytes": n ** 3 * 4, "pyramid_bytes": sparse_pyr, "dense_pyramid_bytes": dense_pyr,
+            "build_ms": round(ms[-1], 3), "same_grid_as_dense": same}
+
+
 def plume_leg(tv, torch) -> dict:
     """The production-scale configuration: 1024^3 plume density resident in
     HBM, adaptive LEB build (~86 M tets), 1024^2 renders at 32 and 1024 spp
@@ -274,6 +301,7 @@ def plume_leg(tv, torch) -> dict:
     for _ in range(2):
         g = tv.leb_build(dev, sc["n"], sc["camera"], build=sc["build"])
         builds.append(g.info())
+    sparse = sparse_build_leg(tv, torch, dev, sc, g)
     del dev
     cam = sc["camera"]
     tv.render(g, cam, sc["medium"], sc["light"], 32, 1, sc["render"])
@@ -291,7 +319,7 @@ def plume_leg(tv, torch) -> dict:
                        "(1 px target, tau 0.2, depth <= 30) -> 1024x1024, 64 bounces, albedo 0.95, HG g 0.6",
            "density_gen_s_host": round(gen_s, 2), "num_tets": builds[-1]["num_tets"],
            "max_depth": builds[-1]["max_depth"], "build_rounds": builds[-1]["rounds"],
-           "build_ms": round(builds[-1]["ms"], 3),
+           "build_ms": round(builds[-1]["ms"], 3), "sparse_input": sparse,
            "spp32": {"ms": round(ms32, 3), "trace_ms": round(tr32, 3),
                      "msamples_per_s": round(px * 32 / (ms32 / 1e3) / 1e6, 3),
                      "tet_steps_per_s": round(steps32 / (tr32 / 1e3), 1), "tet_steps": int(steps32),

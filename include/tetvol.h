@@ -155,6 +155,29 @@ void tet_render_opts_defaults(tet_render_opts* o);
 int leb_build(const tet_density* density, const tet_camera* camera, float target_cell_px,
               const tet_build_opts* opts /* NULL = defaults */, void* hip_stream, tet_grid** out);
 
+/* The same build from a sparse volume (the paper builds from OpenVDB data,
+ * "Subdivision Criteria"): the n^3 volume is zero outside num_bricks
+ * leaf bricks of 8^3 voxels.  brick_coords: 3 int32 per brick, its position
+ * in brick units (voxel / 8) along x, y, z, each in [0, n / 8);
+ * brick_values: 512 FP32 per brick, x fastest inside the brick; both on the
+ * device or both on the host (on_device).  n is a power of two, 8 <= n <=
+ * 4096.  The grid is identical, bit for bit, to leb_build's on the dense
+ * volume the bricks describe; the build never holds that dense volume (the
+ * pyramid's levels 1 and 2 are kept per brick, levels >= 3 dense).  Errors
+ * as leb_build, plus TET_ERR_INVALID_ARG for a brick out of range or listed
+ * twice.  The caller's buffers are only read. */
+typedef struct {
+  const int32_t* brick_coords;
+  const float* brick_values;
+  int64_t num_bricks;
+  int32_t n;
+  int32_t on_device;
+  float density_scale;
+} tet_sparse_density;
+
+int leb_build_sparse(const tet_sparse_density* density, const tet_camera* camera, float target_cell_px,
+                     const tet_build_opts* opts, void* hip_stream, tet_grid** out);
+
 int tet_grid_info(const tet_grid* grid, int64_t* num_tets, int32_t* max_depth, tet_build_stats* stats);
 
 /* Copies grid arrays out (any pointer may be NULL): ids[num_tets] heap ids;

@@ -357,6 +357,16 @@ class Grid:
         return r
 
 
+def densify(coords: np.ndarray, values: np.ndarray, n: int) -> np.ndarray:
+    """The dense n^3 volume (x fastest) a sparse volume describes: zero
+    outside its 8^3 bricks, brick (bx, by, bz) holding voxels 8 bx .. 8 bx
+    + 7 along x (and likewise in y, z), its 512 values x fastest."""
+    out = np.zeros((n, n, n), np.float32)  # [z, y, x]
+    for (bx, by, bz), v in zip(np.asarray(coords).reshape(-1, 3), np.asarray(values).reshape(-1, 512)):
+        out[8 * bz:8 * bz + 8, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8] = v.reshape(8, 8, 8)
+    return out.reshape(-1)
+
+
 def leb_build(density: np.ndarray, n: int, camera: dict, build: dict) -> Grid:
     density = np.ascontiguousarray(density, np.float32)
     assert density.size == n ** 3

@@ -179,6 +179,34 @@ def leb_build(density, n: int, camera: dict, target_cell_px: float = 1.0, build:
     return Grid(h)
 
 
+def leb_build_sparse(coords, values, n: int, camera: dict, target_cell_px: float = 1.0, build: dict | None = None,
+                     density_scale: float | None = None) -> Grid:
+    """The same build from a sparse volume: `coords` (B, 3) int32 brick
+    positions (voxel / 8) and `values` (B, 512) float32 voxels of each 8^3
+    brick, x fastest; both numpy arrays or both CUDA tensors."""
+    b = dict(build or {})
+    scale = b.pop("density_scale", 1.0) if density_scale is None else density_scale
+    target = b.pop("target_px", target_cell_px)
+    b.pop("shuffle_seed", None)
+    if isinstance(coords, np.ndarray):
+        coords = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+        values = np.ascontiguousarray(values, np.float32).reshape(-1, 512)
+    else:
+        coords = coords.contiguous().int().reshape(-1, 3)
+        values = values.contiguous().float().reshape(-1, 512)
+    assert coords.shape[0] == values.shape[0]
+    pc, dev_c = _ptr(coords)
+    pv, dev_v = _ptr(values)
+    assert dev_c == dev_v
+    sd = _abi.TetSparseDensity(pc, pv, int(coords.shape[0]), int(n), dev_c, float(scale))
+    cam = _abi.make_camera(camera)
+    opts = _abi.make_build_opts(b)
+    h = ctypes.c_void_p()
+    check(lib().leb_build_sparse(ctypes.byref(sd), ctypes.byref(cam), float(target), ctypes.byref(opts), _stream(),
+                                 ctypes.byref(h)), "leb_build_sparse")
+    return Grid(h)
+
+
 def render(grid: Grid, camera: dict, medium: dict, light: dict, spp: int, seed: int, render: dict | None = None,
            out=None):
     """Renders (H, W, 3) float32 radiance into a torch CUDA tensor.  Returns
@@ -427,4 +455,4 @@ def release_cache():
     lib().tet_release_cache()
 
 
-__all__ = ["Grid", "Nrc", "Batch", "render_batch", "autotune", "N_PARAMS", "TetError", "leb_build", "render", "dda_render", "release_cache", "lib"]
+__all__ = ["Grid", "Nrc", "Batch", "render_batch", "autotune", "N_PARAMS", "TetError", "leb_build", "leb_build_sparse", "render", "dda_render", "release_cache", "lib"]

@@ -28,6 +28,11 @@ class TetDensity(ctypes.Structure):
                 ("density_scale", ctypes.c_float)]
 
 
+class TetSparseDensity(ctypes.Structure):
+    _fields_ = [("brick_coords", ctypes.c_void_p), ("brick_values", ctypes.c_void_p), ("num_bricks", ctypes.c_int64),
+                ("n", ctypes.c_int32), ("on_device", ctypes.c_int32), ("density_scale", ctypes.c_float)]
+
+
 class TetCamera(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_float * 3), ("look_at", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
                 ("fov_y_deg", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
@@ -110,6 +115,8 @@ SIGNATURES = {
     "tet_render_opts_defaults": (None, [ctypes.POINTER(TetRenderOpts)]),
     "leb_build": (ctypes.c_int, [ctypes.POINTER(TetDensity), ctypes.POINTER(TetCamera), ctypes.c_float,
                                  ctypes.POINTER(TetBuildOpts), VP, ctypes.POINTER(VP)]),
+    "leb_build_sparse": (ctypes.c_int, [ctypes.POINTER(TetSparseDensity), ctypes.POINTER(TetCamera), ctypes.c_float,
+                                        ctypes.POINTER(TetBuildOpts), VP, ctypes.POINTER(VP)]),
     "tet_grid_info": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(TetBuildStats)]),
     "tet_grid_export": (ctypes.c_int, [VP, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),

@@ -120,7 +120,25 @@ __device__ inline void box_stats(const Pyramid& P, const int32_t lo[3], const in
         int64_t o = i + m * (j + m * (int64_t)k);
         float cmn, cmx;
         double cs;
-        if (l == 0) {
+        if (P.bmap && l < kBrickBits) {  // sparse levels 0..2: inside the cell's brick, zero without one
+          const int sb = kBrickBits - l;
+          const int32_t br = P.bmap[(i >> sb) + (int64_t)P.nb * ((j >> sb) + (int64_t)P.nb * (k >> sb))];
+          if (br < 0) {
+            cmn = cmx = 0.0f;
+            cs = 0.0;
+          } else {
+            const int32_t mk = (1 << sb) - 1;
+            const int64_t li = (int64_t)br * (1 << (3 * sb)) + ((i & mk) + ((j & mk) << sb) + ((k & mk) << (2 * sb)));
+            if (l == 0) {
+              cmn = cmx = P.bval[li];
+              cs = (double)cmn;
+            } else {
+              cmn = P.bmn[l][li];
+              cmx = P.bmx[l][li];
+              cs = P.bsum[l][li];
+            }
+          }
+        } else if (l == 0) {
           cmn = cmx = P.dens[o];
           cs = (double)cmn;
         } else {
@@ -1503,6 +1521,154 @@ static bool make_pyramid(const float* d, int32_t n, int L, Pyramid& P, std::vect
   return true;
 }
 
+// Sparse volume: brick map (bit 1 of *bad: a coordinate out of range, bit 2:
+// a brick listed twice).
+__global__ void k_brick_map(const int32_t* __restrict__ coords, int64_t nbricks, int32_t nb, int32_t* __restrict__ bmap,
+                            int* __restrict__ bad) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbricks) return;
+  const int32_t x = coords[3 * b], y = coords[3 * b + 1], z = coords[3 * b + 2];
+  if (x < 0 || y < 0 || z < 0 || x >= nb || y >= nb || z >= nb) {
+    atomicOr(bad, 2);
+    return;
+  }
+  if (atomicCAS(&bmap[x + (int64_t)nb * (y + (int64_t)nb * z)], -1, (int32_t)b) != -1) atomicOr(bad, 4);
+}
+
+// One wave per brick: levels 1 (64 cells) and 2 (8 cells) of the brick, and
+// its level-3 cell in the dense level-3 arrays; children combined as in
+// k_pyramid_level.
+__global__ __launch_bounds__(64) void k_brick_levels(const int32_t* __restrict__ coords, const float* __restrict__ val,
+                                                     int32_t nb, float* __restrict__ mn1, float* __restrict__ mx1,
+                                                     double* __restrict__ s1, float* __restrict__ mn2,
+                                                     float* __restrict__ mx2, double* __restrict__ s2,
+                                                     float* __restrict__ mn3, float* __restrict__ mx3,
+                                                     double* __restrict__ s3) {
+  __shared__ float lmn[64], lmx[64];
+  __shared__ double lsum[64];
+  const int64_t b = blockIdx.x;
+  const int t = threadIdx.x;
+  auto combine = [](const float* lo, const float* hi, const double* s, float& a, float& c, double& sum) {
+    a = lo[0];
+    c = hi[0];
+    for (int q = 1; q < 8; q++) {
+      a = lo[q] < a ? lo[q] : a;
+      c = hi[q] > c ? hi[q] : c;
+    }
+    sum = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  };
+  {  // level 1: cell (i, j, k) of 4^3 from voxels (2i + a, 2j + b, 2k + c) of 8^3
+    const int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
+    float lo[8], hi[8];
+    double s[8];
+    for (int q = 0; q < 8; q++) {
+      const float v = val[b * 512 + (2 * i + (q & 1)) + 8 * ((2 * j + ((q >> 1) & 1)) + 8 * (2 * k + ((q >> 2) & 1)))];
+      lo[q] = v;
+      hi[q] = v;
+      s[q] = (double)v;
+    }
+    float a, c;
+    double sum;
+    combine(lo, hi, s, a, c, sum);
+    mn1[b * 64 + t] = a;
+    mx1[b * 64 + t] = c;
+    s1[b * 64 + t] = sum;
+    lmn[t] = a;
+    lmx[t] = c;
+    lsum[t] = sum;
+  }
+  __syncthreads();
+  float a2 = 0.0f, c2 = 0.0f;
+  double sum2 = 0.0;
+  if (t < 8) {  // level 2: cell of 2^3 from level-1 cells of 4^3
+    const int i = t & 1, j = (t >> 1) & 1, k = t >> 2;
+    float lo[8], hi[8];
+    double s[8];
+    for (int q = 0; q < 8; q++) {
+      const int c = (2 * i + (q & 1)) + 4 * ((2 * j + ((q >> 1) & 1)) + 4 * (2 * k + ((q >> 2) & 1)));
+      lo[q] = lmn[c];
+      hi[q] = lmx[c];
+      s[q] = lsum[c];
+    }
+    combine(lo, hi, s, a2, c2, sum2);
+    mn2[b * 8 + t] = a2;
+    mx2[b * 8 + t] = c2;
+    s2[b * 8 + t] = sum2;
+  }
+  __syncthreads();
+  if (t < 8) {
+    lmn[t] = a2;
+    lmx[t] = c2;
+    lsum[t] = sum2;
+  }
+  __syncthreads();
+  const int32_t bx = coords[3 * b], by = coords[3 * b + 1], bz = coords[3 * b + 2];
+  if (t == 0 && bx >= 0 && by >= 0 && bz >= 0 && bx < nb && by < nb && bz < nb) {
+    // level 3: the brick's own cell (child order q = x + 2y + 4z); bricks
+    // out of range are reported by k_brick_map and skipped here
+    float a, c;
+    double sum;
+    combine(lmn, lmx, lsum, a, c, sum);
+    const int64_t o = bx + (int64_t)nb * (by + (int64_t)nb * bz);
+    mn3[o] = a;
+    mx3[o] = c;
+    s3[o] = sum;
+  }
+}
+
+// Pyramid of a sparse volume (n >= 8): brick map, per-brick levels 1-2,
+// dense levels 3..L (level 3 zero where no brick).  Bricks and values on
+// the device; *d_bad gets bits 2 / 4 for bad coordinates / duplicates.
+static bool make_sparse_pyramid(const int32_t* coords, const float* val, int64_t nbricks, int32_t n, int L, Pyramid& P,
+                                std::vector<Buf>& lv, int* d_bad, hipStream_t st) {
+  memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.L = L;
+  const int32_t nb = n >> kBrickBits;
+  P.nb = nb;
+  const int64_t nbc = (int64_t)nb * nb * nb;
+  lv = std::vector<Buf>(3 * (L + 1) + 1);
+  Buf& map = lv[3 * (L + 1)];
+  if (!map.ensure(nbc * 4)) return false;
+  hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(nbc, 256)), dim3(256), 0, st, map.as<uint32_t>(), nbc, 0xFFFFFFFFu);
+  if (nbricks > 0)
+    hipLaunchKernelGGL(k_brick_map, dim3(nblocks(nbricks, 256)), dim3(256), 0, st, coords, nbricks, nb,
+                       map.as<int32_t>(), d_bad);
+  P.bmap = map.as<int32_t>();
+  P.bval = val;
+  const int64_t nbr = std::max<int64_t>(nbricks, 1);
+  for (int l = 1; l <= 2; l++) {  // per-brick levels
+    const int64_t cells = nbr * (l == 1 ? 64 : 8);
+    if (!lv[3 * l].ensure(cells * 4) || !lv[3 * l + 1].ensure(cells * 4) || !lv[3 * l + 2].ensure(cells * 8))
+      return false;
+    P.bmn[l] = lv[3 * l].as<float>();
+    P.bmx[l] = lv[3 * l + 1].as<float>();
+    P.bsum[l] = lv[3 * l + 2].as<double>();
+  }
+  for (int l = 3; l <= L; l++) {
+    const int64_t m = (int64_t)n >> l, cells = m * m * m;
+    if (!lv[3 * l].ensure(cells * 4) || !lv[3 * l + 1].ensure(cells * 4) || !lv[3 * l + 2].ensure(cells * 8))
+      return false;
+    P.mn[l] = lv[3 * l].as<float>();
+    P.mx[l] = lv[3 * l + 1].as<float>();
+    P.sum[l] = lv[3 * l + 2].as<double>();
+    if (l == 3) {
+      if (hipMemsetAsync(lv[9].p, 0, cells * 4, st) != hipSuccess ||
+          hipMemsetAsync(lv[10].p, 0, cells * 4, st) != hipSuccess ||
+          hipMemsetAsync(lv[11].p, 0, cells * 8, st) != hipSuccess)
+        return false;
+      if (nbricks > 0)
+        hipLaunchKernelGGL(k_brick_levels, dim3((unsigned)nbricks), dim3(64), 0, st, coords, val, nb,
+                           (float*)P.bmn[1], (float*)P.bmx[1], (double*)P.bsum[1], (float*)P.bmn[2], (float*)P.bmx[2],
+                           (double*)P.bsum[2], (float*)P.mn[3], (float*)P.mx[3], (double*)P.sum[3]);
+    } else {
+      hipLaunchKernelGGL(k_pyramid_level, dim3(nblocks(cells, 256)), dim3(256), 0, st, nullptr, P.mn[l - 1],
+                         P.mx[l - 1], P.sum[l - 1], (int32_t)m, (float*)P.mn[l], (float*)P.mx[l], (double*)P.sum[l]);
+    }
+  }
+  return true;
+}
+
 // A device buffer grown keeping its first `keep` bytes.
 static bool grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t st) {
   if (bytes <= b.bytes) return true;
@@ -1525,13 +1691,16 @@ static int64_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, Buf& bsum,
   return 0;
 }
 
-int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, const tet_build_opts* opts_in,
-               hipStream_t st, tet_grid** out) {
+// The build from a dense volume (dens) or a sparse one (sp): they differ
+// only in how the pyramid is made.
+static int build_common(const tet_density* dens, const tet_sparse_density* sp, const tet_camera* cam, float target_px,
+                        const tet_build_opts* opts_in, hipStream_t st, tet_grid** out) {
   if (!out) return fail(TET_ERR_INVALID_ARG, "leb_build: out is NULL");
   *out = nullptr;
-  if (!dens || !dens->data) return fail(TET_ERR_INVALID_ARG, "leb_build: density is NULL");
-  int32_t n = dens->n;
+  const int32_t n = sp ? sp->n : dens->n;
+  const float scale = sp ? sp->density_scale : dens->density_scale;
   if (n < 1 || n > 4096 || (n & (n - 1))) return fail(TET_ERR_INVALID_ARG, "leb_build: n must be a power of two <= 4096");
+  if (sp && n < (1 << kBrickBits)) return fail(TET_ERR_INVALID_ARG, "leb_build_sparse: n must be at least 8");
   if (int rc = check_camera(cam)) return rc;
   tet_build_opts o;
   if (opts_in) o = *opts_in;
@@ -1540,8 +1709,10 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
       o.max_depth > 56 || o.uniform_depth < 0 || o.uniform_depth > 56 || o.majorant_mode < 0 || o.majorant_mode > 1)
     return fail(TET_ERR_INVALID_ARG, "leb_build: bad options");
   if (o.want_mode == 0 && !(target_px > 0.0f)) return fail(TET_ERR_INVALID_ARG, "leb_build: target_cell_px must be > 0");
-  if (!(dens->density_scale >= 0.0f) || std::isinf(dens->density_scale))
-    return fail(TET_ERR_INVALID_ARG, "leb_build: bad density_scale");
+  if (!(scale >= 0.0f) || std::isinf(scale)) return fail(TET_ERR_INVALID_ARG, "leb_build: bad density_scale");
+  if (sp && (sp->num_bricks < 0 || sp->num_bricks > ((int64_t)n * n * n >> (3 * kBrickBits)) ||
+             (sp->num_bricks > 0 && (!sp->brick_coords || !sp->brick_values))))
+    return fail(TET_ERR_INVALID_ARG, "leb_build_sparse: bad brick list");
   int L = 0;
   while ((1 << L) < n) L++;
   int64_t nvox = (int64_t)n * n * n;
@@ -1551,13 +1722,21 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   TV_HIP(hipEventCreate(&e1));
   TV_HIP(hipEventRecord(e0, st));
 
-  // density on the device
-  Buf dcopy;
-  const float* d_dens = dens->data;
-  if (!dens->on_device) {
-    if (!dcopy.ensure(nvox * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: density copy");
-    TV_HIP(hipMemcpyAsync(dcopy.p, dens->data, nvox * 4, hipMemcpyHostToDevice, st));
+  // density on the device (a sparse volume: its bricks)
+  Buf dcopy, ccopy;
+  const float* d_dens = sp ? sp->brick_values : dens->data;
+  const int32_t* d_coords = sp ? sp->brick_coords : nullptr;
+  const int64_t nbricks = sp ? sp->num_bricks : 0;
+  const int64_t nvals = sp ? nbricks << (3 * kBrickBits) : nvox;
+  if (!(sp ? sp->on_device : dens->on_device) && nvals > 0) {
+    if (!dcopy.ensure(nvals * 4)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: density copy");
+    TV_HIP(hipMemcpyAsync(dcopy.p, d_dens, nvals * 4, hipMemcpyHostToDevice, st));
     d_dens = dcopy.as<float>();
+    if (sp) {
+      if (!ccopy.ensure(nbricks * 12)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: brick copy");
+      TV_HIP(hipMemcpyAsync(ccopy.p, d_coords, nbricks * 12, hipMemcpyHostToDevice, st));
+      d_coords = ccopy.as<int32_t>();
+    }
   }
   // small device scratch (32-bit words): [0] density flag, [1] max depth,
   // [2] finalize error, [3] listed faces, [4] scan total, [5] running count of marked splits,
@@ -1569,15 +1748,19 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   uint32_t* d_total = misc.as<uint32_t>() + 4;
   uint32_t* d_splitc = misc.as<uint32_t>() + 5;
   uint32_t* d_vcount = misc.as<uint32_t>() + 6;
-  hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvox, 256)), dim3(256), 0, st, d_dens, nvox, d_flag);
+  if (nvals > 0)
+    hipLaunchKernelGGL(k_check_density, dim3(nblocks(nvals, 256)), dim3(256), 0, st, d_dens, nvals, d_flag);
 
   // pyramid
   Pyramid P;
   std::vector<Buf> lv;
-  if (!make_pyramid(d_dens, n, L, P, lv, st)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: pyramid");
+  if (sp ? !make_sparse_pyramid(d_coords, d_dens, nbricks, n, L, P, lv, d_flag, st)
+         : !make_pyramid(d_dens, n, L, P, lv, st))
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: pyramid");
   int flag = 0;
   TV_HIP(hipMemcpyAsync(&flag, d_flag, 4, hipMemcpyDeviceToHost, st));
   TV_HIP(hipStreamSynchronize(st));
+  if (flag & 6) return fail(TET_ERR_INVALID_ARG, "leb_build_sparse: brick coordinates out of range or listed twice");
   if (flag) return fail(TET_ERR_NUMERIC, "leb_build: density has NaN, infinite or negative values");
 
   CamCrit cc;
@@ -1886,7 +2069,7 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   }
   uint32_t* d_items = misc.as<uint32_t>() + 3;
   hipLaunchKernelGGL(k_records, dim3(nblocks(cur, kRecordsBlock)), dim3(kRecordsBlock), 0, st, cur, g->verts, P,
-                     dens->density_scale, o.majorant_mode, g->rec, g->rec32, items.as<uint32_t>(), item_cap, d_items,
+                     scale, o.majorant_mode, g->rec, g->rec32, items.as<uint32_t>(), item_cap, d_items,
                      d_flag + 2);
   hipLaunchKernelGGL(k_links, dim3(nblocks(item_cap, 128)), dim3(128), 0, st, items.as<uint32_t>(), d_items, item_cap,
                      cur, g->verts, g->keys, g->kidx, g->kbits, g->max_depth, shapes, g->rec, g->rec32, d_flag + 2);
@@ -1912,6 +2095,20 @@ int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, 
   g->stats.ms = ms;
   *out = g;
   return TET_OK;
+}
+
+int build_grid(const tet_density* dens, const tet_camera* cam, float target_px, const tet_build_opts* opts_in,
+               hipStream_t st, tet_grid** out) {
+  if (out) *out = nullptr;
+  if (!dens || !dens->data) return fail(TET_ERR_INVALID_ARG, "leb_build: density is NULL");
+  return build_common(dens, nullptr, cam, target_px, opts_in, st, out);
+}
+
+int build_grid_sparse(const tet_sparse_density* sp, const tet_camera* cam, float target_px,
+                      const tet_build_opts* opts_in, hipStream_t st, tet_grid** out) {
+  if (out) *out = nullptr;
+  if (!sp) return fail(TET_ERR_INVALID_ARG, "leb_build_sparse: density is NULL");
+  return build_common(nullptr, sp, cam, target_px, opts_in, st, out);
 }
 
 // Extra channels: checked first (all of them), then reduced per tet; the

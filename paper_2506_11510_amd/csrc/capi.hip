@@ -14,6 +14,8 @@
 namespace tv {
 
 int build_grid(const tet_density*, const tet_camera*, float, const tet_build_opts*, hipStream_t, tet_grid**);
+int build_grid_sparse(const tet_sparse_density*, const tet_camera*, float, const tet_build_opts*, hipStream_t,
+                      tet_grid**);
 int grid_set_channels(tet_grid*, const tet_channels*, hipStream_t);
 int grid_export_channels(const tet_grid*, float*, float*, float*, int32_t);
 int grid_set_density_model(tet_grid*, const tet_density*, int32_t, hipStream_t);
@@ -261,6 +263,11 @@ void tet_render_opts_defaults(tet_render_opts* o) {
 int leb_build(const tet_density* density, const tet_camera* camera, float target_cell_px, const tet_build_opts* opts,
               void* hip_stream, tet_grid** out) {
   TV_GUARD(build_grid(density, camera, target_cell_px, opts, (hipStream_t)hip_stream, out));
+}
+
+int leb_build_sparse(const tet_sparse_density* density, const tet_camera* camera, float target_cell_px,
+                     const tet_build_opts* opts, void* hip_stream, tet_grid** out) {
+  TV_GUARD(build_grid_sparse(density, camera, target_cell_px, opts, (hipStream_t)hip_stream, out));
 }
 
 int tet_grid_info(const tet_grid* g, int64_t* num_tets, int32_t* max_depth, tet_build_stats* stats) {

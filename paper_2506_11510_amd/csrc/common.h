@@ -80,7 +80,18 @@ struct Pyramid {
   const float* mn[kMaxLevels];
   const float* mx[kMaxLevels];
   const double* sum[kMaxLevels];
+  // sparse volume (zero outside 8^3 bricks; dens and levels 1, 2 unused):
+  // brick index at each brick position (nb^3, -1 = empty), and per brick
+  // its 512 voxels (bval) and its level-1 (64 cells) and level-2 (8 cells)
+  // statistics; levels >= 3 are dense as above
+  const int32_t* bmap;
+  int32_t nb;
+  const float* bval;
+  const float* bmn[3];
+  const float* bmx[3];
+  const double* bsum[3];
 };
+constexpr int kBrickBits = 3;  // sparse bricks of 8^3 voxels
 
 // Camera quantities of the camera criterion, FP64.
 struct CamCrit {

@@ -99,6 +99,23 @@ def channels(seed: int, n: int) -> dict:
     return dict(temperature=temperature, albedo=np.clip(albedo, 0.0, 1.0), g=np.clip(g, -0.4, 0.85))
 
 
+def bricks(density: np.ndarray, n: int, keep_empty: int = 0, seed: int = 0):
+    """Sparse (OpenVDB-like leaf) form of an n^3 volume: the 8^3 bricks that
+    hold a nonzero voxel, as (coords (B, 3) int32 in brick units, values
+    (B, 512) float32, x fastest), in a seeded random order; `keep_empty`
+    all-zero bricks are listed too (a sparse file may carry them)."""
+    nb = n // 8
+    v = np.asarray(density, np.float32).reshape(nb, 8, nb, 8, nb, 8)  # [bz, z, by, y, bx, x]
+    v = v.transpose(0, 2, 4, 1, 3, 5).reshape(nb * nb * nb, 512)  # brick (bz, by, bx), voxel (z, y, x)
+    occupied = np.flatnonzero(v.any(axis=1))
+    rng = np.random.default_rng(seed)
+    empty = np.setdiff1d(np.arange(nb ** 3), occupied)
+    pick = np.concatenate([occupied, rng.choice(empty, size=min(keep_empty, len(empty)), replace=False)])
+    pick = pick[rng.permutation(len(pick))]
+    coords = np.stack([pick % nb, (pick // nb) % nb, pick // (nb * nb)], axis=1).astype(np.int32)
+    return coords, np.ascontiguousarray(v[pick])
+
+
 def _unit(v):
     l = math.sqrt(sum(x * x for x in v))
     return [x / l for x in v]
