@@ -108,3 +108,31 @@ def test_channel_errors(tv):
         tv.render(g, sc["camera"], sc["medium"], sc["light"], 1, 1, dict(r, emission=[1.0, -1.0, 0.0]))
     with pytest.raises(tv.TetError):  # batches carry no channels
         tv.render_batch([g], [sc["camera"]], [sc["medium"]], [sc["light"]], [1], [1], r)
+
+
+@pytest.mark.timeout(900)
+def test_cloud_full_size_channels(tv):
+    """The benchmark frame (256^3 cloud, 7 M tets, 1024^2, 32 spp, 32
+    bounces) with 256^3 temperature, albedo and g channels: per-tet values
+    bit-exact, image on a strided pixel subset the oracle renders."""
+    import torch
+    sc = synthetic.scene("cloud")
+    d = sc["density_fn"]()
+    ch = synthetic.channels(7, 256)
+    say("case channels cloud: gpu build")
+    g = tv.leb_build(torch.from_numpy(d).cuda(), 256, sc["camera"], build=sc["build"])
+    g.set_channels(256, **{k: torch.from_numpy(v).cuda() for k, v in ch.items()})
+    say("case channels cloud: oracle build", g.info())
+    o = oracle.leb_build(d, 256, sc["camera"], sc["build"])
+    o.set_channels(256, **ch)
+    a, b = g.export_channels(), o.export_channels()
+    for k in ("temperature", "albedo", "g"):
+        assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), k
+    r = dict(sc["render"], channels=1, emission=[0.6, 0.35, 0.15])
+    say("case channels cloud: gpu render")
+    img, st = tv.render(g, sc["camera"], sc["medium"], sc["light"], 32, 2026, r)
+    img = img.cpu().numpy().reshape(-1, 3)
+    say("case channels cloud: oracle subset", st)
+    pix = np.arange(0, 1024 * 1024, 4093, dtype=np.int32)
+    ref, _ = o.render(sc["camera"], sc["medium"], sc["light"], 32, 2026, r, pixels=pix, threads=8)
+    assert_image_parity(img[pix], ref, "cloud channels subset")

@@ -91,30 +91,41 @@ def test_constant_volume_is_the_plain_tracer(tv, model, trans):
     assert sm["null_collisions"] == 0 and sm["tet_steps"] == sa["tet_steps"]
 
 
-@pytest.mark.timeout(900)
-def test_cloud_full_size_linear(tv):
-    """The benchmark frame (256^3 cloud, 1024^2, 32 spp, 32 bounces) with
-    the linear model: per-tet values bit-exact, image on a strided pixel
-    subset the oracle renders."""
+@pytest.fixture(scope="module")
+def cloud_grids(tv):
     import torch
     sc = synthetic.scene("cloud")
     d = sc["density_fn"]()
     say("case density model cloud: gpu build")
     g = tv.leb_build(torch.from_numpy(d).cuda(), 256, sc["camera"], build=sc["build"])
-    g.set_density_model(1, torch.from_numpy(d).cuda(), 256, sc["build"]["density_scale"])
     say("case density model cloud: oracle build", g.info())
     o = oracle.leb_build(d, 256, sc["camera"], sc["build"])
-    o.set_density_model(1, d, 256, sc["build"]["density_scale"])
+    return sc, d, g, o
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("model,trans", [(1, 0), (2, 1)])
+def test_cloud_full_size(tv, cloud_grids, model, trans):
+    """The benchmark frame (256^3 cloud, 7 M tets, 1024^2, 32 spp, 32
+    bounces) with each model: per-tet values bit-exact, image on a strided
+    pixel subset the oracle renders."""
+    import torch
+    sc, d, g, o = cloud_grids
+    scale = sc["build"]["density_scale"]
+    g.set_density_model(model, torch.from_numpy(d).cuda(), 256, scale)
+    o.set_density_model(model, d, 256, scale)
     a, b = g.export_density_model(), o.export_density_model()
     assert np.array_equal(a["majorant"].view(np.uint32), b["majorant"].view(np.uint32))
-    assert np.array_equal(a["coef"].view(np.uint32), b["coef"].view(np.uint32))
-    say("case density model cloud: gpu render")
-    img, st = tv.render(g, sc["camera"], sc["medium"], sc["light"], 32, 2025, sc["render"])
+    if model == 1:
+        assert np.array_equal(a["coef"].view(np.uint32), b["coef"].view(np.uint32))
+    r = dict(sc["render"], transmittance=trans)
+    say(f"case density model {model} cloud: gpu render")
+    img, st = tv.render(g, sc["camera"], sc["medium"], sc["light"], 32, 2025, r)
     img = img.cpu().numpy().reshape(-1, 3)
-    say("case density model cloud: oracle subset", st)
+    say(f"case density model {model} cloud: oracle subset", st)
     pix = np.arange(0, 1024 * 1024, 4093, dtype=np.int32)
-    ref, rst = o.render(sc["camera"], sc["medium"], sc["light"], 32, 2025, sc["render"], pixels=pix, threads=8)
-    assert_image_parity(img[pix], ref, "cloud linear subset")
+    ref, rst = o.render(sc["camera"], sc["medium"], sc["light"], 32, 2025, r, pixels=pix, threads=8)
+    assert_image_parity(img[pix], ref, f"cloud model {model} subset")
 
 
 def test_model_errors(tv):
