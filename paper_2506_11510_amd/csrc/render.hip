@@ -324,10 +324,21 @@ struct TetMedium32 {
     const int32_t ioff[4] = {((int32_t)(a.x << 9)) >> 9, ((int32_t)(o1 << 9)) >> 9, ((int32_t)(o2 << 9)) >> 9,
                              ((int32_t)(a.z << 4)) >> 9};
     const uint32_t lw[4] = {b.x, b.y, b.z, b.w};
-    float bnum = 1.0f, bden = 0.0f;
-    uint32_t blink = kLink27Boundary;
+    float bnum, bden;
+    uint32_t blink;
+    {  // face 0 against the start quotient 1/0: it wins exactly when it is a candidate
+      const float* e = tab + (lw[0] >> 28);
+      uint32_t sg = (lw[0] >> 27) << 31;
+      float den = __uint_as_float(__float_as_uint(e[0]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(e[9]) ^ sg);
+      float num = (float)ioff[0] - dot;
+      const bool cand = den > 0.0f;
+      bnum = cand ? num : 1.0f;
+      bden = cand ? den : 0.0f;
+      blink = cand ? (lw[0] & kLink27Boundary) : kLink27Boundary;
+    }
 #pragma unroll
-    for (int f = 0; f < 4; f++) {
+    for (int f = 1; f < 4; f++) {
       const float* e = tab + (lw[f] >> 28);
       uint32_t sg = (lw[f] >> 27) << 31;
       float den = __uint_as_float(__float_as_uint(e[0]) ^ sg);
