@@ -840,7 +840,7 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
 // split leaves the list of its new leaves for the rounds that follow.
 constexpr uint32_t kBarrierSpins = 1u << 24;  // about a second of s_sleep per barrier
 constexpr int64_t kSmallCap = 1 << 21;         // leaves the cooperative rounds may reach
-constexpr int64_t kAppendRatio = 64;           // tail rounds: fewer than leaves / 64 splits
+constexpr int64_t kAppendRatio = 16;           // tail rounds: fewer than leaves / 16 splits
 
 struct SmallRounds {
   uint64_t* ids[2];
