@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -30,7 +31,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_TET_STEP = 32  # algorithmic bytes per walk step (compact tet record)
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 NRC_FLOP_PER_QUERY = 2 * (76 * 64 + 3 * 64 * 64 + 64 * 3)  # multiply-adds of the 76-64-64-64-64-3 network
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_cloud1024_traffic.txt")
+TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "render_cloud1024*_traffic.txt")
+LAUNCH_KEYS = ("waves_per_simd", "event_wait", "batch_items", "block_size", "record_layout", "samples_per_item")
 COPY_BYTES = 1 << 30  # plain device copy used to calibrate the traffic counters
 KERNEL_SOURCES = ["paper_2506_11510_amd/csrc/render.hip", "paper_2506_11510_amd/csrc/common.h"]
 
@@ -56,13 +58,23 @@ def read_kv(path):
     return out
 
 
-def measured_traffic():
+def measured_traffic(launch: dict):
     """HBM bytes per tracing-kernel launch from the committed rocprofv3
-    counter runs, or None when the kernel source changed since."""
-    t = read_kv(TRAFFIC_FILE)
-    if t.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in t:
-        return None
-    return float(t["traffic_bytes_per_launch"])
+    counter runs of this launch configuration, or None when none was
+    profiled or the kernel source changed since."""
+    import glob
+    want = {k: int(launch[k]) for k in LAUNCH_KEYS}
+    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+        t = read_kv(path)
+        if t.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in t:
+            continue
+        try:
+            got = json.loads(t.get("launch", "{}"))
+        except ValueError:
+            continue
+        if {k: got.get(k) for k in LAUNCH_KEYS} == want:
+            return float(t["traffic_bytes_per_launch"])
+    return None
 
 
 def _counter_rows(d):
@@ -100,6 +112,9 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
         f.write(f"# command: {command}\n")
         f.write("# counters are KiB per dispatch; the copy factors map a plain 1 GiB device copy to 1 GiB\n")
         f.write(f"source_hash = {kernel_source_hash()}\n")
+        m = re.search(r"--launch '(\{[^']*\})'", command)
+        if m:
+            f.write(f"launch = {m.group(1)}\n")
         f.write(f"dispatches = {len(ft)}\n")
         f.write(f"fetch_kib_per_launch = {f_kib:.1f}\n")
         f.write(f"write_kib_per_launch = {w_kib:.1f}\n")
@@ -613,7 +628,7 @@ def main():
                      "kernel": "k_render<TetMedium%s, %d, 0, false, false>" % ("32" if sc["render"]["record_layout"] == 32 else "",
                                                                  sc["render"]["waves_per_simd"]), "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(sc["render"]),
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP)},
         "cpu_baseline": None,
     }
