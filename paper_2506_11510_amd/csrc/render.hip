@@ -621,6 +621,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #define TV_OUT (BATCH ? TV_SC.out : A.out)
 #define TV_SUN (BATCH ? make_float3(TV_SC.sun[0], TV_SC.sun[1], TV_SC.sun[2]) : sun0)
 
+  // real collision at t: start the light ray (from the event section, or
+  // right after the walk step in the variants without a radiance cache)
+  auto start_light = [&]() {
+    n_real++;
+    float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+    bounce++;
+    if ((NRC == 2 || (NRC == 1 && trainp)) && (int32_t)bounce <= A.rec_vertices) {
+      uint32_t j = NRC == 2 ? ent : ent - A.train_ent0;
+      float4* q = A.vrec + ((size_t)j * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
+      q[0] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
+      q[1] = make_float4(d.x, d.y, d.z, beta);
+      q[2] = make_float4(L.x, L.y, L.z, 0.0f);
+    }
+    jf = 0;
+    jn = 0;
+    // extra channels of the collision's tet: the emitted radiance by
+    // the collision estimator (absorbed part of the collision), then the
+    // tet's albedo in place of the medium's
+    float alb = TV_ALBEDO;
+    if (EXT && A.ch_a) alb = A.ch_a[cell];
+    if (EXT && A.ch_t) {
+      const float e = (1.0f - alb) * A.ch_t[cell];
+      L.x = L.x + beta * (e * A.emission[0]);
+      L.y = L.y + beta * (e * A.emission[1]);
+      L.z = L.z + beta * (e * A.emission[2]);
+    }
+    beta = beta * alb;
+    dsave = d;
+    o = x;
+    d = TV_SUN;
+    t = 0.0f;
+    cell_x = cell;
+    od = A.transmittance == 0 ? 0.0f : 1.0f;
+    if (A.transmittance != 0) tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamLight, jn++));
+    set_segment(tab, o, d, Med::kOriginScale);
+    mode = M_SHADOW;
+  };
+
   for (;;) {
     // ================= events: run when enough lanes wait for one, or when
     // no lane is walking (waiting lanes idle meanwhile)
@@ -648,41 +686,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           }
         }
       }
-      if (mode == M_COLLIDE) {  // real collision at t: start the light ray
-        n_real++;
-        float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-        bounce++;
-        if ((NRC == 2 || (NRC == 1 && trainp)) && (int32_t)bounce <= A.rec_vertices) {
-          uint32_t j = NRC == 2 ? ent : ent - A.train_ent0;
-          float4* q = A.vrec + ((size_t)j * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
-          q[0] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
-          q[1] = make_float4(d.x, d.y, d.z, beta);
-          q[2] = make_float4(L.x, L.y, L.z, 0.0f);
-        }
-        jf = 0;
-        jn = 0;
-        // extra channels of the collision's tet: the emitted radiance by
-        // the collision estimator (absorbed part of the collision), then the
-        // tet's albedo in place of the medium's
-        float alb = TV_ALBEDO;
-        if (EXT && A.ch_a) alb = A.ch_a[cell];
-        if (EXT && A.ch_t) {
-          const float e = (1.0f - alb) * A.ch_t[cell];
-          L.x = L.x + beta * (e * A.emission[0]);
-          L.y = L.y + beta * (e * A.emission[1]);
-          L.z = L.z + beta * (e * A.emission[2]);
-        }
-        beta = beta * alb;
-        dsave = d;
-        o = x;
-        d = TV_SUN;
-        t = 0.0f;
-        cell_x = cell;
-        od = A.transmittance == 0 ? 0.0f : 1.0f;
-        if (A.transmittance != 0) tau = exp_tau(uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamLight, jn++));
-        set_segment(tab, o, d, Med::kOriginScale);
-        mode = M_SHADOW;
-      }
+      if (mode == M_COLLIDE) start_light();
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
         float Tr = A.transmittance == 0 ? exp_neg(od) : od;
         float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
@@ -881,6 +885,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
             if (collided) {
               t = tc;
               mode = M_COLLIDE;
+              if constexpr (NRC == 0) start_light();  // the lane walks its light ray next iteration
             } else {
               t = st.te;
               if (st.next < 0) mode = M_ESCAPE;
