@@ -251,9 +251,9 @@ int tet_autotune(const tet_grid* grid, const tet_camera* camera, const tet_mediu
 /* Extra channels per tet (paper, "Volumetric Path Tracing": the
  * implementation also carries e.g. temperature, albedo and phase-function
  * parameters per tet).  Each given channel -- n^3 FP32 voxels, x fastest,
- * over the unit cube, n a power of two <= 4096, any n -- is reduced per tet
- * to the mean over the voxels of the tet's bounding box, the rule and
- * summation order of the extinction.  temperature >= 0, albedo in [0, 1],
+ * over the unit cube, n a power of two <= 4096 (independent of the density's
+ * resolution) -- is reduced per tet to the mean over the voxels of the tet's
+ * bounding box, the rule and summation order of the extinction.  temperature >= 0, albedo in [0, 1],
  * g in (-1, 1), else TET_ERR_NUMERIC and the grid is unchanged; NULL =
  * absent.  Replaces the grid's channels.  Buffers are the caller's. */
 typedef struct {
