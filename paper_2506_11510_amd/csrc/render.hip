@@ -621,8 +621,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #define TV_OUT (BATCH ? TV_SC.out : A.out)
 #define TV_SUN (BATCH ? make_float3(TV_SC.sun[0], TV_SC.sun[1], TV_SC.sun[2]) : sun0)
 
-  // real collision at t: start the light ray (from the event section, or
-  // right after the walk step in the variants without a radiance cache)
+  // real collision at t: start the light ray (right after the walk step, or
+  // from the event section for the collisions where a path hands over to the
+  // radiance cache)
   auto start_light = [&]() {
     n_real++;
     float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
@@ -885,7 +886,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
             if (collided) {
               t = tc;
               mode = M_COLLIDE;
-              if constexpr (NRC == 0) start_light();  // the lane walks its light ray next iteration
+              // the lane walks its light ray next iteration (a path that hands
+              // over to the cache at this vertex appends its query in the
+              // event section instead: that append is wave-wide)
+              if (NRC != 1 || trainp || (int32_t)bounce + 1 != A.truncate) start_light();
             } else {
               t = st.te;
               if (st.next < 0) mode = M_ESCAPE;
