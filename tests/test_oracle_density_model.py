@@ -9,6 +9,8 @@ import math
 
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 from scipy import ndimage
 
 import oracle
@@ -276,3 +278,37 @@ def test_density_model_input_checks():
     g.set_density_model(2, d, n, 1.0)
     with pytest.raises(oracle.OracleError):  # voxel lookups: no analytic light transmittance
         g.render(TINY["camera"], TINY["medium"], TINY["light"], 1, 1, dict(TINY["render"], transmittance=0))
+
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2 ** 31 - 1), logn=st.integers(1, 3), depth=st.integers(0, 8),
+       scale=st.floats(0.25, 4.0))
+def test_model_bounds_random_volumes(seed, logn, depth, scale):
+    """For random volumes (including constant and zero regions) and grid
+    depths: the linear model never exceeds its majorant inside a tet (FP32
+    evaluation, tolerance of its rounding) and reproduces the vertex values;
+    the voxel model's majorant is the largest voxel value any interior point
+    of the tet can look up."""
+    n = 2 ** logn
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.0, 5.0, n ** 3).astype(np.float32)
+    d[rng.random(n ** 3) < 0.3] = 0.0
+    g = uniform_grid(d, n, depth)
+    verts = g.export()["verts"].astype(np.float64) / S
+    T = len(verts)
+    g.set_density_model(1, d, n, scale)
+    m = g.export_density_model()
+    lam = rng.dirichlet(np.ones(4), size=T)
+    x = np.einsum("tj,tja->ta", lam, verts)
+    s32 = eval_linear(m["coef"], x).astype(np.float64)
+    mag = np.abs(m["coef"][:, 0]) + np.abs(m["coef"][:, 1:]).sum(axis=1) + 1.0
+    assert np.all(s32 <= m["majorant"] + 1e-6 * mag)
+    rho = scale * trilinear_scipy(d, n, verts.reshape(-1, 3)).reshape(T, 4)
+    np.testing.assert_allclose(m["majorant"], rho.max(axis=1), rtol=2e-7, atol=1e-6)
+    g.set_density_model(2, d, n, scale)
+    m2 = g.export_density_model()
+    vol = d.reshape(n, n, n)
+    idx = np.clip(np.floor(x * n).astype(np.int64), 0, n - 1)
+    looked = np.float32(scale) * vol[idx[:, 2], idx[:, 1], idx[:, 0]]
+    assert np.all(looked <= m2["majorant"])
