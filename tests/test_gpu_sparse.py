@@ -127,3 +127,29 @@ def test_sparse_edge_cases(tv):
     with pytest.raises(tv.TetError) as ex:
         tv.leb_build_sparse(np.zeros((0, 3), np.int32), np.zeros((0, 512), np.float32), 4, cam, build=b)
     assert ex.value.status == -1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_sparse_random_bricks(tv, seed):
+    """Random brick subsets of random volumes (some bricks all zero, values
+    with exact ties), the paper's criteria: sparse and dense builds agree bit
+    for bit."""
+    say(f"case sparse random bricks seed {seed}")
+    import torch
+    rng = np.random.default_rng(100 + seed)
+    n = [16, 32, 64, 32][seed]
+    nb = n // 8
+    keep = rng.random(nb ** 3) < [0.1, 0.3, 0.6, 1.0][seed]
+    vals = np.round(rng.uniform(0.0, 8.0, (nb ** 3, 512)), 1).astype(np.float32)
+    vals[rng.random(nb ** 3) < 0.2] = 0.0
+    pick = np.flatnonzero(keep)
+    coords = np.stack([pick % nb, (pick // nb) % nb, pick // (nb * nb)], axis=1).astype(np.int32)
+    values = vals[pick]
+    d = oracle.densify(coords, values, n)
+    sc = synthetic.scene("blobs_adaptive")
+    b = dict(sc["build"], max_depth=14, variation_tau=[0.1, 0.3, 0.5, 0.2][seed], majorant_mode=seed % 2)
+    order = rng.permutation(len(coords))
+    g = tv.leb_build_sparse(torch.from_numpy(coords[order]).cuda(), torch.from_numpy(values[order]).cuda(), n,
+                            sc["camera"], build=b)
+    dense = tv.leb_build(torch.from_numpy(d).cuda(), n, sc["camera"], build=b)
+    assert_grids_equal(g.export(), dense.export(), f"random bricks {seed}")
