@@ -159,3 +159,30 @@ def test_model_errors(tv):
     with pytest.raises(tv.TetError):
         g.export_density_model()
     tv.render(g, sc["camera"], sc["medium"], sc["light"], 1, 1, r)  # the plain tracer again
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_model_values_random_volumes(tv, seed):
+    """Random volumes (zeros, exact ties, a constant block) on uniform and
+    adaptive grids: majorants and coefficients bit-exact for both models."""
+    say(f"case density model random volume seed {seed}")
+    import torch
+    rng = np.random.default_rng(300 + seed)
+    n = [8, 16, 32][seed]
+    d = np.round(rng.uniform(0.0, 6.0, n ** 3), 1).astype(np.float32)
+    d[rng.random(n ** 3) < 0.3] = 0.0
+    d.reshape(n, n, n)[: n // 2, : n // 2, : n // 2] = 2.5
+    sc = synthetic.scene("blobs_adaptive")
+    b = dict(sc["build"], max_depth=[9, 12, 14][seed], variation_tau=0.2)
+    if seed == 0:
+        b = dict(b, want_mode=1, uniform_depth=9, max_depth=9)
+    g = tv.leb_build(torch.from_numpy(d).cuda(), n, sc["camera"], build=b)
+    o = oracle.leb_build(d, n, sc["camera"], b)
+    for model in (1, 2):
+        scale = [0.5, 1.75, 3.0][seed]
+        g.set_density_model(model, d, n, scale)
+        o.set_density_model(model, d, n, scale)
+        a, r = g.export_density_model(), o.export_density_model()
+        assert np.array_equal(a["majorant"].view(np.uint32), r["majorant"].view(np.uint32)), model
+        if model == 1:
+            assert np.array_equal(a["coef"].view(np.uint32), r["coef"].view(np.uint32))
