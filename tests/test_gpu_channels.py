@@ -136,3 +136,26 @@ def test_cloud_full_size_channels(tv):
     pix = np.arange(0, 1024 * 1024, 4093, dtype=np.int32)
     ref, _ = o.render(sc["camera"], sc["medium"], sc["light"], 32, 2026, r, pixels=pix, threads=8)
     assert_image_parity(img[pix], ref, "cloud channels subset")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_channel_values_random(tv, seed):
+    """Random channel grids at resolutions other than the density's (values
+    at the range ends, exact ties): per-tet means bit-exact."""
+    say(f"case channels random seed {seed}")
+    import torch
+    rng = np.random.default_rng(500 + seed)
+    sc = synthetic.scene(["tiny", "blobs_adaptive"][seed])
+    d = sc["density_fn"]()
+    g = tv.leb_build(torch.from_numpy(d).cuda(), sc["n"], sc["camera"], build=sc["build"])
+    o = oracle.leb_build(d, sc["n"], sc["camera"], sc["build"])
+    n = [8, 128][seed]
+    t = np.round(rng.uniform(0.0, 10.0, n ** 3), 2).astype(np.float32)
+    a = rng.choice(np.array([0.0, 0.25, 1.0], np.float32), n ** 3)
+    gg = rng.uniform(-0.99, 0.99, n ** 3).astype(np.float32)
+    ch = dict(temperature=t, albedo=a, g=gg)
+    g.set_channels(n, **ch)
+    o.set_channels(n, **ch)
+    x, y = g.export_channels(), o.export_channels()
+    for k in ch:
+        assert np.array_equal(x[k].view(np.uint32), y[k].view(np.uint32)), k
