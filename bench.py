@@ -327,6 +327,28 @@ def regular_grid_1024_leg(tv, torch, dev, sc, steps: int = 2) -> dict:
             "cells_ratio": round(n ** 3 / info["num_tets"], 1)}
 
 
+def host_io_leg(tv, torch, d, sc, steps: int = 3) -> dict:
+    """The same step with host buffers at the boundary: the density read
+    from host memory (uploaded over PCIe by the build) and the image
+    written to host memory (copied back by the render)."""
+    import numpy as np
+    cam, spp = sc["camera"], sc["render"]["spp"]
+    img = np.empty((cam["height"], cam["width"], 3), np.float32)
+    g = tv.leb_build(d, sc["n"], cam, build=sc["build"])
+    tv.render(g, cam, sc["medium"], sc["light"], spp, 5, sc["render"], out=img)
+    del g
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        g = tv.leb_build(d, sc["n"], cam, build=sc["build"])
+        tv.render(g, cam, sc["medium"], sc["light"], spp, 900 + i, sc["render"], out=img)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_step": round(ms, 3),
+            "msamples_per_s": round(cam["width"] * cam["height"] * spp / (ms / 1e3) / 1e6, 3),
+            "bytes_over_pcie_per_step": int(d.nbytes + img.nbytes)}
+
+
 def plume_leg(tv, torch) -> dict:
     """The production-scale configuration: 1024^3 plume density resident in
     HBM, adaptive LEB build (~86 M tets), 1024^2 renders at 32 and 1024 spp
@@ -635,6 +657,7 @@ def main():
     if not args.no_dda:
         res["dda"] = dda_leg(tv, dev, sc)
         res["dda"]["tet_vs_dda_render_speedup"] = round(res["dda"]["ms"] / mean_render_ms, 3)
+    res["host_buffers"] = host_io_leg(tv, torch, d, sc)
     if not args.no_dda:
         res["regular_grid_1024"] = regular_grid_1024_leg(tv, torch, dev, sc)
     if not args.no_batch:
