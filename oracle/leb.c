@@ -14,22 +14,22 @@
  *      unique longest edge of every tet of these grids (pinned by a test);
  *      children:  first  = (x0..x_{k-1}, z, x_{k+1}..x3),
  *                 second = (x1..x_k,     z, x_{k+1}..x3),  z = (x0+xk)/2.
- *   3. Propagation ("a deterministic rule that guarantees a conforming
- *      grid").  Reading: the recursive conforming refinement of a tet T:
+ *   3. Propagation (the paper spreads each bisection to the neighbours by a
+ *      fixed rule that keeps the grid conforming).  Reading: the recursive conforming refinement of a tet T:
  *      while some leaf sharing T's refinement edge e has a different
  *      refinement edge, refine that leaf first; then bisect every leaf of the
  *      star of e.  This keeps the mesh conforming after every call.
  *   4. Subdivision criteria.  Density variation: (max D - min D) / mean D
- *      above a threshold tau.  Reading of D ("all density values present in
- *      a cell's volume"): the voxels overlapping the open bounding box of the
+ *      above a threshold tau.  Reading of D (the paper: every density value
+ *      inside the cell): the voxels overlapping the open bounding box of the
  *      tet, summarised through a min/max/sum pyramid (definition below).
  *      Camera: no split outside the view frustum or below a projected size
  *      of target_px pixels.  Reading of both tests: see want_camera().
  *   5. Neighbour table: for each face, the unique other leaf having the same
  *      three vertices (found by hashing sorted vertex triples), plus the
  *      index of that face in the neighbour ("back face").
- *   6. Per-tet medium: one extinction value per tet ("a volumetric density
- *      value per tetrahedron").  Reading: density_scale * mean(D(T)); the
+ *   6. Per-tet medium: one extinction value per tet (the paper stores one
+ *      density per tet).  Reading: density_scale * mean(D(T)); the
  *      majorant is that value (tight) or density_scale * max(D(T)).
  *   7. Face orientation codes: the outward normal of every face is one of 18
  *      directions (+-axes, +-face diagonals); code = 2 * (direction index) +
@@ -453,8 +453,8 @@ static void camera_frame(bctx* c) {
   c->tgt2 = (double)c->o.target_px * (double)c->o.target_px;
 }
 
-/* Camera criterion.  Reading (the paper gives no measure of "projects into
- * less than one pixel"): centroid c, bounding radius l = longest edge
+/* Camera criterion.  Reading (the paper gives no measure of a tet's projected
+ * size against one pixel): centroid c, bounding radius l = longest edge
  * (>= 4/3 of the largest centroid-vertex distance), w = c - pos.
  *   in frustum  <=>  f.w >= -l and n_p.w >= -l for the 4 inward side normals
  *   big enough  <=>  |w|^2 <= l^2  or  l^2 k_px^2 > target^2 |w|^2

@@ -33,7 +33,7 @@
  *     majorant comes from the model and each tentative collision evaluates
  *     the extinction at its point; the analytic light transmittance of the
  *     linear model integrates it exactly per segment (trapezoid rule).
- * Cell marching ("at most 4 ray/tetrahedron intersections per cell"; stored
+ * Cell marching (at most four ray/face tests per cell in the paper; stored
  * normals let the direction rule faces out, leaving at most 3): for a face
  * with outward normal n (entries -1, 0, 1) and offset o_f,
  *   den = (n.x d.x + n.y d.y) + n.z d.z,  only den > 0 can be an exit,
