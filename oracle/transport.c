@@ -50,8 +50,9 @@
  * seed, counter = (pixel, sample, (bounce << 8) | stream, draw >> 2), word
  * draw & 3; u = (word >> 8) * 2^-24.  Streams: 0 camera, 1 free flight,
  * 2 phase, 3 light transmittance.  "bounce" = number of real collisions so
- * far.  All arithmetic is FP32 (transcendentals by the explicit algorithms
- * below) except the exact FP64 comparison of exit quotients.
+ * far.  Arithmetic is FP32 except the exact FP64 comparison of exit
+ * quotients and the transcendentals (FP64 library functions on the FP32
+ * argument, rounded once to FP32).
  */
 #include "oracle_internal.h"
 #include <math.h>
@@ -110,93 +111,50 @@ static float rnd(rng_t* r, int stream) {
   return oracle_uniform(r->seed, r->pixel, r->sample, r->bounce, (uint32_t)stream, r->draws[stream]++);
 }
 
-/* ---------------- FP32 elementary functions ----------------
- * Transcendentals are evaluated by explicit FP32 algorithms, so that every
- * implementation following these steps rounds identically:
- *   -ln(1-u):   y = 1-u = m 2^e with m in [sqrt(1/2), sqrt(2)); with
- *               s = (m-1)/(m+1), ln m = 2 atanh(s) = 2s + s z (2/3 + z (2/5 +
- *               z (2/7 + z 2/9))), z = s^2 (series truncation < 1e-9);
- *               ln y = e ln2 + ln m.
- *   e^-x:       Cody-Waite reduction x = k ln2 + r (ln2 split in a 16-bit
- *               head and a tail), e^-r by its Taylor polynomial of degree 7
- *               (|r| <= ln2/2, truncation < 6e-9), scaled by 2^-k.
- *   cos, sin of 2 pi u (u in [0,1)): quadrant q = round(4u), w = u - q/4
- *               (exact), theta = 2 pi w, Taylor polynomials to degree 12 /
- *               11 (|theta| <= pi/4, truncation < 1e-12), rotated by q.
- * Accuracy against FP64 libm is pinned by tests. */
-float oracle_neglog1m(float u) {
-  float y = 1.0f - u;
-  uint32_t b;
-  memcpy(&b, &y, 4);
-  int e = (int)((b >> 23) & 0xFF) - 127;
-  uint32_t mb = (b & 0x7FFFFFu) | 0x3F800000u;
-  float m;
-  memcpy(&m, &mb, 4);
-  if (m > 1.41421354f) {
-    m = m * 0.5f;
-    e = e + 1;
-  }
-  float f = m - 1.0f;
-  float sv = f / (2.0f + f);
-  float z = sv * sv;
-  float lnm = 2.0f * sv + sv * z * (0.666666667f + z * (0.4f + z * (0.285714286f + z * 0.222222222f)));
-  float lny = (float)e * 0.693147182f + lnm;
-  return 0.0f - lny;
-}
+/* ---------------- elementary functions ----------------
+ * Every transcendental of the method is taken at its plain definition: the
+ * FP64 C library function evaluated on the FP32 argument (exact in FP64) and
+ * rounded once to FP32.  A device implementation that meets the same
+ * definition to within an FP32 ulp or so reproduces the oracle's paths except
+ * where a comparison sits within that ulp. */
+float oracle_neglog1m(float u) { return (float)(0.0 - log1p(-(double)u)); }
 
-float oracle_expneg(float x) {
-  if (!(x < 104.0f)) return 0.0f;
-  int k = (int)(x * 1.44269504f + 0.5f);
-  float r = (x - (float)k * 0.693145752f) - (float)k * 1.42860677e-06f;
-  float y = 0.0f - r;
-  float p = 1.0f + y * (1.0f + y * (0.5f + y * (0.166666667f + y * (0.0416666667f + y * (0.00833333333f +
-            y * (0.00138888889f + y * 0.000198412698f))))));
-  return ldexpf(p, -k);
-}
+float oracle_expneg(float x) { return (float)exp(-(double)x); }
 
 void oracle_sincos2pi(float u, float* c, float* s) {
-  int q = (int)(u * 4.0f + 0.5f);
-  float w = u - (float)q * 0.25f;
-  float th = w * 6.28318531f;
-  float z = th * th;
-  float sn = th * (1.0f + z * (-0.166666667f + z * (0.00833333333f + z * (-0.000198412698f +
-             z * (2.75573192e-06f + z * -2.50521084e-08f)))));
-  float cs = 1.0f + z * (-0.5f + z * (0.0416666667f + z * (-0.00138888889f + z * (2.48015873e-05f +
-             z * (-2.75573192e-07f + z * 2.08767570e-09f)))));
-  switch (q & 3) {
-    case 0: *c = cs; *s = sn; break;
-    case 1: *c = 0.0f - sn; *s = cs; break;
-    case 2: *c = 0.0f - cs; *s = 0.0f - sn; break;
-    default: *c = sn; *s = 0.0f - cs; break;
-  }
+  double a = (2.0 * OR_PI) * (double)u;
+  *c = (float)cos(a);
+  *s = (float)sin(a);
 }
 
-/* Exponential optical depth from a uniform. */
+/* Exponential optical depth from a uniform (inversion of the Exp(1) CDF). */
 static float sample_tau(float u) { return oracle_neglog1m(u); }
 
 /* ---------------- Henyey-Greenstein ---------------- */
 /* p(mu) = (1 - g^2) / (4 pi (1 + g^2 - 2 g mu)^(3/2)), mu = cosine between
- * successive propagation directions; FP32. */
+ * successive propagation directions; FP64, rounded once. */
 float oracle_hg_eval(float g, float mu) {
-  float g2 = g * g;
-  float den = (1.0f + g2) - (2.0f * g) * mu;
-  return (1.0f - g2) / ((12.5663706f * den) * sqrtf(den));
+  double gg = (double)g, m = (double)mu;
+  double g2 = gg * gg;
+  double den = (1.0 + g2) - (2.0 * gg) * m;
+  return (float)((1.0 - g2) / (((4.0 * OR_PI) * den) * sqrt(den)));
 }
 
 /* Inversion of the HG cumulative distribution (mu increasing in u); for
- * |g| < 1e-3 its g -> 0 limit, the isotropic 2u - 1.  FP32. */
+ * |g| < 1e-3 its g -> 0 limit, the isotropic 2u - 1.  FP64, clamped to
+ * [-1, 1], rounded once. */
 float oracle_hg_sample_mu(float g, float u) {
-  float mu;
-  if (fabsf(g) < 1e-3f) {
-    mu = 2.0f * u - 1.0f;
+  double gg = (double)g, uu = (double)u, mu;
+  if (fabs(gg) < 1e-3) {
+    mu = 2.0 * uu - 1.0;
   } else {
-    float g2 = g * g;
-    float sv = (1.0f - g2) / ((1.0f - g) + (2.0f * g) * u);
-    mu = ((1.0f + g2) - sv * sv) / (2.0f * g);
+    double g2 = gg * gg;
+    double sv = (1.0 - g2) / ((1.0 - gg) + (2.0 * gg) * uu);
+    mu = ((1.0 + g2) - sv * sv) / (2.0 * gg);
   }
-  if (mu < -1.0f) mu = -1.0f;
-  if (mu > 1.0f) mu = 1.0f;
-  return mu;
+  if (mu < -1.0) mu = -1.0;
+  if (mu > 1.0) mu = 1.0;
+  return (float)mu;
 }
 
 static void normalize3f(float v[3]) {

@@ -302,3 +302,128 @@ def test_capacity_and_bad_input(dens64):
     bad[5] = -1.0
     assert oracle.leb_build_status(bad, 64, TINY["camera"], TINY["build"]) == -5
     assert oracle.leb_build_status(dens64[:1000], 10, TINY["camera"], TINY["build"]) == -1
+
+
+# ---------------------------------------------------------------- criteria and per-tet medium
+# A camera for which the camera criterion holds for every tet of the cube: far
+# enough that the whole cube sits inside the frustum, and a target size no tet
+# falls below, so want = (depth < max depth) and the density variation alone.
+WIDE = dict(pos=[0.5, 0.5, -3.0], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=60.0, width=64, height=64)
+
+
+def open_box_voxels(G, v):
+    """The voxels of G ([k][j][i], n^3) overlapping the open bounding box of
+    the tet with lattice vertices v (4 x 3): voxel i spans [i, i+1) * S/n on
+    each axis and overlaps (lo, hi) iff i S/n < hi and (i+1) S/n > lo."""
+    n = G.shape[0]
+    vs = S // n
+    idx = np.arange(n)
+    sel = []
+    for a in range(3):
+        lo, hi = int(v[:, a].min()), int(v[:, a].max())
+        sel.append(np.flatnonzero((idx * vs < hi) & ((idx + 1) * vs > lo)))
+    return G[np.ix_(sel[2], sel[1], sel[0])]
+
+
+def test_variation_predicate_on_hand_built_volumes():
+    """Density variation (Subdivision Criteria): a tet is split iff max D -
+    min D > tau * mean D with mean D > 0.  Roots span the whole cube, so D is
+    the whole volume: half the voxels 0.5 and half 1.5 give mean 1 and
+    max - min = 1 exactly, which puts tau = 1 on the boundary (strict >)."""
+    n = 8
+    e = oracle.leb_build(np.ones(n ** 3, np.float32), n, WIDE, dict(want_mode=1, uniform_depth=0, max_tets=64)).export()
+    verts, ids = e["verts"], e["ids"]
+    depth = np.zeros(len(ids), np.int32)
+    b = dict(want_mode=0, max_depth=30, target_px=1e-6, density_scale=1.0, max_tets=1 << 20)
+
+    def w(d, tau):
+        return oracle.want(d, n, WIDE, dict(b, variation_tau=tau), verts, depth, ids)
+
+    half = np.where(np.arange(n ** 3) % 2 == 0, 0.5, 1.5).astype(np.float32)
+    assert w(half, 1.0 - 2.0 ** -40).all()
+    assert not w(half, 1.0).any()  # equal is not "varies above"
+    assert not w(half, 1.0 + 2.0 ** -40).any()
+    assert w(half, 0.0).all() and w(half, -1.0).all()
+    # constant volume: max - min = 0, so only a negative tau splits
+    const = np.full(n ** 3, 3.0, np.float32)
+    assert not w(const, 0.0).any() and w(const, -1e-9).all()
+    # an empty volume (mean 0) is never split, whatever tau
+    zero = np.zeros(n ** 3, np.float32)
+    assert not w(zero, -1.0).any() and not w(zero, 0.0).any()
+    # one hot voxel of value 512 among zeros: mean 1, max - min = 512
+    hot = zero.copy()
+    hot[137] = 512.0
+    assert w(hot, 511.999).all() and not w(hot, 512.0).any()
+    # the same predicate with max depth reached: never split
+    assert not oracle.want(half, n, WIDE, dict(b, variation_tau=0.0, max_depth=0), verts, depth, ids).any()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_variation_predicate_against_brute_force(seed):
+    """Every tet of uniform grids at depths 0-10 on integer-valued volumes
+    (sums exact in any order): the oracle's split decision equals max - min >
+    tau * mean over the voxels of the tet's open bounding box, mean > 0."""
+    rng = np.random.default_rng(seed)
+    n = 16
+    d = (rng.integers(0, 8, n ** 3) * (rng.random(n ** 3) < 0.6)).astype(np.float32)
+    d[: n * n * 3] = 0.0  # a slab of empty voxels: mean-0 boxes
+    G = d.reshape(n, n, n)
+    b = dict(want_mode=0, max_depth=40, target_px=1e-6, density_scale=1.0, max_tets=1 << 20)
+    checked = 0
+    for depth in range(0, 11):
+        e = oracle.leb_build(d, n, WIDE, dict(want_mode=1, uniform_depth=depth, max_tets=1 << 16)).export()
+        verts, ids = e["verts"], e["ids"]
+        dep = np.full(len(ids), depth, np.int32)
+        stats = [(float(B.max()) - float(B.min()), float(B.sum()) / B.size)
+                 for B in (open_box_voxels(G, v) for v in verts)]
+        for tau in (0.0, 0.5, 1.0, 2.5):
+            got = oracle.want(d, n, WIDE, dict(b, variation_tau=tau), verts, dep, ids)
+            want = np.array([m > 0 and r > tau * m for r, m in stats])
+            assert np.array_equal(got, want), f"depth {depth} tau {tau}: {np.flatnonzero(got != want)[:5]}"
+            checked += len(ids)
+    assert checked > 20000
+
+
+@pytest.mark.parametrize("n,scale", [(8, 1.0), (16, 0.37), (16, 2.5)])
+def test_sigma_and_loose_majorant_at_coarse_depths(n, scale):
+    """One density value per tet (Volumetric Path Tracing): sigma = scale *
+    mean of D(T), and in loose mode the majorant = scale * max of D(T), over
+    the voxels of the tet's open bounding box, at depths from the roots to
+    voxel size and one level below, rounded once to FP32 (up to 2000 tets a
+    depth)."""
+    rng = np.random.default_rng(n + int(scale * 100))
+    d = (rng.integers(0, 16, n ** 3) * (rng.random(n ** 3) < 0.7)).astype(np.float32)
+    G = d.reshape(n, n, n)
+    vox = 3 * int(math.log2(n))
+    for depth in sorted(set(range(0, vox, 2)) | {vox - 1, vox, vox + 1}):
+        b = dict(want_mode=1, uniform_depth=depth, density_scale=scale, majorant_mode=1, max_tets=1 << 20)
+        e = oracle.leb_build(d, n, WIDE, b).export()
+        pick = rng.permutation(len(e["ids"]))[:2000]
+        e = {k: e[k][pick] for k in ("verts", "sigma", "majorant")}
+        boxes = [open_box_voxels(G, v) for v in e["verts"]]
+        sc = np.float64(np.float32(scale))  # the scale is an FP32 parameter
+        sig = np.array([np.float32(sc * (float(B.sum()) / B.size)) for B in boxes], np.float32)
+        maj = np.array([np.float32(sc * float(B.max())) for B in boxes], np.float32)
+        assert np.array_equal(e["sigma"].view(np.uint32), sig.view(np.uint32)), f"sigma at depth {depth}"
+        assert np.array_equal(e["majorant"].view(np.uint32), maj.view(np.uint32)), f"majorant at depth {depth}"
+        assert (e["sigma"] <= e["majorant"]).all()
+        tight = oracle.leb_build(d, n, WIDE, dict(b, majorant_mode=0)).export()
+        assert np.array_equal(tight["majorant"][pick].view(np.uint32), sig.view(np.uint32))
+
+
+def test_sigma_of_real_valued_volume_within_rounding():
+    """The same definition on a real-valued volume: sigma within FP32
+    rounding of the exact box mean (the FP64 sum's order is the oracle's
+    own), and the loose majorant exact."""
+    rng = np.random.default_rng(5)
+    n = 16
+    d = (rng.random(n ** 3) * 7.0 * (rng.random(n ** 3) < 0.5)).astype(np.float32)
+    G = d.reshape(n, n, n)
+    for depth in (1, 4, 7, 11):
+        e = oracle.leb_build(d, n, WIDE, dict(want_mode=1, uniform_depth=depth, density_scale=1.0,
+                                              majorant_mode=1, max_tets=1 << 20)).export()
+        for v, s, m in zip(e["verts"], e["sigma"], e["majorant"]):
+            B = open_box_voxels(G, v)
+            exact = float(sum(Fraction(float(x)) for x in B.ravel()) / B.size)
+            assert abs(float(s) - exact) <= 2 ** -23 * abs(exact) + 1e-30
+            assert m == B.max()
