@@ -307,6 +307,22 @@ int tet_grid_export_density_model(const tet_grid* grid, float* majorant, float* 
 int tet_locate(const tet_grid* grid, const float* pts, int64_t count, int64_t* out, int32_t on_device,
                void* hip_stream);
 
+/* The tracer's elementary functions on the device, at n given arguments
+ * (a test hook: their accuracy against the definitions they stand for).
+ * Each is computed in FP64 and rounded once to FP32.  fn:
+ *   0  -ln(1 - a), a in [0, 1)  (the exponential free path of Algorithm 1's
+ *      free-path sampling, from a uniform);
+ *   1  e^-a, a >= 0  (transmittance from an optical depth);
+ *   2  (cos, sin)(2 pi a), a in [0, 1), written to out[2i], out[2i + 1]
+ *      (the azimuth of a scattered direction);
+ *   3  Henyey-Greenstein density of the cosine a for g = b[i];
+ *   4  Henyey-Greenstein inverse CDF at a for g = b[i] (the cosine of a
+ *      phase-function sample).
+ * a, b (fn 3 and 4 only) and out (2n values for fn 2, else n) live on the
+ * same side (on_device); n <= 2^30. */
+int tet_eval_functions(int32_t fn, int64_t n, const float* a, const float* b, float* out, int32_t on_device,
+                       void* hip_stream);
+
 /* The same integrator on the regular voxel grid (the paper's regular-grid
  * reference renderer), voxels walked by Amanatides-Woo traversal. */
 int dda_render(const tet_density* density, const tet_camera* camera, const tet_medium* medium,

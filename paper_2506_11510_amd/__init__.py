@@ -451,6 +451,23 @@ class Nrc:
         return st.as_dict()
 
 
+FUNCTIONS = {"neglog1m": 0, "expneg": 1, "sincos2pi": 2, "hg_pdf": 3, "hg_mu": 4}
+
+
+def eval_functions(name: str, a, b=None) -> np.ndarray:
+    """The tracer's device elementary function `name` (a key of FUNCTIONS)
+    at host arguments a (and g = b for the HG functions); FP32 results,
+    (n, 2) = (cos, sin) for sincos2pi."""
+    fn = FUNCTIONS[name]
+    a = np.ascontiguousarray(a, np.float32).ravel()
+    bb = None if b is None else np.ascontiguousarray(np.broadcast_to(np.float32(b) if np.isscalar(b) else b, a.shape),
+                                                     np.float32)
+    out = np.empty((len(a), 2) if fn == 2 else len(a), np.float32)
+    check(lib().tet_eval_functions(fn, len(a), a.ctypes.data, None if bb is None else bb.ctypes.data,
+                                   out.ctypes.data, 0, _stream()), "tet_eval_functions")
+    return out
+
+
 def release_cache():
     lib().tet_release_cache()
 

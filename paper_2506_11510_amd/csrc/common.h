@@ -219,74 +219,127 @@ __device__ inline uint2 uniform01x2(uint64_t seed, uint32_t pixel, uint32_t samp
 
 enum { kStreamCamera = 0, kStreamFlight = 1, kStreamPhase = 2, kStreamLight = 3 };
 
-// ---- FP32 elementary functions (explicit algorithms, fixed operation order)
-// -ln(1 - u): 1 - u = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
-// s = (m - 1) / (m + 1), series to s^9; ln(1 - u) = e ln2 + ln m.
+// ---- elementary functions.  Each is evaluated in FP64 to about 1e-16
+// relative accuracy and rounded once to FP32: the result is the correctly
+// rounded value of the exact function unless that value lies within ~1e-16
+// (relative) of the midpoint between two FP32 numbers.  FP64 runs at half
+// the FP32 rate here and these run per collision, scattering or light ray,
+// never per walk step.
+
+// -ln(1 - u) for u in [0, 1) (1 - u is exact in FP32): with 1 - u = m 2^e,
+// m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m - 1) / (m + 1),
+// |s| <= 0.1716, by the atanh series through s^21 (truncation < 1e-17
+// relative); ln(1 - u) = e ln 2 + ln m.
 __device__ inline float exp_tau(float u) {
-  float y = 1.0f - u;
-  uint32_t b = __float_as_uint(y);
+  const float y = 1.0f - u;
+  const uint32_t b = __float_as_uint(y);
   int e = (int)((b >> 23) & 0xFFu) - 127;
-  float m = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
-  if (m > 1.41421354f) {
-    m = m * 0.5f;
+  double m = (double)__uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
+  if (m > 1.4142135623730951) {
+    m = m * 0.5;
     e = e + 1;
   }
-  float f = m - 1.0f;
-  float sv = f / (2.0f + f);
-  float z = sv * sv;
-  float lnm = 2.0f * sv + sv * z * (0.666666667f + z * (0.4f + z * (0.285714286f + z * 0.222222222f)));
-  float lny = (float)e * 0.693147182f + lnm;
-  return 0.0f - lny;
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 21.0;
+  p = p * z + 1.0 / 19.0;
+  p = p * z + 1.0 / 17.0;
+  p = p * z + 1.0 / 15.0;
+  p = p * z + 1.0 / 13.0;
+  p = p * z + 1.0 / 11.0;
+  p = p * z + 1.0 / 9.0;
+  p = p * z + 1.0 / 7.0;
+  p = p * z + 1.0 / 5.0;
+  p = p * z + 1.0 / 3.0;
+  p = p * z + 1.0;
+  const double lnm = (2.0 * s) * p;
+  return (float)(0.0 - ((double)e * 0.6931471805599453 + lnm));
 }
 
-// e^-x for x >= 0: x = k ln2 + r (Cody-Waite, ln2 = 16-bit head + tail),
-// degree-7 Taylor polynomial of e^-r, times 2^-k.
+// e^-x for x >= 0 (0 from x >= 104 on, where the FP32 result rounds to 0):
+// x = k ln 2 + r with k = rint(x / ln 2), ln 2 split in a 32-bit head (k ln2_hi
+// exact) and a tail, |r| <= 0.347; e^-r by its Taylor polynomial through
+// degree 13 (truncation < 5e-18), times 2^-k.
 __device__ inline float exp_neg(float x) {
   if (!(x < 104.0f)) return 0.0f;
-  int k = (int)(x * 1.44269504f + 0.5f);
-  float r = (x - (float)k * 0.693145752f) - (float)k * 1.42860677e-06f;
-  float y = 0.0f - r;
-  float p = 1.0f + y * (1.0f + y * (0.5f + y * (0.166666667f + y * (0.0416666667f + y * (0.00833333333f +
-            y * (0.00138888889f + y * 0.000198412698f))))));
-  return ldexpf(p, -k);
+  const double xd = (double)x;
+  const double k = rint(xd * 1.4426950408889634);
+  const double r = (xd - k * 0x1.62e42ffp-1) - k * -0x1.718432a1b0e26p-35;
+  const double y = 0.0 - r;
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = p * y + 1.0 / 479001600.0;
+  p = p * y + 1.0 / 39916800.0;
+  p = p * y + 1.0 / 3628800.0;
+  p = p * y + 1.0 / 362880.0;
+  p = p * y + 1.0 / 40320.0;
+  p = p * y + 1.0 / 5040.0;
+  p = p * y + 1.0 / 720.0;
+  p = p * y + 1.0 / 120.0;
+  p = p * y + 1.0 / 24.0;
+  p = p * y + 1.0 / 6.0;
+  p = p * y + 0.5;
+  p = p * y + 1.0;
+  p = p * y + 1.0;
+  return (float)ldexp(p, -(int)k);
 }
 
-// (cos, sin)(2 pi u), u in [0,1): quadrant q = round(4u), theta = 2 pi (u -
-// q/4), Taylor polynomials to degree 12 / 11, rotated by q.
+// (cos, sin)(2 pi u) for u in [0, 1): quadrant q = round(4u), w = u - q/4
+// (exact), theta = 2 pi w in FP64 (|theta| <= pi/4), Taylor polynomials
+// through degree 18 / 17 (truncation < 1e-19), rotated by q.
 __device__ inline void sincos_2pi(float u, float& c, float& s) {
-  int q = (int)(u * 4.0f + 0.5f);
-  float w = u - (float)q * 0.25f;
-  float th = w * 6.28318531f;
-  float z = th * th;
-  float sn = th * (1.0f + z * (-0.166666667f + z * (0.00833333333f + z * (-0.000198412698f +
-             z * (2.75573192e-06f + z * -2.50521084e-08f)))));
-  float cs = 1.0f + z * (-0.5f + z * (0.0416666667f + z * (-0.00138888889f + z * (2.48015873e-05f +
-             z * (-2.75573192e-07f + z * 2.08767570e-09f)))));
-  int r = q & 3;
+  const int q = (int)(u * 4.0f + 0.5f);
+  const float w = u - (float)q * 0.25f;
+  const double th = (double)w * 6.283185307179586;
+  const double z = th * th;
+  double ps = 1.0 / 355687428096000.0;  // 1/17!
+  ps = ps * z - 1.0 / 1307674368000.0;
+  ps = ps * z + 1.0 / 6227020800.0;
+  ps = ps * z - 1.0 / 39916800.0;
+  ps = ps * z + 1.0 / 362880.0;
+  ps = ps * z - 1.0 / 5040.0;
+  ps = ps * z + 1.0 / 120.0;
+  ps = ps * z - 1.0 / 6.0;
+  ps = ps * z + 1.0;
+  double pc = -1.0 / 6402373705728000.0;  // -1/18!
+  pc = pc * z + 1.0 / 20922789888000.0;
+  pc = pc * z - 1.0 / 87178291200.0;
+  pc = pc * z + 1.0 / 479001600.0;
+  pc = pc * z - 1.0 / 3628800.0;
+  pc = pc * z + 1.0 / 40320.0;
+  pc = pc * z - 1.0 / 720.0;
+  pc = pc * z + 1.0 / 24.0;
+  pc = pc * z - 0.5;
+  pc = pc * z + 1.0;
+  const float sn = (float)(th * ps), cs = (float)pc;
+  const int r = q & 3;
   c = r == 0 ? cs : (r == 1 ? 0.0f - sn : (r == 2 ? 0.0f - cs : sn));
   s = r == 0 ? sn : (r == 1 ? cs : (r == 2 ? 0.0f - sn : 0.0f - cs));
 }
 
-// Henyey-Greenstein density of the cosine between successive propagation
-// directions, FP32.
+// Henyey-Greenstein density of the cosine mu between successive propagation
+// directions, (1 - g^2) / (4 pi (1 + g^2 - 2 g mu)^(3/2)), in FP64 (IEEE
+// division and square root), rounded once.
 __device__ inline float hg_pdf(float g, float mu) {
-  float g2 = g * g;
-  float den = (1.0f + g2) - (2.0f * g) * mu;
-  return (1.0f - g2) / ((12.5663706f * den) * sqrtf(den));
+  const double gd = (double)g, md = (double)mu;
+  const double g2 = gd * gd;
+  const double den = (1.0 + g2) - (2.0 * gd) * md;
+  return (float)((1.0 - g2) / (((4.0 * 3.141592653589793) * den) * sqrt(den)));
 }
 
-// Inverse HG cumulative distribution (isotropic limit 2u - 1 for |g| < 1e-3).
+// Inverse HG cumulative distribution (isotropic limit 2u - 1 for
+// |g| < 1e-3), in FP64, clamped to [-1, 1], rounded once.
 __device__ inline float hg_mu(float g, float u) {
-  float mu;
-  if (fabsf(g) < 1e-3f) {
-    mu = 2.0f * u - 1.0f;
+  const double gd = (double)g, ud = (double)u;
+  double mu;
+  if (fabs(gd) < 1e-3) {
+    mu = 2.0 * ud - 1.0;
   } else {
-    float g2 = g * g;
-    float sv = (1.0f - g2) / ((1.0f - g) + (2.0f * g) * u);
-    mu = ((1.0f + g2) - sv * sv) / (2.0f * g);
+    const double g2 = gd * gd;
+    const double sv = (1.0 - g2) / ((1.0 - gd) + (2.0 * gd) * ud);
+    mu = ((1.0 + g2) - sv * sv) / (2.0 * gd);
   }
-  mu = mu < -1.0f ? -1.0f : (mu > 1.0f ? 1.0f : mu);
-  return mu;
+  mu = mu < -1.0 ? -1.0 : (mu > 1.0 ? 1.0 : mu);
+  return (float)mu;
 }
 
 __device__ inline float3 normalize3(float3 v) {

@@ -1643,4 +1643,52 @@ int locate_points(const tet_grid* g, const float* pts, int64_t count, int64_t* o
   return TET_OK;
 }
 
+// The tracer's elementary functions at given arguments (fn: 0 -ln(1 - a),
+// 1 e^-a, 2 (cos, sin)(2 pi a) into out[2i], out[2i + 1], 3 the HG density
+// of cosine a for g = b, 4 the HG inverse CDF at a for g = b).
+__global__ void k_eval_functions(int fn, int64_t n, const float* __restrict__ a, const float* __restrict__ b,
+                                 float* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float x = a[i];
+  switch (fn) {
+    case 0: out[i] = exp_tau(x); break;
+    case 1: out[i] = exp_neg(x); break;
+    case 2: sincos_2pi(x, out[2 * i], out[2 * i + 1]); break;
+    case 3: out[i] = hg_pdf(b[i], x); break;
+    default: out[i] = hg_mu(b[i], x); break;
+  }
+}
+
+int eval_functions(int32_t fn, int64_t n, const float* a, const float* b, float* out, int32_t on_device,
+                   hipStream_t st) {
+  if (fn < 0 || fn > 4 || n < 0 || n > (1ll << 30) || (n && (!a || !out || (fn >= 3 && !b))))
+    return fail(TET_ERR_INVALID_ARG, "tet_eval_functions: bad arguments");
+  if (n == 0) return TET_OK;
+  const int64_t nout = fn == 2 ? 2 * n : n, nin = fn >= 3 ? 2 * n : n;
+  const float *da = a, *db = b;
+  float* dout = out;
+  char* tmp = nullptr;
+  if (!on_device) {
+    tmp = (char*)dev_alloc((size_t)(nin + nout) * 4);
+    if (!tmp) return fail(TET_ERR_OUT_OF_MEMORY, "tet_eval_functions: scratch");
+    float* ta = (float*)tmp;
+    TV_HIP(hipMemcpyAsync(ta, a, n * 4, hipMemcpyHostToDevice, st));
+    if (fn >= 3) TV_HIP(hipMemcpyAsync(ta + n, b, n * 4, hipMemcpyHostToDevice, st));
+    da = ta;
+    db = ta + n;
+    dout = ta + nin;
+  }
+  struct Free {
+    void* p;
+    ~Free() { if (p) dev_free(p); }
+  } f_{tmp};
+  hipLaunchKernelGGL(k_eval_functions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)fn, n, da,
+                     fn >= 3 ? db : nullptr, dout);
+  TV_HIP(hipGetLastError());
+  if (!on_device) TV_HIP(hipMemcpyAsync(out, dout, nout * 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  return TET_OK;
+}
+
 }  // namespace tv
