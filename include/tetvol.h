@@ -199,6 +199,25 @@ int tet_render(const tet_grid* grid, const tet_camera* camera, const tet_medium*
                int32_t spp, uint64_t seed, const tet_render_opts* opts /* NULL = defaults */, float* out_rgb,
                int32_t on_device, void* hip_stream, tet_render_stats* stats /* nullable */);
 
+/* tet_render for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same render (same kernels, same image up to FP32 summation order),
+ * with its scratch -- per-pass entry records and counters -- in a fixed
+ * device array of 64 MiB + 256 bytes that the library holds on each device
+ * it runs on until the process ends, instead of memory it allocates; the
+ * call makes
+ * no hipMalloc or hipFree and launches on the stream without waiting (the
+ * image is complete once the stream is).  Limits: a tet grid built on the
+ * current device, no radiance cache (opts->nrc NULL), out_rgb on the
+ * device; one sample of every pixel must fit the array (2^21 entry
+ * records: images of up to 2^21 pixels once rounded up to 8 x 8 tiles, e.g.
+ * 2048 x 1024), else TET_ERR_CAPACITY; a frame takes ceil(spp / floor(2^21
+ * / tiled pixels)) passes.  Every call on a device shares its array: calls that
+ * overlap on one device race (serialise them, e.g. on one stream). */
+int tet_render_noalloc(const tet_grid* grid, const tet_camera* camera, const tet_medium* medium,
+                       const tet_light* light, int32_t spp, uint64_t seed, const tet_render_opts* opts,
+                       float* out_rgb, void* hip_stream);
+
 /* Renders n scenes (each its own grid, camera, medium, light, spp and
  * seed) with one persistent launch of the same path tracer: the scenes'
  * samples are work items of one queue, so small images fill the GPU

@@ -224,6 +224,24 @@ def render(grid: Grid, camera: dict, medium: dict, light: dict, spp: int, seed: 
     return out, st.as_dict()
 
 
+def render_noalloc(grid: Grid, camera: dict, medium: dict, light: dict, spp: int, seed: int,
+                   render: dict | None = None, out=None):
+    """tet_render_noalloc: the same render with the library's fixed scratch
+    (no device allocation inside the call) into a torch CUDA tensor `out`
+    (allocated here when None); launches on the current stream without
+    waiting.  Returns the image."""
+    import torch
+    cam = _abi.make_camera(camera)
+    if out is None:
+        out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")
+    assert out.is_cuda and out.is_contiguous() and out.numel() == cam.height * cam.width * 3
+    check(lib().tet_render_noalloc(grid.handle, ctypes.byref(cam), ctypes.byref(_abi.make_medium(medium)),
+                                   ctypes.byref(_abi.make_light(light)), int(spp), int(seed),
+                                   ctypes.byref(_abi.make_render_opts(render)), ctypes.c_void_p(out.data_ptr()),
+                                   _stream()), "tet_render_noalloc")
+    return out
+
+
 def dda_render(density, n: int, density_scale: float, camera: dict, medium: dict, light: dict, spp: int, seed: int,
                render: dict | None = None, out=None):
     """Same integrator on the regular voxel grid (regular-grid reference)."""

@@ -127,6 +127,9 @@ SIGNATURES = {
     "tet_render": (ctypes.c_int, [VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium), ctypes.POINTER(TetLight),
                                   ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(TetRenderOpts), VP, ctypes.c_int32,
                                   VP, ctypes.POINTER(TetRenderStats)]),
+    "tet_render_noalloc": (ctypes.c_int, [VP, ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium),
+                                          ctypes.POINTER(TetLight), ctypes.c_int32, ctypes.c_uint64,
+                                          ctypes.POINTER(TetRenderOpts), VP, VP]),
     "tet_locate": (ctypes.c_int, [VP, VP, ctypes.c_int64, VP, ctypes.c_int32, VP]),
     "tet_eval_functions": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, VP, VP, VP, ctypes.c_int32, VP]),
     "dda_render": (ctypes.c_int, [ctypes.POINTER(TetDensity), ctypes.POINTER(TetCamera), ctypes.POINTER(TetMedium),

@@ -1409,17 +1409,29 @@ bool make_shapes(std::vector<uint32_t>& tab) {
 }
 }  // namespace
 
+namespace {
+std::mutex g_shape_mu;
+std::map<int, uint32_t*> g_shape_tab;  // one copy per device, kept until exit
+}  // namespace
+
+const uint32_t* shape_table_existing() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  auto it = g_shape_tab.find(dev);
+  return it == g_shape_tab.end() ? nullptr : it->second;
+}
+
 const uint32_t* shape_table() {
   static std::once_flag once;
   static std::vector<uint32_t> host;
   static bool ok = false;
   std::call_once(once, [] { ok = make_shapes(host); });
   if (!ok) return nullptr;
-  static std::mutex mu;
-  static std::map<int, uint32_t*> dev_tab;  // one copy per device, kept until exit
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(mu);
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  auto& dev_tab = g_shape_tab;
   auto it = dev_tab.find(dev);
   if (it != dev_tab.end()) return it->second;
   uint32_t* p = nullptr;

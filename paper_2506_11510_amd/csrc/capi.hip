@@ -26,6 +26,8 @@ int render_voxels(const tet_density*, const tet_camera*, const tet_medium*, cons
                   const tet_render_opts*, float*, int32_t, hipStream_t, tet_render_stats*);
 int locate_points(const tet_grid*, const float*, int64_t, int64_t*, int32_t, hipStream_t);
 int eval_functions(int32_t, int64_t, const float*, const float*, float*, int32_t, hipStream_t);
+int render_grid_noalloc(const tet_grid*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
+                        const tet_render_opts*, float*, hipStream_t);
 int render_batch(int32_t, const tet_grid* const*, const tet_camera*, const tet_medium*, const tet_light*,
                  const int32_t*, const uint64_t*, const tet_render_opts*, float* const*, hipStream_t,
                  tet_render_stats*);
@@ -309,6 +311,11 @@ int tet_render(const tet_grid* g, const tet_camera* camera, const tet_medium* me
 
 int tet_locate(const tet_grid* g, const float* pts, int64_t count, int64_t* out, int32_t on_device, void* hip_stream) {
   TV_GUARD(locate_points(g, pts, count, out, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_render_noalloc(const tet_grid* g, const tet_camera* camera, const tet_medium* medium, const tet_light* light,
+                       int32_t spp, uint64_t seed, const tet_render_opts* opts, float* out_rgb, void* hip_stream) {
+  TV_GUARD(render_grid_noalloc(g, camera, medium, light, spp, seed, opts, out_rgb, (hipStream_t)hip_stream));
 }
 
 int tet_eval_functions(int32_t fn, int64_t n, const float* a, const float* b, float* out, int32_t on_device,

@@ -172,6 +172,8 @@ __device__ inline int64_t search_keys_idx(const uint64_t* __restrict__ keys, con
 // if the table could not be made.
 constexpr int kShapeWords = 256;
 const uint32_t* shape_table();
+// The current device's table if it has been made, else NULL (never allocates).
+const uint32_t* shape_table_existing();
 
 // Midpoint z of the edge (v0, vK) and the bisection normal of class word w.
 template <int K>

@@ -38,6 +38,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -998,30 +1000,31 @@ constexpr int64_t kMaxEntriesPerPass = 1ll << 25;  // 1 GiB of entry records
 template <class Med, int NRC>
 static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, int32_t spp, int64_t npix,
                       char* sc, RayEntry* entries, int64_t pass_cap, hipStream_t st, float* ms_total,
-                      float* ms_trace, float* ms_cache) {
+                      float* ms_trace, float* ms_cache, bool timed = true) {
   int bs = o.block_size ? o.block_size : 256;
   int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
   const bool ext = A.model != 0 || A.ch_t || A.ch_a || A.ch_g;
-  hipEvent_t e0, e1, e2, t0, t1;
-  TV_HIP(hipEventCreate(&e0));
-  TV_HIP(hipEventCreate(&e1));
-  TV_HIP(hipEventCreate(&e2));
-  TV_HIP(hipEventCreate(&t0));
-  TV_HIP(hipEventCreate(&t1));
+  // timed: HIP events around the passes, waited for after each pass;
+  // untimed: kernel launches on the stream only
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, t0 = nullptr, t1 = nullptr;
   struct Ev {
-    hipEvent_t a, b, c, d, f;
+    hipEvent_t *a, *b, *c, *d, *f;
     ~Ev() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-      (void)hipEventDestroy(c);
-      (void)hipEventDestroy(d);
-      (void)hipEventDestroy(f);
+      for (hipEvent_t* e : {a, b, c, d, f})
+        if (*e) (void)hipEventDestroy(*e);
     }
-  } ev{e0, e1, e2, t0, t1};
+  } ev{&e0, &e1, &e2, &t0, &t1};
+  if (timed) {
+    TV_HIP(hipEventCreate(&e0));
+    TV_HIP(hipEventCreate(&e1));
+    TV_HIP(hipEventCreate(&e2));
+    TV_HIP(hipEventCreate(&t0));
+    TV_HIP(hipEventCreate(&t1));
+  }
   *ms_total = 0.0f;
   *ms_trace = 0.0f;
   *ms_cache = 0.0f;
-  TV_HIP(hipEventRecord(e0, st));
+  if (timed) TV_HIP(hipEventRecord(e0, st));
   if (A.accumulate && NRC != 2)
     hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3);
   for (int32_t done = 0; done < spp; done += (int32_t)pass_cap) {
@@ -1051,7 +1054,7 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     int64_t grid = (int64_t)cu_count() * bpc;
     int64_t need = ((int64_t)P.items + bs - 1) / bs;
     grid = std::max<int64_t>(1, std::min(grid, need));
-    TV_HIP(hipEventRecord(t0, st));
+    if (timed) TV_HIP(hipEventRecord(t0, st));
     if (NRC != 0) {
       hipLaunchKernelGGL((k_render<Med, 5, NRC>), dim3((unsigned)grid), dim3(bs), 0, st, P, med);
     } else if (ext) {
@@ -1072,23 +1075,28 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
       }
     }
     TV_HIP(hipGetLastError());
-    TV_HIP(hipEventRecord(t1, st));
+    if (timed) TV_HIP(hipEventRecord(t1, st));
     if (NRC == 1)  // the pass's cache queries, added to their pixels
       if (int rc = nrc_query_pass(A.nrc, A.qbuf, A.qpix, A.qcount, A.out, (int64_t)ne, st)) return rc;
-    TV_HIP(hipEventRecord(e2, st));
-    TV_HIP(hipEventSynchronize(e2));
-    float ms = 0.0f;
-    TV_HIP(hipEventElapsedTime(&ms, t0, t1));
-    *ms_trace += ms;
-    TV_HIP(hipEventElapsedTime(&ms, t1, e2));
-    *ms_cache += ms;
+    if (timed) {
+      TV_HIP(hipEventRecord(e2, st));
+      TV_HIP(hipEventSynchronize(e2));
+      float ms = 0.0f;
+      TV_HIP(hipEventElapsedTime(&ms, t0, t1));
+      *ms_trace += ms;
+      TV_HIP(hipEventElapsedTime(&ms, t1, e2));
+      *ms_cache += ms;
+    }
   }
   if (A.accumulate && NRC != 2)
     hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)((npix * 3 + 255) / 256)), dim3(256), 0, st, A.out, npix * 3,
                        (float)spp);
-  TV_HIP(hipEventRecord(e1, st));
-  TV_HIP(hipEventSynchronize(e1));
-  TV_HIP(hipEventElapsedTime(ms_total, e0, e1));
+  TV_HIP(hipGetLastError());
+  if (timed) {
+    TV_HIP(hipEventRecord(e1, st));
+    TV_HIP(hipEventSynchronize(e1));
+    TV_HIP(hipEventElapsedTime(ms_total, e0, e1));
+  }
   return TET_OK;
 }
 
@@ -1118,7 +1126,10 @@ static void set_scene(RenderArgs& A, const tet_camera* cam, const tet_medium* me
 static int render_common(int kind, const tet_grid* g, const tet_density* dens, const tet_camera* cam,
                          const tet_medium* medm, const tet_light* light, int32_t spp, uint64_t seed,
                          const tet_render_opts* opts_in, float* out_rgb, int32_t on_device, hipStream_t st,
-                         tet_render_stats* stats) {
+                         tet_render_stats* stats, char* fixed = nullptr, size_t fixed_bytes = 0) {
+  // fixed != NULL: the scratch is the caller's fixed device array (no
+  // allocation, no timing, no wait; launches on the stream only)
+  const bool noalloc = fixed != nullptr;
   if (int rc = check_camera(cam)) return rc;
   if (!medm || !light || !out_rgb) return fail(TET_ERR_INVALID_ARG, "render: NULL medium, light or output");
   if (spp < 1) return fail(TET_ERR_INVALID_ARG, "render: spp must be >= 1");
@@ -1149,13 +1160,24 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (model && nrc) return fail(TET_ERR_UNSUPPORTED, "render: density models do not render with a radiance cache");
   if (model && g->model == 2 && o.transmittance == 0)
     return fail(TET_ERR_INVALID_ARG, "render: the voxel-lookup model needs ratio or delta tracking for the light");
-  const uint32_t* shapes = shape_table();
+  if (noalloc && (kind != 0 || nrc || !on_device || stats))
+    return fail(TET_ERR_UNSUPPORTED,
+                "tet_render_noalloc: tet grids only, no radiance cache, output on the device, no stats");
+  // the no-alloc path only takes a shape table that already exists (every
+  // grid's build made the one of its device)
+  const uint32_t* shapes = noalloc ? shape_table_existing() : shape_table();
   if (!shapes) return fail(TET_ERR_DEVICE, "render: shape table");
   int64_t npix = (int64_t)cam->width * cam->height;
   int tiles_x = (cam->width + 7) / 8, tiles_y = (cam->height + 7) / 8;
   int64_t slots = (int64_t)tiles_x * tiles_y * 64;
   if (slots >= (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: image too large");
-  int64_t pass_cap = std::max<int64_t>(1, std::min<int64_t>(spp, kMaxEntriesPerPass / slots));
+  const int64_t entry_cap =
+      noalloc ? std::min<int64_t>(kMaxEntriesPerPass, ((int64_t)fixed_bytes - 256) / (int64_t)sizeof(RayEntry))
+              : kMaxEntriesPerPass;
+  if (noalloc && slots > entry_cap)
+    return fail(TET_ERR_CAPACITY, "tet_render_noalloc: one sample per pixel of this image does not fit the "
+                                  "fixed scratch (" + std::to_string(entry_cap) + " entry records)");
+  int64_t pass_cap = std::max<int64_t>(1, std::min<int64_t>(spp, entry_cap / slots));
   int per_item = (o.samples_per_item <= 0 || o.samples_per_item > pass_cap) ? (int)pass_cap : o.samples_per_item;
   if (slots * ((pass_cap + per_item - 1) / per_item) >= (1ll << 32))
     return fail(TET_ERR_INVALID_ARG, "render: too many work items");
@@ -1207,12 +1229,13 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   size_t vrec_bytes = (size_t)n_train * (size_t)kv * 48, pl_bytes = (size_t)n_train * 16;
   size_t q_bytes = nrc ? (size_t)slots * (size_t)pass_cap * 36 : 0;  // at most one query per sample
   size_t scratch = 256 + ent_bytes + (on_device ? 0 : img_bytes) + vrec_bytes + pl_bytes + q_bytes;
-  char* sc = (char*)dev_alloc(scratch);
+  if (noalloc && scratch > fixed_bytes) return fail(TET_ERR_INTERNAL, "tet_render_noalloc: scratch overrun");
+  char* sc = noalloc ? fixed : (char*)dev_alloc(scratch);
   if (!sc) return fail(TET_ERR_OUT_OF_MEMORY, "render: scratch");
   struct Free {
     void* p;
-    ~Free() { dev_free(p); }
-  } fr_{sc};
+    ~Free() { if (p) dev_free(p); }
+  } fr_{noalloc ? nullptr : sc};
   A.counter = (uint32_t*)sc;
   A.stats = (unsigned long long*)(sc + 64);  // counters: 8 work ranges in sc[0..32), query count at sc[32]
   RayEntry* entries = (RayEntry*)(sc + 256);
@@ -1234,18 +1257,24 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   int rc;
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
     TetMedium32 m{model ? g->mrec32 : g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
-    rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
-             : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
+    rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
+                                          !noalloc)
+             : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
+                                          !noalloc);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
     TetMedium m{model ? g->mrec : g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
-    rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache)
-             : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
+    rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
+                                        !noalloc)
+             : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
+                                        !noalloc);
   } else {
     VoxelMedium m{dens->data, dens->n, dens->density_scale};
-    rc = run_passes<VoxelMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache);
+    rc = run_passes<VoxelMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
+                                    !noalloc);
   }
   if (rc) return rc;
+  if (noalloc) return TET_OK;
   int64_t records = 0;
   double loss = 0.0;
   if (train) {  // the cache's Adam steps on the frame's training paths (timed into ms)
@@ -1353,6 +1382,43 @@ int render_grid(const tet_grid* g, const tet_camera* cam, const tet_medium* m, c
                 tet_render_stats* stats) {
   if (!g) return fail(TET_ERR_INVALID_ARG, "tet_render: grid is NULL");
   return render_common(0, g, nullptr, cam, m, l, spp, seed, o, out, on_device, st, stats);
+}
+
+// ---------------------------------------------------------------- render without allocation
+// The scratch of tet_render_noalloc: a fixed array, one copy per device (made
+// when the library's code is loaded on it, kept until the process ends).  In
+// host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, looked up once per device.
+constexpr size_t kNoAllocBytes = (size_t(64) << 20) + 256;  // counters, then 2^21 entry records
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+
+static char* noalloc_scratch() {
+  static std::mutex mu;
+  static char* ptr[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    ptr[dev] = (char*)p;
+  }
+  return ptr[dev];
+}
+
+int render_grid_noalloc(const tet_grid* g, const tet_camera* cam, const tet_medium* m, const tet_light* l,
+                        int32_t spp, uint64_t seed, const tet_render_opts* o, float* out, hipStream_t st) {
+  if (!g) return fail(TET_ERR_INVALID_ARG, "tet_render_noalloc: grid is NULL");
+  int dev = -1;
+  TV_HIP(hipGetDevice(&dev));
+  if (dev != g->device) return fail(TET_ERR_INVALID_ARG, "tet_render_noalloc: the grid lives on another device");
+  char* sc = noalloc_scratch();
+  if (!sc) return fail(TET_ERR_DEVICE, "tet_render_noalloc: no device address for the fixed scratch");
+  return render_common(0, g, nullptr, cam, m, l, spp, seed, o, out, 1, st, nullptr, sc, kNoAllocBytes);
 }
 
 int render_voxels(const tet_density* dens, const tet_camera* cam, const tet_medium* m, const tet_light* l,
