@@ -11,6 +11,8 @@ cache online on the same grid and compares, at equal RMSE against a
 one training frame each) with the plain renderer's.  The batch leg
 ("batch") renders 64 small scenes (64^2..512^2, 4..64 spp, 3k..5M tets) as
 one captured HIP-graph frame and as 64 tet_render calls one after another.
+The camera-path leg ("camera_path") rebuilds the grid for a moving camera
+with leb_update and times it against scratch builds.
 """
 from __future__ import annotations
 
@@ -308,6 +310,43 @@ def sparse_build_leg(tv, torch, dev, sc, dense_grid) -> dict:
             "build_ms": round(ms[-1], 3), "same_grid_as_dense": same}
 
 
+def camera_path_leg(tv, torch, dev, sc, frames: int = 16) -> dict:
+    """The grid following a moving camera (the paper's real-time use):
+    leb_update from the previous frame's grid against a scratch leb_build,
+    per frame, on two scripted paths of the cloud: the benchmark camera
+    orbiting 2 degrees and dollying 1 % a frame (the whole volume stays in
+    view), and a close-up orbit 3 degrees a frame from 0.75 away, where the
+    frustum clips the volume and the grid changes every frame.  Both grids
+    are compared on the device every frame."""
+    import numpy as np
+    import synthetic
+    out = {}
+    close = dict(sc["camera"], pos=[0.5, 0.47, -0.25], look_at=[0.5, 0.5, 0.5])
+    for name, cams in (("orbit", synthetic.camera_path(sc["camera"], frames + 1, 2.0, 0.01)),
+                       ("close_up_orbit", synthetic.camera_path(close, frames + 1, 3.0, 0.0))):
+        g = tv.leb_build(dev, sc["n"], cams[0], build=sc["build"])
+        upd, scr, stood, same, tets = [], [], 0, True, []
+        for cam in cams[1:]:
+            g.update(dev, sc["n"], cam, build=sc["build"])
+            r = tv.leb_build(dev, sc["n"], cam, build=sc["build"])
+            a, b = g.info(), r.info()
+            upd.append(a["ms"])
+            scr.append(b["ms"])
+            stood += a["rounds"] == 0
+            tets.append(a["num_tets"])
+            ea, eb = g.export(device=True, fields=("ids", "nbr")), r.export(device=True, fields=("ids", "nbr"))
+            same = same and ea["ids"].shape == eb["ids"].shape and bool(torch.equal(ea["ids"], eb["ids"])) and \
+                bool(torch.equal(ea["nbr"], eb["nbr"]))
+            del r, ea, eb
+        del g
+        out[name] = {"frames": frames, "update_ms": round(float(np.mean(upd)), 3),
+                     "scratch_build_ms": round(float(np.mean(scr)), 3),
+                     "speedup": round(float(np.mean(scr)) / float(np.mean(upd)), 3),
+                     "frames_tree_stood": int(stood), "tets_min_max": [int(min(tets)), int(max(tets))],
+                     "same_grid_as_scratch_every_frame": same}
+    return out
+
+
 def regular_grid_1024_leg(tv, torch, dev, sc, steps: int = 2) -> dict:
     """The paper's comparison at its resolution: the cloud resampled to a
     1024^3 regular grid (trilinear, on the device), the adaptive tet grid
@@ -573,6 +612,7 @@ def main():
                     help="also render the cloud resampled to 1024^3 with both renderers (the paper's "
                          "comparison at its resolution)")
     ap.add_argument("--no-channels", action="store_true", help="skip the extra-channel leg")
+    ap.add_argument("--no-camera-path", action="store_true", help="skip the moving-camera (leb_update) leg")
     ap.add_argument("--no-density-models", action="store_true", help="skip the density-model leg")
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 1024^3 plume leg (the radiance-cache leg then runs on the cloud)")
@@ -699,6 +739,8 @@ def main():
     res["host_buffers"] = host_io_leg(tv, torch, d, sc)
     if args.regular_grid_1024:
         res["regular_grid_1024"] = regular_grid_1024_leg(tv, torch, dev, sc)
+    if not args.no_camera_path:
+        res["camera_path"] = camera_path_leg(tv, torch, dev, sc)
     if not args.no_batch:
         res["batch"] = batch_leg(tv, torch, 64)
     if grid is None:

@@ -178,6 +178,26 @@ typedef struct {
 int leb_build_sparse(const tet_sparse_density* density, const tet_camera* camera, float target_cell_px,
                      const tet_build_opts* opts, void* hip_stream, tet_grid** out);
 
+/* Rebuilds `grid` in place for a new camera (or density, target or
+ * options), starting from the grid's current tree instead of the 6 roots:
+ * the real-time use of the paper ("Results": pre-visualisation at
+ * interactive rates and animated sequences, where the grid follows the
+ * camera, which the camera criterion of "Subdivision Criteria" makes it
+ * depend on).  The result is identical, bit for bit, to leb_build (resp.
+ * leb_build_sparse) with the same arguments.  Every node of the current
+ * tree that the new criteria want, as they want all its ancestors, is
+ * split by that build too, so its rounds are continued from those nodes:
+ * tets the new criteria no longer want merge back into their first
+ * unwanted ancestor, tets they want split further, and the rounds restore
+ * conformity.  Arguments and errors as leb_build; on error the grid is
+ * unchanged.  Extra channels and density models set on the grid are
+ * dropped (they are per tet: set them again).  The grid must live on the
+ * current device. */
+int leb_update(tet_grid* grid, const tet_density* density, const tet_camera* camera, float target_cell_px,
+               const tet_build_opts* opts, void* hip_stream);
+int leb_update_sparse(tet_grid* grid, const tet_sparse_density* density, const tet_camera* camera,
+                      float target_cell_px, const tet_build_opts* opts, void* hip_stream);
+
 int tet_grid_info(const tet_grid* grid, int64_t* num_tets, int32_t* max_depth, tet_build_stats* stats);
 
 /* Copies grid arrays out (any pointer may be NULL): ids[num_tets] heap ids;

@@ -64,6 +64,38 @@ class Grid:
     def num_tets(self) -> int:
         return self.info()["num_tets"]
 
+    def update(self, density, n: int, camera: dict, target_cell_px: float = 1.0, build: dict | None = None,
+               density_scale: float | None = None) -> "Grid":
+        """leb_update: rebuilds this grid in place for a new camera (same
+        result as leb_build with these arguments), seeded from its current
+        tree.  Returns self."""
+        b = dict(build or {})
+        scale = b.pop("density_scale", 1.0) if density_scale is None else density_scale
+        target = b.pop("target_px", target_cell_px)
+        b.pop("shuffle_seed", None)
+        ds = density_struct(density, n, scale)
+        cam = _abi.make_camera(camera)
+        opts = _abi.make_build_opts(b)
+        check(lib().leb_update(self._h, ctypes.byref(ds), ctypes.byref(cam), float(target), ctypes.byref(opts),
+                               _stream()), "leb_update")
+        self.__dict__.pop("_model", None)
+        return self
+
+    def update_sparse(self, coords, values, n: int, camera: dict, target_cell_px: float = 1.0,
+                      build: dict | None = None, density_scale: float | None = None) -> "Grid":
+        """leb_update_sparse: the same from 8^3 bricks (see leb_build_sparse)."""
+        b = dict(build or {})
+        scale = b.pop("density_scale", 1.0) if density_scale is None else density_scale
+        target = b.pop("target_px", target_cell_px)
+        b.pop("shuffle_seed", None)
+        sd, _keep = _sparse_struct(coords, values, n, scale)
+        cam = _abi.make_camera(camera)
+        opts = _abi.make_build_opts(b)
+        check(lib().leb_update_sparse(self._h, ctypes.byref(sd), ctypes.byref(cam), float(target),
+                                      ctypes.byref(opts), _stream()), "leb_update_sparse")
+        self.__dict__.pop("_model", None)
+        return self
+
     def export(self, device: bool = False, fields=("ids", "nbr", "sigma", "majorant", "verts")) -> dict:
         """Copies of ids, neighbour links, extinction, majorant, vertices:
         numpy arrays, or CUDA tensors with device=True (ids and links as
@@ -179,15 +211,8 @@ def leb_build(density, n: int, camera: dict, target_cell_px: float = 1.0, build:
     return Grid(h)
 
 
-def leb_build_sparse(coords, values, n: int, camera: dict, target_cell_px: float = 1.0, build: dict | None = None,
-                     density_scale: float | None = None) -> Grid:
-    """The same build from a sparse volume: `coords` (B, 3) int32 brick
-    positions (voxel / 8) and `values` (B, 512) float32 voxels of each 8^3
-    brick, x fastest; both numpy arrays or both CUDA tensors."""
-    b = dict(build or {})
-    scale = b.pop("density_scale", 1.0) if density_scale is None else density_scale
-    target = b.pop("target_px", target_cell_px)
-    b.pop("shuffle_seed", None)
+def _sparse_struct(coords, values, n: int, scale: float):
+    """(tet_sparse_density, the contiguous arrays it points into)."""
     if isinstance(coords, np.ndarray):
         coords = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
         values = np.ascontiguousarray(values, np.float32).reshape(-1, 512)
@@ -198,7 +223,19 @@ def leb_build_sparse(coords, values, n: int, camera: dict, target_cell_px: float
     pc, dev_c = _ptr(coords)
     pv, dev_v = _ptr(values)
     assert dev_c == dev_v
-    sd = _abi.TetSparseDensity(pc, pv, int(coords.shape[0]), int(n), dev_c, float(scale))
+    return _abi.TetSparseDensity(pc, pv, int(coords.shape[0]), int(n), dev_c, float(scale)), (coords, values)
+
+
+def leb_build_sparse(coords, values, n: int, camera: dict, target_cell_px: float = 1.0, build: dict | None = None,
+                     density_scale: float | None = None) -> Grid:
+    """The same build from a sparse volume: `coords` (B, 3) int32 brick
+    positions (voxel / 8) and `values` (B, 512) float32 voxels of each 8^3
+    brick, x fastest; both numpy arrays or both CUDA tensors."""
+    b = dict(build or {})
+    scale = b.pop("density_scale", 1.0) if density_scale is None else density_scale
+    target = b.pop("target_px", target_cell_px)
+    b.pop("shuffle_seed", None)
+    sd, _keep = _sparse_struct(coords, values, n, scale)
     cam = _abi.make_camera(camera)
     opts = _abi.make_build_opts(b)
     h = ctypes.c_void_p()

@@ -117,6 +117,10 @@ SIGNATURES = {
                                  ctypes.POINTER(TetBuildOpts), VP, ctypes.POINTER(VP)]),
     "leb_build_sparse": (ctypes.c_int, [ctypes.POINTER(TetSparseDensity), ctypes.POINTER(TetCamera), ctypes.c_float,
                                         ctypes.POINTER(TetBuildOpts), VP, ctypes.POINTER(VP)]),
+    "leb_update": (ctypes.c_int, [VP, ctypes.POINTER(TetDensity), ctypes.POINTER(TetCamera), ctypes.c_float,
+                                  ctypes.POINTER(TetBuildOpts), VP]),
+    "leb_update_sparse": (ctypes.c_int, [VP, ctypes.POINTER(TetSparseDensity), ctypes.POINTER(TetCamera),
+                                         ctypes.c_float, ctypes.POINTER(TetBuildOpts), VP]),
     "tet_grid_info": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(TetBuildStats)]),
     "tet_grid_export": (ctypes.c_int, [VP, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),

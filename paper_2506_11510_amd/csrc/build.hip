@@ -274,10 +274,6 @@ __device__ inline void block_count(bool x, uint32_t* slots) {
   if (threadIdx.x == 0 && s_n) atomicAdd(&slots[blockIdx.x % kCountSlots], s_n);
 }
 
-__device__ inline void vset_insert(uint64_t* tab, uint64_t mask, uint64_t key, uint32_t* count) {
-  if (vset_add(tab, mask, key)) atomicAdd(count, 1u);
-}
-
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -290,10 +286,12 @@ __global__ void k_vset_rehash(const uint64_t* __restrict__ old, int64_t ocap, ui
   block_count(added, count);
 }
 
+// The vertices of n leaves (their 4 n packed vertices, with repeats).
 __global__ void k_vset_seed(const uint64_t* __restrict__ verts, int64_t n, uint64_t* tab, uint64_t mask,
                             uint32_t* count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 4 * n) vset_insert(tab, mask, verts[i], count);
+  const bool added = i < 4 * n && vset_add(tab, mask, verts[i]);
+  block_count(added, count);
 }
 
 // ---------------------------------------------------------------- rounds
@@ -619,28 +617,40 @@ __device__ inline uint64_t children(uint64_t id, const uint64_t v[4], uint64_t a
   return z;
 }
 
+// Want bits of a leaf's ancestor chain (bit d: the ancestor at depth d was
+// split because the want predicate held, not only to keep the grid
+// conforming).  A split leaf passes its chain on with its own bit: flag bit 0
+// set means its predicate was false, so a conformity split.
+__device__ inline uint64_t child_chain(uint64_t chain, uint8_t flag, uint64_t id) {
+  return chain | ((flag & 1) ? 0ull : (1ull << id_depth(id)));
+}
+
 // Copies leaf i to position o, or writes its two children there and adds
 // the new vertex to the vertex set (and to the new-vertex set when given);
 // true when the vertex is new.
 __device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_t* ids, const uint64_t* verts,
-                                 const uint8_t* flags, uint64_t* nids, uint64_t* nverts, uint8_t* nflags,
-                                 uint64_t* vset, uint64_t vmask, uint64_t* nset, uint64_t nmask, uint32_t* cells,
-                                 uint32_t* work) {
+                                 const uint8_t* flags, const uint64_t* chain, uint64_t* nids, uint64_t* nverts,
+                                 uint8_t* nflags, uint64_t* nchain, uint64_t* vset, uint64_t vmask, uint64_t* nset,
+                                 uint64_t nmask, uint32_t* cells, uint32_t* work) {
   uint64_t id = ids[i];
   uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]};
   if (!split) {
     nids[o] = id;
     nflags[o] = flags[i];
+    nchain[o] = chain[i];
 #pragma unroll
     for (int j = 0; j < 4; j++) nverts[4 * o + j] = v[j];
     return false;
   }
   uint64_t a[4], b[4];
   const uint64_t z = children(id, v, a, b);
+  const uint64_t ch = child_chain(chain[i], flags[i], id);
   nids[o] = 2 * id;
   nids[o + 1] = 2 * id + 1;
   nflags[o] = 0;
   nflags[o + 1] = 0;
+  nchain[o] = ch;
+  nchain[o + 1] = ch;
   const int64_t r = o - i;  // splits before this leaf
   work[2 * r] = (uint32_t)o;
   work[2 * r + 1] = (uint32_t)(o + 1);
@@ -658,15 +668,16 @@ __device__ inline bool split_one(int64_t i, int64_t o, bool split, const uint64_
 }
 
 __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ verts,
-                        const uint8_t* __restrict__ flags, const uint32_t* __restrict__ cnt,
-                        const uint32_t* __restrict__ offs, uint64_t* __restrict__ nids, uint64_t* __restrict__ nverts,
-                        uint8_t* __restrict__ nflags, uint64_t* vset, uint64_t vmask, uint32_t* vcount,
+                        const uint8_t* __restrict__ flags, const uint64_t* __restrict__ chain,
+                        const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ offs,
+                        uint64_t* __restrict__ nids, uint64_t* __restrict__ nverts, uint8_t* __restrict__ nflags,
+                        uint64_t* __restrict__ nchain, uint64_t* vset, uint64_t vmask, uint32_t* vcount,
                         uint64_t* nset, uint64_t nmask, uint32_t* cells, uint32_t* __restrict__ work) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool added = false;
   if (i < n)
-    added = split_one(i, offs[i], cnt[i] != 1u, ids, verts, flags, nids, nverts, nflags, vset, vmask, nset, nmask,
-                      cells, work);
+    added = split_one(i, offs[i], cnt[i] != 1u, ids, verts, flags, chain, nids, nverts, nflags, nchain, vset, vmask,
+                      nset, nmask, cells, work);
   block_count(added, vcount);
 }
 
@@ -678,7 +689,8 @@ __global__ void k_split(int64_t n, const uint64_t* __restrict__ ids, const uint6
 // particular order, so neither are the appended leaves until k_merge.
 __global__ void k_split_append(int64_t count, const uint32_t* __restrict__ slist, int64_t n, int64_t nmain,
                                uint64_t* __restrict__ ids, uint64_t* __restrict__ verts,
-                               uint8_t* __restrict__ flags, uint32_t* __restrict__ anc, uint64_t* vset,
+                               uint8_t* __restrict__ flags, uint64_t* __restrict__ chain,
+                               uint32_t* __restrict__ anc, uint64_t* vset,
                                uint64_t vmask, uint32_t* vcount, uint64_t* nset, uint64_t nmask, uint32_t* cells,
                                uint32_t* __restrict__ work) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -688,10 +700,13 @@ __global__ void k_split_append(int64_t count, const uint32_t* __restrict__ slist
     const uint64_t id = ids[i];
     uint64_t v[4] = {verts[4 * i], verts[4 * i + 1], verts[4 * i + 2], verts[4 * i + 3]}, a[4], b[4];
     const uint64_t z = children(id, v, a, b);
+    const uint64_t ch = child_chain(chain[i], flags[i], id);
     ids[i] = 2 * id;
     ids[o] = 2 * id + 1;
     flags[i] = 0;
     flags[o] = 0;
+    chain[i] = ch;
+    chain[o] = ch;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       verts[4 * i + j] = a[j];
@@ -738,9 +753,10 @@ __device__ inline uint64_t dfs_key(uint64_t id) { return id << (60 - id_depth(id
 // appended descendants ranked by key (they are leaves of one subtree, so
 // their keys are distinct).
 __global__ void k_merge(int64_t nmain, int64_t m, int64_t total, const uint64_t* __restrict__ ids,
-                        const uint64_t* __restrict__ verts, const uint32_t* __restrict__ anc,
-                        const uint32_t* __restrict__ pos, const uint32_t* __restrict__ slots,
-                        uint64_t* __restrict__ out_ids, uint64_t* __restrict__ out_verts) {
+                        const uint64_t* __restrict__ verts, const uint64_t* __restrict__ chain,
+                        const uint32_t* __restrict__ anc, const uint32_t* __restrict__ pos,
+                        const uint32_t* __restrict__ slots, uint64_t* __restrict__ out_ids,
+                        uint64_t* __restrict__ out_verts, uint64_t* __restrict__ out_chain) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nmain + m) return;
   int64_t o;
@@ -756,6 +772,7 @@ __global__ void k_merge(int64_t nmain, int64_t m, int64_t total, const uint64_t*
     o = first + r;
   }
   out_ids[o] = ids[t];
+  out_chain[o] = chain[t];
 #pragma unroll
   for (int q = 0; q < 4; q++) out_verts[4 * o + q] = verts[4 * t + q];
 }
@@ -828,6 +845,288 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const u
   }
 }
 
+// ---------------------------------------------------------------- seed from a previous grid
+// A previous grid's tree seeds the rounds of a new build.  A node of that
+// tree that satisfies the (new) want predicate, as all its ancestors do, is
+// split in the new grid as well: the rounds from the roots split every
+// wanted leaf, so such a node becomes a leaf at some round and is then split.
+// The seed -- the previous tree cut at the first node of each branch that is
+// not wanted, or at the previous leaf -- is therefore a stage that the rounds
+// from the roots pass through, and the rounds continued from it end at the
+// same grid, which does not depend on the order of the splits.  Leaves the
+// new criteria no longer want are merged away by not being seeded; the
+// splits that conformity forced are found again by the rounds.
+//
+// Node a of the previous tree is owned by the first leaf of its subtree in
+// depth-first order: leaf p owns itself and its ancestors below its deepest
+// common ancestor with leaf p - 1.  Each leaf evaluates the predicate of the
+// nodes it owns (bit d for the node at depth d), and an inclusive scan of
+// M_p = (M_{p-1} & keep_p) | bits_p gives each leaf the bits of its whole
+// ancestor chain and itself (keep_p: the depths it does not own).
+//
+// The previous grid keeps the same bits from its own build (its chain: the
+// predicate of every ancestor; a leaf's own predicate was false).  When the
+// new bits equal them for every leaf, the predicate takes the same value on
+// every node of the previous tree, so a build from the roots under the new
+// criteria makes exactly the same splits: the grid stands as it is.
+
+// Lattice vertices of root r (the Kuhn tet of axis order (a, b, the third)).
+__device__ inline void root_vertices(int r, uint64_t v[4]) {
+  const int a = r >> 1;
+  const int b = a == 0 ? ((r & 1) ? 2 : 1) : (a == 1 ? ((r & 1) ? 2 : 0) : ((r & 1) ? 1 : 0));
+  int32_t c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+  c1[a] = kLatS;
+  c2[a] = kLatS;
+  c2[b] = kLatS;
+  v[0] = pack_vertex(0, 0, 0);
+  v[1] = pack_vertex(c1[0], c1[1], c1[2]);
+  v[2] = pack_vertex(c2[0], c2[1], c2[2]);
+  v[3] = pack_vertex(kLatS, kLatS, kLatS);
+}
+
+// Vertices of the depth-d ancestor of the tet with heap id h (depth D >= d),
+// by bisecting down from its root.
+__device__ inline void ancestor_vertices(uint64_t h, int D, int d, uint64_t v[4]) {
+  root_vertices((int)(h >> D) - 8, v);
+  for (int e = 0; e < d; e++) {
+    uint64_t c0[4], c1[4];
+    children(h >> (D - e), v, c0, c1);
+    const bool right = (h >> (D - e - 1)) & 1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = right ? c1[j] : c0[j];
+  }
+}
+
+// Depth of the deepest common ancestor of two distinct leaves (-1: roots differ).
+__device__ inline int common_depth(uint64_t a, uint64_t b) {
+  const int da = id_depth(a), db = id_depth(b), m = min(da, db);
+  const uint64_t x = (a >> (da - m)) ^ (b >> (db - m));
+  if (!x) return m;
+  return max(m - (64 - (int)__builtin_clzll(x)), -1);
+}
+
+__global__ void k_seed_chain(int64_t n, const uint64_t* __restrict__ ids, Pyramid P, CamCrit cc, WantParams wp,
+                             uint64_t* __restrict__ keep, uint64_t* __restrict__ bits) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint64_t h = ids[p];
+  const int D = id_depth(h);
+  const int c = p ? common_depth(ids[p - 1], h) : -1;
+  uint64_t v[4];
+  root_vertices((int)(h >> D) - 8, v);
+  uint64_t b = 0;
+  for (int d = 0; d <= D; d++) {
+    const uint64_t a = h >> (D - d);
+    if (d > c && want(P, cc, wp, v, a)) b |= 1ull << d;
+    if (d == D) break;
+    uint64_t c0[4], c1[4];
+    children(a, v, c0, c1);
+    const bool right = (h >> (D - d - 1)) & 1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = right ? c1[j] : c0[j];
+  }
+  keep[p] = c >= 0 ? (~0ull >> (63 - c)) : 0ull;
+  bits[p] = b;
+}
+
+// Transform M -> (M & k) | b of the chain scan; compose(x, y) applies x, then y.
+struct ChainT {
+  uint64_t k, b;
+};
+__device__ inline ChainT chain_compose(ChainT x, ChainT y) { return {x.k & y.k, (x.b & y.k) | y.b}; }
+
+// Exclusive scan of one transform per thread over the block (kScanThreads);
+// *total receives the block's whole composition.
+__device__ inline ChainT block_chain_exclusive(ChainT x, ChainT* ws, ChainT* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  ChainT inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const ChainT y = {__shfl_up(inc.k, o, 64), __shfl_up(inc.b, o, 64)};
+    if (lane >= o) inc = chain_compose(y, inc);
+  }
+  ChainT ex = {__shfl_up(inc.k, 1, 64), __shfl_up(inc.b, 1, 64)};
+  if (lane == 0) ex = {~0ull, 0ull};
+  if (lane == 63) ws[wid] = inc;
+  __syncthreads();
+  ChainT pre = {~0ull, 0ull}, tot = {~0ull, 0ull};
+  for (int w = 0; w < kScanThreads / 64; w++) {
+    if (w < wid) pre = chain_compose(pre, ws[w]);
+    tot = chain_compose(tot, ws[w]);
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return chain_compose(pre, ex);
+}
+
+__device__ inline ChainT chain_items(const uint64_t* keep, const uint64_t* bits, int64_t base, int64_t n) {
+  ChainT t = {~0ull, 0ull};
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++)
+    if (base + q < n) t = chain_compose(t, ChainT{keep[base + q], bits[base + q]});
+  return t;
+}
+
+__global__ void k_chain_reduce(const uint64_t* __restrict__ keep, const uint64_t* __restrict__ bits, int64_t n,
+                               ChainT* __restrict__ bagg) {
+  __shared__ ChainT ws[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  ChainT tot;
+  block_chain_exclusive(chain_items(keep, bits, base, n), ws, &tot);
+  if (threadIdx.x == 0) bagg[blockIdx.x] = tot;
+}
+
+// One block: the chain bits entering each block, in place of its aggregate.
+__global__ void k_chain_blocks(ChainT* bagg, int64_t nb) {
+  __shared__ ChainT ws[kScanThreads / 64];
+  ChainT carry = {~0ull, 0ull};
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const ChainT x = i < nb ? bagg[i] : ChainT{~0ull, 0ull};
+    ChainT tot;
+    const ChainT ex = block_chain_exclusive(x, ws, &tot);
+    if (i < nb) bagg[i] = ChainT{0ull, chain_compose(carry, ex).b};  // applied to M = 0 before the first leaf
+    carry = chain_compose(carry, tot);
+  }
+}
+
+// M of every leaf, written over bits.
+__global__ void k_chain_apply(const uint64_t* __restrict__ keep, uint64_t* __restrict__ bits, int64_t n,
+                              const ChainT* __restrict__ bagg) {
+  __shared__ ChainT ws[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint64_t k[kScanItems], b[kScanItems];
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++) {
+    k[q] = base + q < n ? keep[base + q] : ~0ull;
+    b[q] = base + q < n ? bits[base + q] : 0ull;
+  }
+  ChainT t = {~0ull, 0ull};
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++) t = chain_compose(t, ChainT{k[q], b[q]});
+  const ChainT ex = block_chain_exclusive(t, ws, nullptr);
+  uint64_t m = (bagg[blockIdx.x].b & ex.k) | ex.b;
+#pragma unroll
+  for (int q = 0; q < kScanItems; q++) {
+    m = (m & k[q]) | b[q];
+    if (base + q < n) bits[base + q] = m;
+  }
+}
+
+// Seed node of leaf h with chain bits m: its ancestor at the first depth
+// whose node is not wanted, or h itself; *wanted when the whole chain,
+// h included, is wanted.
+__device__ inline uint64_t seed_node(uint64_t h, uint64_t m, int* depth, bool* wanted) {
+  const int D = id_depth(h);
+  const int f = (int)__builtin_ctzll(~m);  // m has no bit above depth 56
+  *wanted = f > D;
+  *depth = min(f, D);
+  return h >> (D - *depth);
+}
+
+__global__ void k_seed_first(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ chain,
+                             uint32_t* __restrict__ first) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int d;
+  bool w;
+  const uint64_t s = seed_node(ids[p], chain[p], &d, &w);
+  first[p] = (p == 0 || seed_node(ids[p - 1], chain[p - 1], &d, &w) != s) ? 1u : 0u;
+}
+
+// Extinction and majorant of every tet of a grid whose tree stays, for the
+// volume and scale of a new build (k_records' rule; the rest of the records
+// depends on the tree alone).
+__global__ void k_refresh_medium(int64_t n, const uint64_t* __restrict__ verts, Pyramid P, float scale,
+                                 int majorant_mode, TetRec* __restrict__ rec, TetRec32* __restrict__ rec32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint64_t pv[4] = {verts[4 * t], verts[4 * t + 1], verts[4 * t + 2], verts[4 * t + 3]};
+  int32_t lo[3], hi[3];
+  tet_box(pv, lo, hi);
+  float mn, mx;
+  double sm, c;
+  box_stats(P, lo, hi, mn, mx, sm, c);
+  const float sigma = (float)((double)scale * (sm / c));
+  const float majorant = majorant_mode == 1 ? (float)((double)scale * (double)mx) : sigma;
+  rec[t].sigma = sigma;
+  rec[t].majorant = majorant;
+  if (rec32) rec32[t].w[3] = __float_as_uint(sigma);
+}
+
+// Leaves whose chain bits differ from the previous grid's (one atomic per wave).
+__global__ void k_chain_diff(int64_t n, const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                             uint32_t* count) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool d = p < n && a[p] != b[p];
+  count_new(d, count);
+}
+
+// Adds x over the block to slots[blockIdx.x % kCountSlots] (every thread of
+// the block calls it, in uniform control flow).
+__device__ inline void block_add(uint32_t x, uint32_t* slots) {
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  if (x) atomicAdd(&s_n, x);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_n) atomicAdd(&slots[blockIdx.x % kCountSlots], s_n);
+}
+
+// The seed's leaves in depth-first order, with their chains and the flags of
+// the rounds (0: wanted, listed for k_want; 1: not wanted, checked by k_mark
+// against the whole vertex set).  The seed's vertices are the cube's corners
+// and the midpoints of its split nodes; the first leaf of each seed node's
+// run owns the split nodes above it that the previous tree's ownership gives
+// it (depths c < d < m), and adds their midpoints to the vertex set.
+__global__ void k_seed_write(int64_t n, const uint64_t* __restrict__ ids, const uint64_t* __restrict__ chain,
+                             const uint32_t* __restrict__ first, const uint32_t* __restrict__ pos,
+                             uint64_t* __restrict__ sids, uint64_t* __restrict__ sverts, uint8_t* __restrict__ sflags,
+                             uint64_t* __restrict__ schain, uint32_t* __restrict__ work, uint32_t* count,
+                             uint64_t* vset, uint64_t vmask, uint32_t* vcount) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool listed = false;
+  uint32_t o = 0, added = 0;
+  if (p == 0) {  // the corners
+    for (int q = 0; q < 8; q++)
+      added += vset_add(vset, vmask, pack_vertex((q & 1) ? kLatS : 0, (q & 2) ? kLatS : 0, (q & 4) ? kLatS : 0));
+  }
+  if (p < n && first[p]) {
+    const uint64_t h = ids[p];
+    const int D = id_depth(h);
+    const int c = p ? common_depth(ids[p - 1], h) : -1;
+    int m;
+    bool w;
+    const uint64_t sd = seed_node(h, chain[p], &m, &w);
+    uint64_t v[4];
+    root_vertices((int)(h >> D) - 8, v);
+    for (int d = 0; d < m; d++) {
+      uint64_t c0[4], c1[4];
+      const uint64_t z = children(h >> (D - d), v, c0, c1);
+      if (d > c) added += vset_add(vset, vmask, z);
+      const bool right = (h >> (D - d - 1)) & 1;
+#pragma unroll
+      for (int j = 0; j < 4; j++) v[j] = right ? c1[j] : c0[j];
+    }
+    o = pos[p];
+    sids[o] = sd;
+#pragma unroll
+    for (int j = 0; j < 4; j++) sverts[4 * (size_t)o + j] = v[j];
+    sflags[o] = w ? 0 : 1;
+    schain[o] = m ? (~0ull >> (64 - m)) : 0ull;  // every ancestor of a seed node is wanted
+    listed = w;
+  }
+  block_add(added, vcount);
+  const unsigned long long mk = __ballot(listed);
+  if (mk) {
+    const int lane = __lane_id(), leader = (int)__builtin_ctzll(mk);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mk));
+    base = __shfl(base, leader, 64);
+    if (listed) work[base + (uint32_t)__popcll(mk & (lane ? (~0ull >> (64 - lane)) : 0ull))] = o;
+  }
+}
+
 // ---------------------------------------------------------------- small grids
 // While the grid is small a round holds too little work to hide the cost of
 // its launches and of the host reading the leaf count back, so the first
@@ -846,6 +1145,7 @@ struct SmallRounds {
   uint64_t* ids[2];
   uint64_t* verts[2];
   uint8_t* flags[2];
+  uint64_t* chain[2];
   uint32_t* cnt;    // per leaf: 1 or 2
   uint32_t* bsum;   // per block: sum of cnt over its chunk
   uint32_t* work;   // new leaves of the last split
@@ -945,8 +1245,9 @@ __global__ __launch_bounds__(256) void k_small_rounds(SmallRounds S, Pyramid P, 
       const uint32_t ex = block_exclusive(x, ws, &t);
       bool added = false;
       if (i < hi)
-        added = split_one(i, (int64_t)carry + ex, x != 1u, ids, verts, flags, S.ids[src ^ 1], S.verts[src ^ 1],
-                          S.flags[src ^ 1], S.vset, S.vmask, nullptr, 0, nullptr, S.work);
+        added = split_one(i, (int64_t)carry + ex, x != 1u, ids, verts, flags, S.chain[src], S.ids[src ^ 1],
+                          S.verts[src ^ 1], S.flags[src ^ 1], S.chain[src ^ 1], S.vset, S.vmask, nullptr, 0,
+                          nullptr, S.work);
       block_count(added, S.vcount);
       carry += t;
     }
@@ -1479,18 +1780,19 @@ struct Buf {
 };
 
 struct Leaves {
-  Buf ids, verts, flags;
+  Buf ids, verts, flags, chain;
   int64_t cap = 0;
   void swap_with(Leaves& o) {
     ids.swap_with(o.ids);
     verts.swap_with(o.verts);
     flags.swap_with(o.flags);
+    chain.swap_with(o.chain);
     std::swap(cap, o.cap);
   }
   bool ensure(int64_t n) {
     if (n <= cap) return true;
     int64_t c = std::max<int64_t>(n, cap + cap / 2);
-    if (!ids.ensure(c * 8) || !verts.ensure(c * 32) || !flags.ensure(c)) return false;
+    if (!ids.ensure(c * 8) || !verts.ensure(c * 32) || !flags.ensure(c) || !chain.ensure(c * 8)) return false;
     cap = c;
     return true;
   }
@@ -1503,6 +1805,7 @@ struct Leaves {
     if (keep > 0 && (hipMemcpyAsync(t.ids.p, ids.p, keep * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
                      hipMemcpyAsync(t.verts.p, verts.p, keep * 32, hipMemcpyDeviceToDevice, st) != hipSuccess ||
                      hipMemcpyAsync(t.flags.p, flags.p, keep, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                     hipMemcpyAsync(t.chain.p, chain.p, keep * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
                      hipStreamSynchronize(st) != hipSuccess))
       return false;
     swap_with(t);
@@ -1705,8 +2008,74 @@ static int64_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, Buf& bsum,
 
 // The build from a dense volume (dens) or a sparse one (sp): they differ
 // only in how the pyramid is made.
+// The seed of a build from a previous grid (see k_seed_chain): its leaves in
+// A (depth-first order), the wanted ones listed in wk, its vertices in a new
+// vertex set vs of *vcap keys.  *cur and *nwork receive the counts;
+// *unchanged is set (and nothing else done) when the previous grid is
+// already the result.
+static int seed_from_grid(const tet_grid* prev, const Pyramid& P, const CamCrit& cc, const WantParams& wp,
+                          Leaves& A, Buf& wk, Buf& vs, uint64_t* vcap, Buf& bsum, uint32_t* d_total,
+                          uint32_t* d_count, uint32_t* d_vcount, uint32_t* hbuf, hipStream_t st, int64_t* cur,
+                          int64_t* nwork, bool allow_same, bool* unchanged) {
+  const int64_t n = prev->n;
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  *unchanged = false;
+  Buf keep, bits, first, pos, bagg;
+  if (!keep.ensure(n * 8) || !bits.ensure(n * 8) || !first.ensure(n * 4) || !pos.ensure(n * 4) ||
+      !bagg.ensure(nb * sizeof(ChainT)))
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_update: seed");
+  hipLaunchKernelGGL(k_seed_chain, dim3(nblocks(n, 256)), dim3(256), 0, st, n, (const uint64_t*)prev->ids, P, cc, wp,
+                     keep.as<uint64_t>(), bits.as<uint64_t>());
+  hipLaunchKernelGGL(k_chain_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, keep.as<uint64_t>(),
+                     bits.as<uint64_t>(), n, bagg.as<ChainT>());
+  hipLaunchKernelGGL(k_chain_blocks, dim3(1), dim3(kScanThreads), 0, st, bagg.as<ChainT>(), nb);
+  hipLaunchKernelGGL(k_chain_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, keep.as<uint64_t>(),
+                     bits.as<uint64_t>(), n, bagg.as<ChainT>());
+  if (allow_same) {
+    TV_HIP(hipMemsetAsync(d_count, 0, 4, st));
+    hipLaunchKernelGGL(k_chain_diff, dim3(nblocks(n, 256)), dim3(256), 0, st, n,
+                       (const uint64_t*)bits.as<uint64_t>(), (const uint64_t*)prev->chain, d_count);
+    TV_HIP(hipMemcpyAsync(hbuf, d_count, 4, hipMemcpyDeviceToHost, st));
+    TV_HIP(hipStreamSynchronize(st));
+    if (hbuf[0] == 0) {
+      *unchanged = true;
+      return TET_OK;
+    }
+  }
+  hipLaunchKernelGGL(k_seed_first, dim3(nblocks(n, 256)), dim3(256), 0, st, n, (const uint64_t*)prev->ids,
+                     bits.as<uint64_t>(), first.as<uint32_t>());
+  if (scan_u32(first.as<uint32_t>(), n, pos.as<uint32_t>(), bsum, d_total, st))
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_update: seed scan");
+  TV_HIP(hipMemcpyAsync(hbuf, d_total, 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  const int64_t m = hbuf[0];
+  if (m < 6 || m > n) return fail(TET_ERR_INTERNAL, "leb_update: bad seed size");
+  if (!A.ensure(std::max<int64_t>(m, 1 << 16)) || !wk.ensure((size_t)m * 4))
+    return fail(TET_ERR_OUT_OF_MEMORY, "leb_update: seed leaves");
+  // a seed holds the 8 corners and at most one vertex per split node (m - 6
+  // of them); the set stays at most half full
+  uint64_t cap = 1 << 16;
+  while (cap < 2 * (uint64_t)(m + 2)) cap <<= 2;
+  if (!vs.ensure(cap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_update: vertex set");
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(cap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)cap,
+                     kEmptyKey);
+  TV_HIP(hipMemsetAsync(d_count, 0, 4, st));
+  hipLaunchKernelGGL(k_seed_write, dim3(nblocks(n, 256)), dim3(256), 0, st, n, (const uint64_t*)prev->ids,
+                     bits.as<uint64_t>(), first.as<uint32_t>(), pos.as<uint32_t>(), A.ids.as<uint64_t>(),
+                     A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), A.chain.as<uint64_t>(), wk.as<uint32_t>(), d_count,
+                     vs.as<uint64_t>(), cap - 1, d_vcount);
+  TV_HIP(hipGetLastError());
+  TV_HIP(hipMemcpyAsync(hbuf, d_count, 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));  // before the scratch returns to the pool
+  *cur = m;
+  *nwork = hbuf[0];
+  *vcap = cap;
+  return TET_OK;
+}
+
 static int build_common(const tet_density* dens, const tet_sparse_density* sp, const tet_camera* cam, float target_px,
-                        const tet_build_opts* opts_in, hipStream_t st, tet_grid** out) {
+                        const tet_build_opts* opts_in, hipStream_t st, tet_grid** out,
+                        tet_grid* prev = nullptr, float* unchanged_ms = nullptr) {
   if (!out) return fail(TET_ERR_INVALID_ARG, "leb_build: out is NULL");
   *out = nullptr;
   const int32_t n = sp ? sp->n : dens->n;
@@ -1793,16 +2162,45 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
   TV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   TV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_small_rounds), 256, 0));
   const int64_t small_cap = std::min<int64_t>(kSmallCap, o.max_tets);
-  const bool small = coop && occ > 0 && ncu > 0 && small_cap >= 12;
+  const bool small = !prev && coop && occ > 0 && ncu > 0 && small_cap >= 12;
   // half the CUs: the rounds are small, and every block adds an arrival to
   // each grid barrier (128 blocks measured best on 256 CUs)
   const int small_blocks = std::max(1, ncu / 2);
 
-  // roots
+  uint32_t* hbuf = nullptr;
+  TV_HIP(hipHostMalloc((void**)&hbuf, 128, hipHostMallocDefault));
+  struct HostFree {
+    uint32_t* p;
+    ~HostFree() { if (p) (void)hipHostFree(p); }
+  } hf{hbuf};
   Leaves A, B;
-  const int64_t lcap = std::max<int64_t>(1 << 16, small ? small_cap : 0);
-  if (!A.ensure(lcap) || !B.ensure(lcap)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
-  {
+  int64_t cur = 6, nwork = 6;
+  Buf vs, vs_old, cntb, offb, bsum, ns, wk;  // ns: vertices made by the last split pass; wk: its new leaves
+  uint64_t vcap = 1 << 16;
+  if (prev) {
+    // the seed from the previous grid's tree
+    bool same = false;
+    if (int rc = seed_from_grid(prev, P, cc, wp, A, wk, vs, &vcap, bsum, d_total, misc.as<uint32_t>() + 31,
+                                d_vcount, hbuf, st, &cur, &nwork, prev->majorant_mode == o.majorant_mode, &same))
+      return rc;
+    if (same) {  // the previous tree is the result; its tets take the new volume's extinction
+      hipLaunchKernelGGL(k_refresh_medium, dim3(nblocks(prev->n, 256)), dim3(256), 0, st, prev->n, prev->verts, P,
+                         scale, o.majorant_mode, prev->rec, prev->rec32);
+      TV_HIP(hipGetLastError());
+      TV_HIP(hipEventRecord(e1, st));
+      TV_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (unchanged_ms) *unchanged_ms = ms;  // *out stays NULL
+      return TET_OK;
+    }
+    if (cur > o.max_tets) return fail(TET_ERR_CAPACITY, "leb_build: grid exceeds max_tets");
+  } else {
+    // roots
+    const int64_t lcap = std::max<int64_t>(1 << 16, small ? small_cap : 0);
+    if (!A.ensure(lcap) || !B.ensure(lcap)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: leaves");
     uint64_t hid[6], hv[24];
     const int p0[6] = {0, 0, 1, 1, 2, 2}, p1[6] = {1, 2, 0, 2, 0, 1};
     for (int r = 0; r < 6; r++) {
@@ -1819,10 +2217,13 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
     TV_HIP(hipMemcpyAsync(A.ids.p, hid, sizeof(hid), hipMemcpyHostToDevice, st));
     TV_HIP(hipMemcpyAsync(A.verts.p, hv, sizeof(hv), hipMemcpyHostToDevice, st));
     TV_HIP(hipMemsetAsync(A.flags.p, 0, 6, st));
+    TV_HIP(hipMemsetAsync(A.chain.p, 0, 6 * 8, st));
+    // the first worklist: the 6 roots
+    if (!wk.ensure(small ? small_cap * 4 : 64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
+    uint32_t w0[6] = {0, 1, 2, 3, 4, 5};
+    TV_HIP(hipMemcpyAsync(wk.p, w0, sizeof(w0), hipMemcpyHostToDevice, st));
   }
-  int64_t cur = 6;
   // vertex hash set
-  Buf vs, vs_old, cntb, offb, bsum, ns, wk;  // ns: vertices made by the last split pass; wk: its new leaves
   // ns: the new-vertex set (nscap keys) followed by the cell map, both
   // cleared to all ones by one fill
   uint64_t nscap = 1024;
@@ -1831,28 +2232,16 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
                      (int64_t)(nscap + kMapWords / 2),
                      kEmptyKey);
   // capacities are even powers of two and grow by factors of 4, so the
-  // sizes the set passes through do not depend on where it started
-  uint64_t vcap = 1 << 16;
-  while (small && vcap < 4 * (uint64_t)small_cap) vcap <<= 2;  // stays at most half full in the small rounds
-  if (!vs.ensure(vcap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
-  hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)vcap,
-                     kEmptyKey);
-  hipLaunchKernelGGL(k_vset_seed, dim3(1), dim3(64), 0, st, A.verts.as<uint64_t>(), (int64_t)6, vs.as<uint64_t>(),
-                     vcap - 1, d_vcount);
-
-  // the first worklist: the 6 roots
-  if (!wk.ensure(small ? small_cap * 4 : 64)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: worklist");
-  {
-    uint32_t w0[6] = {0, 1, 2, 3, 4, 5};
-    TV_HIP(hipMemcpyAsync(wk.p, w0, sizeof(w0), hipMemcpyHostToDevice, st));
+  // sizes the set passes through do not depend on where it started (a
+  // seed made its own set)
+  if (!prev) {
+    while (small && vcap < 4 * (uint64_t)small_cap) vcap <<= 2;  // stays at most half full in the small rounds
+    if (!vs.ensure(vcap * 8)) return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: vertex set");
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(vcap, 256)), dim3(256), 0, st, vs.as<uint64_t>(), (int64_t)vcap,
+                       kEmptyKey);
+    hipLaunchKernelGGL(k_vset_seed, dim3(1), dim3(64), 0, st, A.verts.as<uint64_t>(), cur, vs.as<uint64_t>(),
+                       vcap - 1, d_vcount);
   }
-  int64_t nwork = 6;
-  uint32_t* hbuf = nullptr;
-  TV_HIP(hipHostMalloc((void**)&hbuf, 128, hipHostMallocDefault));
-  struct HostFree {
-    uint32_t* p;
-    ~HostFree() { if (p) (void)hipHostFree(p); }
-  } hf{hbuf};
   int rounds = 0;
   bool done = false;
   int64_t nmain = -1;  // >= 0 once the tail rounds append (leaves below nmain stay in key order)
@@ -1870,6 +2259,8 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
     S.verts[1] = B.verts.as<uint64_t>();
     S.flags[0] = A.flags.as<uint8_t>();
     S.flags[1] = B.flags.as<uint8_t>();
+    S.chain[0] = A.chain.as<uint64_t>();
+    S.chain[1] = B.chain.as<uint64_t>();
     S.cnt = cntb.as<uint32_t>();
     S.bsum = bsum.as<uint32_t>();
     S.work = wk.as<uint32_t>();
@@ -1909,7 +2300,8 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
                          A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), vs.as<uint64_t>(), vcap - 1,
                          ns.as<uint64_t>(), nscap - 1, (const uint32_t*)(ns.as<uint64_t>() + nscap),
                          cbox.as<uint32_t>(), d_splitc, splitc, cntb.as<uint32_t>(), (int)(cur > nmain));
-    hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
+    if (nwork > 0)  // a seed from a previous grid may list no wanted leaf
+      hipLaunchKernelGGL(k_want, dim3(nblocks(nwork, 256)), dim3(256), 0, st, nwork, wk.as<uint32_t>(),
                        A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), P,
                        cc, wp, vs.as<uint64_t>(), vcap - 1, d_splitc, splitc, nmain < 0 ? nullptr : cntb.as<uint32_t>());
     if (nmain < 0 && scan_u32(cntb.as<uint32_t>(), cur, offb.as<uint32_t>(), bsum, d_total, st))
@@ -1962,8 +2354,9 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
     uint32_t* cells = (uint32_t*)(ns.as<uint64_t>() + nscap);
     if (nmain < 0) {
       hipLaunchKernelGGL(k_split, dim3(nblocks(cur, 256)), dim3(256), 0, st, cur, A.ids.as<uint64_t>(),
-                         A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), cntb.as<uint32_t>(), offb.as<uint32_t>(),
-                         B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(), vs.as<uint64_t>(),
+                         A.verts.as<uint64_t>(), A.flags.as<uint8_t>(), A.chain.as<uint64_t>(), cntb.as<uint32_t>(),
+                         offb.as<uint32_t>(), B.ids.as<uint64_t>(), B.verts.as<uint64_t>(), B.flags.as<uint8_t>(),
+                         B.chain.as<uint64_t>(), vs.as<uint64_t>(),
                          vcap - 1, d_vcount, dense ? nullptr : ns.as<uint64_t>(), nscap - 1, cells,
                          wk.as<uint32_t>());
       A.swap_with(B);
@@ -1974,6 +2367,7 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
         B.ids.release();
         B.verts.release();
         B.flags.release();
+        B.chain.release();
         B.cap = 0;
         const int64_t chunks = nmain / kChunk;  // whole chunks of the main part
         if (!cbox.ensure((size_t)std::max<int64_t>(chunks, 1) * 32))
@@ -1985,7 +2379,8 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
     } else {
       hipLaunchKernelGGL(k_split_append, dim3(nblocks(splits, 256)), dim3(256), 0, st, splits, cntb.as<uint32_t>(),
                          cur, nmain, A.ids.as<uint64_t>(), A.verts.as<uint64_t>(), A.flags.as<uint8_t>(),
-                         anc.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, d_vcount, ns.as<uint64_t>(), nscap - 1,
+                         A.chain.as<uint64_t>(), anc.as<uint32_t>(), vs.as<uint64_t>(), vcap - 1, d_vcount,
+                         ns.as<uint64_t>(), nscap - 1,
                          cells, wk.as<uint32_t>());
     }
     cur = total;
@@ -1997,19 +2392,22 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
   B.ids.release();
   B.verts.release();
   B.flags.release();
+  B.chain.release();
 
   // finalize
   tet_grid* g = new tet_grid();
   memset(g, 0, sizeof(*g));
   TV_HIP(hipGetDevice(&g->device));
   g->n = cur;
+  g->majorant_mode = o.majorant_mode;
   g->ids = (uint64_t*)dev_alloc(cur * 8);
   g->keys = (uint64_t*)dev_alloc(cur * 8);
   g->verts = (uint64_t*)dev_alloc(cur * 32);
+  g->chain = (uint64_t*)dev_alloc(cur * 8);
   g->rec = (TetRec*)dev_alloc(cur * sizeof(TetRec));
   bool compact = o.majorant_mode == 0 && cur <= kMaxTets32;
   g->rec32 = compact ? (TetRec32*)dev_alloc(cur * sizeof(TetRec32)) : nullptr;
-  if (!g->ids || !g->keys || !g->verts || !g->rec || (compact && !g->rec32)) {
+  if (!g->ids || !g->keys || !g->verts || !g->chain || !g->rec || (compact && !g->rec32)) {
     tet_grid_free(g);
     return fail(TET_ERR_OUT_OF_MEMORY, "leb_build: grid arrays");
   }
@@ -2017,6 +2415,7 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
   if (nmain < 0) {
     he = hipMemcpyAsync(g->ids, A.ids.p, cur * 8, hipMemcpyDeviceToDevice, st);
     if (he == hipSuccess) he = hipMemcpyAsync(g->verts, A.verts.p, cur * 32, hipMemcpyDeviceToDevice, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(g->chain, A.chain.p, cur * 8, hipMemcpyDeviceToDevice, st);
   } else {
     // depth-first order of the main part and the appended leaves
     const int64_t m = cur - nmain;
@@ -2037,7 +2436,8 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
     hipLaunchKernelGGL(k_group_slots, dim3(nblocks(m, 256)), dim3(256), 0, st, m, anc.as<uint32_t>(), pos, gc,
                        slots.as<uint32_t>());
     hipLaunchKernelGGL(k_merge, dim3(nblocks(cur, 256)), dim3(256), 0, st, nmain, m, cur, A.ids.as<uint64_t>(),
-                       A.verts.as<uint64_t>(), anc.as<uint32_t>(), pos, slots.as<uint32_t>(), g->ids, g->verts);
+                       A.verts.as<uint64_t>(), A.chain.as<uint64_t>(), anc.as<uint32_t>(), pos, slots.as<uint32_t>(),
+                       g->ids, g->verts, g->chain);
     he = hipGetLastError();
     if (he == hipSuccess) he = hipStreamSynchronize(st);  // before the scratch returns to the pool
   }
@@ -2121,6 +2521,42 @@ int build_grid_sparse(const tet_sparse_density* sp, const tet_camera* cam, float
   if (out) *out = nullptr;
   if (!sp) return fail(TET_ERR_INVALID_ARG, "leb_build_sparse: density is NULL");
   return build_common(nullptr, sp, cam, target_px, opts_in, st, out);
+}
+
+// A rebuild for a new camera (or density, or options) seeded from the grid's
+// current tree; the new arrays replace the old ones only on success (the
+// grid's extra channels and density model, per tet, are dropped).  When the
+// predicate keeps its value on every node of the tree, the grid is kept as
+// it is (channels and model included).
+static int update_common(tet_grid* g, const tet_density* dens, const tet_sparse_density* sp, const tet_camera* cam,
+                         float target_px, const tet_build_opts* opts_in, hipStream_t st) {
+  if (!g) return fail(TET_ERR_INVALID_ARG, "leb_update: grid is NULL");
+  int dev = -1;
+  TV_HIP(hipGetDevice(&dev));
+  if (dev != g->device) return fail(TET_ERR_INVALID_ARG, "leb_update: the grid lives on another device");
+  tet_grid* ng = nullptr;
+  float same_ms = -1.0f;
+  if (int rc = build_common(dens, sp, cam, target_px, opts_in, st, &ng, g, &same_ms)) return rc;
+  if (!ng) {  // every node of the tree keeps its predicate: the grid is the result
+    g->stats.rounds = 0;
+    g->stats.ms = same_ms;
+    return TET_OK;
+  }
+  std::swap(*g, *ng);
+  tet_grid_free(ng);  // the previous arrays
+  return TET_OK;
+}
+
+int update_grid(tet_grid* g, const tet_density* dens, const tet_camera* cam, float target_px,
+                const tet_build_opts* opts_in, hipStream_t st) {
+  if (!dens || !dens->data) return fail(TET_ERR_INVALID_ARG, "leb_update: density is NULL");
+  return update_common(g, dens, nullptr, cam, target_px, opts_in, st);
+}
+
+int update_grid_sparse(tet_grid* g, const tet_sparse_density* sp, const tet_camera* cam, float target_px,
+                       const tet_build_opts* opts_in, hipStream_t st) {
+  if (!sp) return fail(TET_ERR_INVALID_ARG, "leb_update_sparse: density is NULL");
+  return update_common(g, nullptr, sp, cam, target_px, opts_in, st);
 }
 
 // Extra channels: checked first (all of them), then reduced per tet; the

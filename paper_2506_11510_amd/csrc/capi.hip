@@ -26,6 +26,9 @@ int render_voxels(const tet_density*, const tet_camera*, const tet_medium*, cons
                   const tet_render_opts*, float*, int32_t, hipStream_t, tet_render_stats*);
 int locate_points(const tet_grid*, const float*, int64_t, int64_t*, int32_t, hipStream_t);
 int eval_functions(int32_t, int64_t, const float*, const float*, float*, int32_t, hipStream_t);
+int update_grid(tet_grid*, const tet_density*, const tet_camera*, float, const tet_build_opts*, hipStream_t);
+int update_grid_sparse(tet_grid*, const tet_sparse_density*, const tet_camera*, float, const tet_build_opts*,
+                       hipStream_t);
 int render_grid_noalloc(const tet_grid*, const tet_camera*, const tet_medium*, const tet_light*, int32_t, uint64_t,
                         const tet_render_opts*, float*, hipStream_t);
 int render_batch(int32_t, const tet_grid* const*, const tet_camera*, const tet_medium*, const tet_light*,
@@ -273,6 +276,16 @@ int leb_build_sparse(const tet_sparse_density* density, const tet_camera* camera
   TV_GUARD(build_grid_sparse(density, camera, target_cell_px, opts, (hipStream_t)hip_stream, out));
 }
 
+int leb_update(tet_grid* grid, const tet_density* density, const tet_camera* camera, float target_cell_px,
+               const tet_build_opts* opts, void* hip_stream) {
+  TV_GUARD(update_grid(grid, density, camera, target_cell_px, opts, (hipStream_t)hip_stream));
+}
+
+int leb_update_sparse(tet_grid* grid, const tet_sparse_density* density, const tet_camera* camera,
+                      float target_cell_px, const tet_build_opts* opts, void* hip_stream) {
+  TV_GUARD(update_grid_sparse(grid, density, camera, target_cell_px, opts, (hipStream_t)hip_stream));
+}
+
 int tet_grid_info(const tet_grid* g, int64_t* num_tets, int32_t* max_depth, tet_build_stats* stats) {
   if (!g) return fail(TET_ERR_INVALID_ARG, "tet_grid_info: grid is NULL");
   if (num_tets) *num_tets = g->n;
@@ -336,6 +349,7 @@ void tet_grid_free(tet_grid* g) {
   dev_free(g->keys);
   dev_free(g->kidx);
   dev_free(g->verts);
+  dev_free(g->chain);
   dev_free(g->rec);
   dev_free(g->rec32);
   for (int k = 0; k < 3; k++) dev_free(g->ch[k]);

@@ -395,12 +395,14 @@ struct tet_grid {
   int device;
   int64_t n;
   int32_t max_depth;
+  int32_t majorant_mode;  // of the build (0 tight, 1 loose)
   tet_build_stats stats;
   uint64_t* ids;    // heap ids, depth-first order
   uint64_t* keys;   // depth-first keys (sorted ascending)
   uint32_t* kidx;   // bucket index of the keys (key_bucket_index)
   int32_t kbits;
   uint64_t* verts;  // 4 packed lattice vertices per tet
+  uint64_t* chain;  // per tet: bit d = its depth-d ancestor was split because the want predicate held
   tv::TetRec* rec;      // traversal records
   tv::TetRec32* rec32;  // compact records (NULL when the grid cannot use them)
   float* ch[3];         // extra channels per tet: temperature, albedo, g (NULL = absent)

@@ -178,6 +178,24 @@ def scene(name: str, **over) -> dict:
     return s
 
 
+def camera_path(cam: dict, count: int, degrees_per_frame: float = 2.0, dolly_per_frame: float = 0.0) -> list:
+    """`count` cameras of a scripted move (frame 0 = `cam`): the position
+    turned about the vertical axis through look_at by `degrees_per_frame`
+    each frame, and moved toward look_at by `dolly_per_frame` of its
+    distance each frame; positions rounded to FP32, other fields as `cam`."""
+    out = []
+    c = np.array(cam["look_at"], np.float64)
+    p0 = np.array(cam["pos"], np.float64) - c
+    for f in range(count):
+        a = math.radians(degrees_per_frame * f)
+        r = (1.0 - dolly_per_frame) ** f
+        x = (p0[0] * math.cos(a) + p0[2] * math.sin(a)) * r
+        z = (-p0[0] * math.sin(a) + p0[2] * math.cos(a)) * r
+        pos = [float(np.float32(c[0] + x)), float(np.float32(c[1] + p0[1] * r)), float(np.float32(c[2] + z))]
+        out.append(dict(cam, pos=pos))
+    return out
+
+
 def scene_batch(count: int = 64, first_seed: int = 100) -> list:
     """A batch of small scenes for batched rendering: scene i has seed
     first_seed + i; even i are Gaussian blobs at 64^3 on a uniform depth-9

@@ -5,9 +5,16 @@ albedo 0.95, HG g 0.6).
 At 256^3 (4.0 M tets) the oracle builds the same grid in seconds: the grid
 must match it bit for bit and the image its strided pixel subset at the
 image bar.  At the full 1024^3 size (85.7 M tets) the oracle's recursive
-build is out of reach, so the grid is checked by properties that hold at
-any size -- volume, reciprocal links, face matching on sampled links -- and
-the render by its own invariants."""
+build takes ~7 minutes and ~55 GB, so tests/golden/make_plume1024.py (which
+runs only the generator and the oracle) stored its SHA-256 digests and its
+32-spp render of a strided pixel subset: the device grid must match the
+digests bit for bit and its image the subset at the image bar; properties
+that hold at any size -- volume, reciprocal links, face matching on sampled
+links -- are checked as well."""
+import base64
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -64,16 +71,34 @@ def depth_of(ids):
     return lg - 3
 
 
-def test_plume_full_size_grid_invariants_and_render(tv):
-    say("case plume 1024^3: grid invariants at full size, render")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plume1024.json")
+
+
+def sha(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.mark.timeout(900)
+def test_plume_full_size_against_oracle_golden_and_invariants(tv):
+    say("case plume 1024^3: grid against the oracle's digests, image against its subset, invariants")
     import torch
+    gold = json.load(open(GOLDEN))
     sc = synthetic.scene("plume")
-    d = torch.from_numpy(sc["density_fn"]()).cuda()
+    dh = sc["density_fn"]()
+    assert sha(dh) == gold["density_sha256"], "the generator made another volume than the stored one"
+    d = torch.from_numpy(dh).cuda()
+    del dh
     g = tv.leb_build(d, 1024, sc["camera"], build=sc["build"])
     del d
     info = g.info()
     n, D = info["num_tets"], info["max_depth"]
     say(f"  {n} tets, depth {D}, {info['rounds']} rounds, {info['ms']:.1f} ms")
+    assert n == gold["num_tets"] and D == gold["max_depth"]
+    for k in ("ids", "nbr", "verts", "sigma", "majorant"):
+        a = g.export(fields=(k,))[k]
+        assert sha(a) == gold[f"{k}_sha256"], f"plume grid: {k} differs from the oracle's"
+        del a
+    say("  grid bit-exact with the oracle's (ids, links, vertices, extinction, majorant)")
     assert 50_000_000 <= n <= 100_000_000 and D <= 30
     e = g.export(device=True, fields=("ids", "nbr", "verts"))
     # volume: every tet of depth d is 2^-d of a root, the 6 roots fill the cube
@@ -113,3 +138,9 @@ def test_plume_full_size_grid_invariants_and_render(tv):
     say(f"  render 32 spp: {st['ms']:.1f} ms, {st['tet_steps']} tet steps, mean {im.mean():.4f}")
     assert np.isfinite(im).all() and im.min() >= 0.0 and 0.01 < im.mean() < 10.0
     assert st["truncated"] == 0 and st["tet_steps"] > 1e9 and st["real_collisions"] > 1e6
+    r = gold["render"]
+    assert (r["spp"], r["seed"]) == (32, 9)
+    ref = np.frombuffer(base64.b64decode(r["rgb_f32_le_base64"]), "<f4").reshape(-1, 3)
+    pix = np.arange(0, 1024 * 1024, r["pixel_stride"])
+    assert len(pix) == len(ref) == r["pixels"]
+    assert_image_parity(im.reshape(-1, 3)[pix], ref, "plume 1024 image vs the oracle's subset")
