@@ -88,7 +88,7 @@ def _counter_rows(d):
     return rows
 
 
-def summarize_pmc(fetch_dir, write_dir, out_path, command):
+def summarize_pmc(fetch_dir, write_dir, out_path, command, workload="the 1024^2 x 32 spp cloud frame"):
     """Traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE runs (KiB
     per dispatch), each scaled by the factor that maps the same counter on
     a plain 1 GiB device copy to its true size."""
@@ -110,7 +110,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
     w_fac = (COPY_BYTES / 1024) / max(wc)
     traffic = (f_kib * f_fac + w_kib * w_fac) * 1024
     with open(out_path, "w") as f:
-        f.write("# HBM traffic of the tracing kernel k_render<TetMedium32> on the 1024^2 x 32 spp cloud frame\n")
+        f.write(f"# HBM traffic of the tracing kernel k_render<TetMedium32> on {workload}\n")
         f.write(f"# command: {command}\n")
         f.write("# counters are KiB per dispatch; the copy factors map a plain 1 GiB device copy to 1 GiB\n")
         f.write(f"source_hash = {kernel_source_hash()}\n")
@@ -397,7 +397,7 @@ def host_io_leg(tv, torch, d, sc, steps: int = 3) -> dict:
             "bytes_over_pcie_per_step": int(d.nbytes + img.nbytes)}
 
 
-def plume_leg(tv, torch) -> dict:
+def plume_leg(tv, torch, host_rounds: bool = False) -> dict:
     """The production-scale configuration: 1024^3 plume density resident in
     HBM, adaptive LEB build (~86 M tets), 1024^2 renders at 32 and 1024 spp
     with 64 bounces.  Returns the figures and (grid, scene, 1024-spp image)
@@ -407,6 +407,8 @@ def plume_leg(tv, torch) -> dict:
     sc = synthetic.scene("plume")
     sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
                         event_wait=48)
+    if host_rounds:
+        sc["build"] = dict(sc["build"], host_rounds=1)
     t0 = time.perf_counter()
     dev = torch.from_numpy(sc["density_fn"]()).cuda()
     gen_s = time.perf_counter() - t0
@@ -592,6 +594,16 @@ def batch_leg(tv, torch, count: int, frames: int = 3) -> dict:
             "tet_steps_per_s_graph": round(st["tet_steps"] / (ms_graph / 1e3), 1)}
 
 
+def calibrate_copy(torch):
+    """A plain device copy of COPY_BYTES: the counters' scale reference."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -619,12 +631,18 @@ def main():
     ap.add_argument("--nrc-frames", type=int, default=100)
     ap.add_argument("--nrc-lr", type=float, default=1e-2)
     ap.add_argument("--nrc-ema", type=float, default=0.99)
+    ap.add_argument("--plume-only", action="store_true",
+                    help="run only the 1024^3 plume leg (its build and 32 / 1024 spp renders) and print its figures")
+    ap.add_argument("--host-rounds", action="store_true",
+                    help="build with every round driven from the host (no cooperative launch; the grid is the "
+                         "same): for runs under rocprofv3, which fails at exit after a cooperative launch")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"))
     ap.add_argument("--command", default="")
+    ap.add_argument("--workload", default="", help="workload named in a counter summary")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc, args.command)
+        summarize_pmc(*args.summarize_pmc, args.command, *( [args.workload] if args.workload else []))
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.command)
@@ -640,7 +658,16 @@ def main():
     import synthetic
     import paper_2506_11510_amd as tv
 
+    if args.plume_only:
+        plume, _ = plume_leg(tv, torch, args.host_rounds)
+        if args.calibrate_copy:
+            calibrate_copy(torch)
+        print(json.dumps({"plume": plume}), flush=True)
+        return
+
     sc = synthetic.scene("cloud")
+    if args.host_rounds:
+        sc["build"] = dict(sc["build"], host_rounds=1)
     # launch configuration of the tracing kernel: the library's autotuner
     # times probe renders of this frame (8 spp) from this starting point
     # (one sample per work item, batches of 64 items per wave, compact
@@ -752,7 +779,7 @@ def main():
     del dev
     plume = None
     if not args.no_plume:
-        res["plume"], plume = plume_leg(tv, torch)
+        res["plume"], plume = plume_leg(tv, torch, args.host_rounds)
     if not args.no_nrc:
         if plume is not None:  # the cache study runs on the production-scale scene
             del grid
@@ -764,12 +791,7 @@ def main():
             res["nrc"] = nrc_leg(tv, torch, grid, sc, args.nrc_frames, args.nrc_lr, ema=args.nrc_ema)
             res["nrc"]["scene"] = "cloud 256^3 (32 bounces)"
     if args.calibrate_copy:
-        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibrate_copy(torch)
     if not args.no_cpu_baseline:
         # the host threads this process may use: the GPU machine grants one
         # GPU's share of its cores (16), whatever os.cpu_count() reports

@@ -90,7 +90,9 @@ typedef struct {
   int64_t max_tets;        /* capacity; TET_ERR_CAPACITY beyond it */
   uint64_t rand_seed;
   int32_t rand_thresh;
-  int32_t reserved;
+  int32_t host_rounds;     /* 1: every refinement round is driven from the host; 0 (default): while the
+                              grid is small, rounds run inside one cooperative launch.  The grid is the
+                              same; profilers that fail on cooperative launches want 1. */
 } tet_build_opts;
 
 typedef struct {

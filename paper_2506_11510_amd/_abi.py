@@ -50,7 +50,7 @@ class TetLight(ctypes.Structure):
 class TetBuildOpts(ctypes.Structure):
     _fields_ = [("want_mode", ctypes.c_int32), ("uniform_depth", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("majorant_mode", ctypes.c_int32), ("variation_tau", ctypes.c_double), ("max_tets", ctypes.c_int64),
-                ("rand_seed", ctypes.c_uint64), ("rand_thresh", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("rand_seed", ctypes.c_uint64), ("rand_thresh", ctypes.c_int32), ("host_rounds", ctypes.c_int32)]
 
 
 class TetRenderOpts(ctypes.Structure):
@@ -223,7 +223,7 @@ def make_build_opts(b: dict | None) -> TetBuildOpts:
     o = TetBuildOpts()
     lib().tet_build_opts_defaults(ctypes.byref(o))
     for k, v in (b or {}).items():
-        if hasattr(o, k) and k != "reserved":
+        if hasattr(o, k):
             setattr(o, k, type(getattr(o, k))(v))
     return o
 
@@ -238,7 +238,7 @@ def make_render_opts(r: dict | None) -> TetRenderOpts:
             o.nrc = v.handle if v is not None else None
         elif k == "emission":
             o.emission[:] = [float(x) for x in v]
-        elif hasattr(o, k) and k != "reserved":
+        elif hasattr(o, k):
             setattr(o, k, type(getattr(o, k))(v))
     return o
 
@@ -247,7 +247,7 @@ def make_nrc_opts(d: dict | None) -> TetNrcOpts:
     o = TetNrcOpts()
     lib().tet_nrc_opts_defaults(ctypes.byref(o))
     for k, v in (d or {}).items():
-        if not hasattr(o, k) or k == "reserved":
+        if not hasattr(o, k):
             raise KeyError(f"unknown radiance-cache option {k}")
         setattr(o, k, type(getattr(o, k))(v))
     return o

@@ -2087,7 +2087,8 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
   if (opts_in) o = *opts_in;
   else tet_build_opts_defaults(&o);
   if (o.want_mode < 0 || o.want_mode > 2 || o.max_tets < 6 || o.max_tets > (1ll << 30) || o.max_depth < 0 ||
-      o.max_depth > 56 || o.uniform_depth < 0 || o.uniform_depth > 56 || o.majorant_mode < 0 || o.majorant_mode > 1)
+      o.max_depth > 56 || o.uniform_depth < 0 || o.uniform_depth > 56 || o.majorant_mode < 0 || o.majorant_mode > 1 ||
+      o.host_rounds < 0 || o.host_rounds > 1)
     return fail(TET_ERR_INVALID_ARG, "leb_build: bad options");
   if (o.want_mode == 0 && !(target_px > 0.0f)) return fail(TET_ERR_INVALID_ARG, "leb_build: target_cell_px must be > 0");
   if (!(scale >= 0.0f) || std::isinf(scale)) return fail(TET_ERR_INVALID_ARG, "leb_build: bad density_scale");
@@ -2162,7 +2163,7 @@ static int build_common(const tet_density* dens, const tet_sparse_density* sp, c
   TV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   TV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_small_rounds), 256, 0));
   const int64_t small_cap = std::min<int64_t>(kSmallCap, o.max_tets);
-  const bool small = !prev && coop && occ > 0 && ncu > 0 && small_cap >= 12;
+  const bool small = !prev && !o.host_rounds && coop && occ > 0 && ncu > 0 && small_cap >= 12;
   // half the CUs: the rounds are small, and every block adds an arrival to
   // each grid barrier (128 blocks measured best on 256 CUs)
   const int small_blocks = std::max(1, ncu / 2);

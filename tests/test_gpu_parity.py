@@ -93,6 +93,18 @@ def test_build_phases_bitexact(tv, tiny_density, max_tets):
         assert e.value.status == -3
 
 
+@pytest.mark.parametrize("b", [dict(uniform_depth=9), dict(want_mode=2, max_depth=16, rand_seed=1, rand_thresh=30000)])
+def test_build_host_rounds_option(tv, tiny_density, b):
+    """host_rounds = 1 drives every round from the host (no cooperative
+    launch): the same grid as the default build and the oracle's."""
+    say(f"case build host_rounds {b}")
+    bb = dict(TINY["build"], **b)
+    g = gpu_build(tv, tiny_density, 64, TINY["camera"], dict(bb, host_rounds=1))
+    o = oracle.leb_build(tiny_density, 64, TINY["camera"], bb)
+    assert_grids_equal(g.export(), o.export(), f"host rounds {b}")
+    assert_grids_equal(gpu_build(tv, tiny_density, 64, TINY["camera"], bb).export(), o.export(), "default")
+
+
 def test_build_host_rounds_only(tv, tiny_density):
     """max_tets below 12 leaves no room for the cooperative rounds, so every
     round runs from the host (the path of devices without cooperative
