@@ -289,6 +289,20 @@ int tet_autotune(const tet_grid* grid, const tet_camera* camera, const tet_mediu
                  const tet_autotune_opts* aopts /* NULL = defaults */, tet_render_opts* inout, void* hip_stream,
                  double* best_ms);
 
+/* The face data of the traversal records as the walk reads them (paper,
+ * "Path Tracing within Tetrahedral Grids": each face stored as one of 18
+ * orientations and an offset, so an exit test is a few operations): per
+ * tet and face f, codes[4 t + f] = 2 N + s (outward normal (-1)^s dir_N over
+ * the 9 directions x, y, z, x+y, x-y, x+z, x-z, y+z, y-z), offsets[4 t + f] =
+ * the outward normal . any vertex of the face, in lattice units (world *
+ * 2^20), links[4 t + f] = the link word as stored.  layout 48: the 48-byte
+ * records (link = (index << 2) | back face, or 0xFFFFFFFF on the boundary);
+ * 32: the compact records (link = 27-bit index, or 2^27 - 1 on the
+ * boundary; TET_ERR_INVALID_ARG when the grid has none).  Any output may be
+ * NULL; all on one side (on_device). */
+int tet_grid_export_faces(const tet_grid* grid, int32_t layout, uint8_t* codes, int32_t* offsets, uint32_t* links,
+                          int32_t on_device, void* hip_stream);
+
 /* Extra channels per tet (paper, "Volumetric Path Tracing": the
  * implementation also carries e.g. temperature, albedo and phase-function
  * parameters per tet).  Each given channel -- n^3 FP32 voxels, x fastest,

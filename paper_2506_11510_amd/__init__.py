@@ -140,6 +140,16 @@ class Grid:
         check(lib().tet_grid_set_channels(self._h, ctypes.byref(c), _stream()), "tet_grid_set_channels")
         self._channels = tuple(a is not None for a in arrs)
 
+    def export_faces(self, layout: int = 48) -> dict:
+        """Face data of the 48- or 32-byte traversal records: codes (n, 4)
+        uint8, offsets (n, 4) int32 (lattice units), links (n, 4) uint32."""
+        n = self.num_tets
+        out = dict(codes=np.empty((n, 4), np.uint8), offsets=np.empty((n, 4), np.int32),
+                   links=np.empty((n, 4), np.uint32))
+        check(lib().tet_grid_export_faces(self._h, int(layout), out["codes"].ctypes.data, out["offsets"].ctypes.data,
+                                          out["links"].ctypes.data, 0, _stream()), "tet_grid_export_faces")
+        return out
+
     def export_channels(self) -> dict:
         """Per-tet channel values (numpy float32; None for absent ones)."""
         n = self.num_tets

@@ -124,6 +124,7 @@ SIGNATURES = {
     "tet_grid_info": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(TetBuildStats)]),
     "tet_grid_export": (ctypes.c_int, [VP, VP, VP, VP, VP, VP, ctypes.c_int32, VP]),
+    "tet_grid_export_faces": (ctypes.c_int, [VP, ctypes.c_int32, VP, VP, VP, ctypes.c_int32, VP]),
     "tet_grid_set_channels": (ctypes.c_int, [VP, ctypes.POINTER(TetChannels), VP]),
     "tet_grid_export_channels": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int32]),
     "tet_grid_set_density_model": (ctypes.c_int, [VP, ctypes.POINTER(TetDensity), ctypes.c_int32, VP]),

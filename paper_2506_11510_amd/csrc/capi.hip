@@ -232,6 +232,70 @@ static int export_grid(const tet_grid* g, uint64_t* ids, uint32_t* nbr4, float* 
   return TET_OK;
 }
 
+// Face data of the traversal records as stored: per face the orientation
+// code, the plane offset in lattice units and the link word.
+__global__ void k_export_faces(int64_t n, const TetRec* __restrict__ rec, const TetRec32* __restrict__ rec32,
+                               uint8_t* __restrict__ codes, int32_t* __restrict__ offs,
+                               uint32_t* __restrict__ links) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (rec32) {
+    const TetRec32 r = rec32[i];
+    const uint32_t o1 = (uint32_t)((((uint64_t)r.w[1] << 32) | r.w[0]) >> 23);
+    const uint32_t o2 = (uint32_t)((((uint64_t)r.w[2] << 32) | r.w[1]) >> 14);
+    const int32_t io[4] = {((int32_t)(r.w[0] << 9)) >> 9, ((int32_t)(o1 << 9)) >> 9, ((int32_t)(o2 << 9)) >> 9,
+                           ((int32_t)(r.w[2] << 4)) >> 9};
+    for (int f = 0; f < 4; f++) {
+      if (codes) codes[4 * i + f] = (uint8_t)(r.w[4 + f] >> 27);
+      if (offs) offs[4 * i + f] = io[f];
+      if (links) links[4 * i + f] = r.w[4 + f] & kLink27Boundary;
+    }
+  } else {
+    const TetRec r = rec[i];
+    for (int f = 0; f < 4; f++) {
+      if (codes) codes[4 * i + f] = (uint8_t)((r.codes >> (8 * f)) & 0xFFu);
+      if (offs) offs[4 * i + f] = (int32_t)(r.off[f] * 0x1p20f);  // n_f . v * 2^-20, exact
+      if (links) links[4 * i + f] = r.nbr[f];
+    }
+  }
+}
+
+static int export_faces(const tet_grid* g, int32_t layout, uint8_t* codes, int32_t* offs, uint32_t* links,
+                        int32_t on_device, hipStream_t st) {
+  if (!g || (layout != 32 && layout != 48)) return fail(TET_ERR_INVALID_ARG, "tet_grid_export_faces: bad arguments");
+  if (layout == 32 && !g->rec32) return fail(TET_ERR_INVALID_ARG, "tet_grid_export_faces: no compact records");
+  const int64_t n = g->n;
+  const size_t b_c = (size_t)n * 4, b_o = (size_t)n * 16;
+  uint8_t* d_c = codes;
+  int32_t* d_o = offs;
+  uint32_t* d_l = links;
+  char* tmp = nullptr;
+  if (!on_device) {
+    tmp = (char*)dev_alloc((codes ? b_c : 0) + (offs ? b_o : 0) + (links ? b_o : 0) + 64);
+    if (!tmp) return fail(TET_ERR_OUT_OF_MEMORY, "tet_grid_export_faces: scratch");
+    char* q = tmp;
+    if (offs) { d_o = (int32_t*)q; q += b_o; }
+    if (links) { d_l = (uint32_t*)q; q += b_o; }
+    if (codes) d_c = (uint8_t*)q;
+  }
+  struct Free {
+    void* p;
+    ~Free() { if (p) dev_free(p); }
+  } f_{tmp};
+  if (codes || offs || links) {
+    hipLaunchKernelGGL(k_export_faces, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, g->rec,
+                       layout == 32 ? g->rec32 : nullptr, d_c, d_o, d_l);
+    TV_HIP(hipGetLastError());
+  }
+  if (!on_device) {
+    if (codes) TV_HIP(hipMemcpyAsync(codes, d_c, b_c, hipMemcpyDeviceToHost, st));
+    if (offs) TV_HIP(hipMemcpyAsync(offs, d_o, b_o, hipMemcpyDeviceToHost, st));
+    if (links) TV_HIP(hipMemcpyAsync(links, d_l, b_o, hipMemcpyDeviceToHost, st));
+  }
+  TV_HIP(hipStreamSynchronize(st));
+  return TET_OK;
+}
+
 }  // namespace tv
 
 using namespace tv;
@@ -324,6 +388,11 @@ int tet_render(const tet_grid* g, const tet_camera* camera, const tet_medium* me
 
 int tet_locate(const tet_grid* g, const float* pts, int64_t count, int64_t* out, int32_t on_device, void* hip_stream) {
   TV_GUARD(locate_points(g, pts, count, out, on_device, (hipStream_t)hip_stream));
+}
+
+int tet_grid_export_faces(const tet_grid* grid, int32_t layout, uint8_t* codes, int32_t* offsets, uint32_t* links,
+                          int32_t on_device, void* hip_stream) {
+  TV_GUARD(export_faces(grid, layout, codes, offsets, links, on_device, (hipStream_t)hip_stream));
 }
 
 int tet_render_noalloc(const tet_grid* g, const tet_camera* camera, const tet_medium* medium, const tet_light* light,

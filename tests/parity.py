@@ -34,3 +34,20 @@ def assert_grids_equal(gpu: dict, ref: dict, what=""):
         else:
             eq = a == b
         assert eq.all(), f"{what}: {k} differs at {np.argwhere(~eq)[:5].tolist()} of {a.shape}"
+
+
+def assert_faces_equal(g, ref: dict, what=""):
+    """The face data the walk reads -- orientation codes and plane offsets of
+    the 48-byte and (when the grid has them) the compact records -- equal the
+    oracle's, and each layout's links equal the exported neighbour table."""
+    nbr = g.export(fields=("nbr",))["nbr"]
+    for layout in (48, 32):
+        try:
+            f = g.export_faces(layout)
+        except Exception as e:  # no compact records (loose majorants)
+            assert layout == 32 and getattr(e, "status", None) == -1, e
+            continue
+        assert np.array_equal(f["codes"], ref["codes"]), f"{what}: face codes differ ({layout}-byte records)"
+        assert np.array_equal(f["offsets"], ref["offsets"]), f"{what}: plane offsets differ ({layout}-byte records)"
+        want = nbr if layout == 48 else np.where(nbr == 0xFFFFFFFF, (1 << 27) - 1, nbr >> 2).astype(np.uint32)
+        assert np.array_equal(f["links"], want), f"{what}: links of the {layout}-byte records"

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synthetic
-from parity import assert_grids_equal, assert_image_parity
+from parity import assert_faces_equal, assert_grids_equal, assert_image_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,9 @@ def test_build_uniform_bitexact(tv, tiny_density, depth):
     b = dict(TINY["build"], uniform_depth=depth)
     g = gpu_build(tv, tiny_density, 64, TINY["camera"], b)
     o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
-    assert_grids_equal(g.export(), o.export(), f"uniform {depth}")
+    e = o.export()
+    assert_grids_equal(g.export(), e, f"uniform {depth}")
+    assert_faces_equal(g, e, f"uniform {depth}")
     assert g.info()["max_depth"] == depth
 
 
@@ -57,7 +59,9 @@ def test_build_random_adaptive_bitexact(tv, tiny_density, seed, depth, thresh):
     b = dict(TINY["build"], want_mode=2, max_depth=depth, rand_seed=seed, rand_thresh=thresh)
     g = gpu_build(tv, tiny_density, 64, TINY["camera"], b)
     o = oracle.leb_build(tiny_density, 64, TINY["camera"], b)
-    assert_grids_equal(g.export(), o.export(), f"random {seed}")
+    e = o.export()
+    assert_grids_equal(g.export(), e, f"random {seed}")
+    assert_faces_equal(g, e, f"random {seed}")
 
 
 @pytest.mark.parametrize("maj,tau,tgt", [(1, 0.3, 2.0), (0, 0.1, 1.0), (1, 0.6, 0.5)])
@@ -68,7 +72,9 @@ def test_build_criteria_bitexact(tv, maj, tau, tgt):
     say(f"case build criteria maj {maj} tau {tau} target {tgt}")
     g = gpu_build(tv, d, 32, sc["camera"], b)
     o = oracle.leb_build(d, 32, sc["camera"], b)
-    assert_grids_equal(g.export(), o.export(), "criteria")
+    e = o.export()
+    assert_grids_equal(g.export(), e, "criteria")
+    assert_faces_equal(g, e, "criteria")  # loose majorants (maj 1): 48-byte records only
 
 
 RANDOM_706K = dict(want_mode=2, max_depth=17, rand_seed=3, rand_thresh=22000)  # 706,206 tets
@@ -285,7 +291,10 @@ def test_cloud_full_size(tv):
     say("case cloud full size: oracle build", g.info())
     o = oracle.leb_build(d, 256, sc["camera"], sc["build"])
     say("case cloud full size: compare grids")
-    assert_grids_equal(g.export(), o.export(), "cloud")
+    e = o.export()
+    assert_grids_equal(g.export(), e, "cloud")
+    assert_faces_equal(g, e, "cloud")
+    del e
     say("case cloud full size: gpu render")
     # the launch bench.py times (one sample per work item, chunk sums added
     # atomically, compact records, 5 waves per SIMD)
