@@ -128,6 +128,37 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command, workload="the 1024^2 
     print(open(out_path).read())
 
 
+def summarize_counters(pmc_dir, out_path, command, steps_per_launch: float = 0.0):
+    """Per-dispatch averages of every counter collected on the tracing
+    kernel, with the L2 hit rate and VALU instructions per tet step."""
+    rows = [r for r in _counter_rows(pmc_dir)
+            if "k_render<" in r["Kernel_Name"] and ", 0, false, false>" in r["Kernel_Name"]]
+    acc, cnt = {}, {}
+    for r in rows:
+        k = r["Counter_Name"]
+        acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        cnt[k] = cnt.get(k, 0) + 1
+    avg = {k: acc[k] / cnt[k] for k in acc}
+    with open(out_path, "w") as f:
+        f.write("# rocprofv3 counters of the tracing kernel k_render<TetMedium32>, per dispatch\n")
+        f.write(f"# command: {command}\n")
+        f.write(f"source_hash = {kernel_source_hash()}\n")
+        m = re.search(r"--launch '(\{[^']*\})'", command)
+        if m:
+            f.write(f"launch = {m.group(1)}\n")
+        f.write(f"dispatches = {max(cnt.values()) if cnt else 0}\n")
+        for k in sorted(avg):
+            f.write(f"{k} = {avg[k]:.6g}\n")
+        hit, miss = avg.get("TCC_HIT_sum"), avg.get("TCC_MISS_sum")
+        if hit is not None and miss is not None and hit + miss > 0:
+            f.write(f"l2_hit_rate = {hit / (hit + miss):.4f}\n")
+        if steps_per_launch and "SQ_INSTS_VALU" in avg:
+            f.write(f"tet_steps_per_launch = {steps_per_launch:.6g}\n")
+            f.write(f"valu_wave_instructions_per_tet_step = {avg['SQ_INSTS_VALU'] / steps_per_launch:.4f}\n")
+            f.write(f"valu_issue_slots_per_tet_step = {64 * avg['SQ_INSTS_VALU'] / steps_per_launch:.2f}\n")
+    print(open(out_path).read())
+
+
 def summarize_trace(trace_dir, out_path, command):
     """Short kernel table from a rocprofv3 --kernel-trace --stats run."""
     import csv
@@ -638,6 +669,8 @@ def main():
                          "same): for runs under rocprofv3, which fails at exit after a cooperative launch")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT"))
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_DIR", "OUT"))
+    ap.add_argument("--steps-per-launch", type=float, default=0.0)
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="", help="workload named in a counter summary")
     args = ap.parse_args()
@@ -646,6 +679,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.command, args.steps_per_launch)
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the method's hot path is "
