@@ -116,7 +116,9 @@ typedef struct {
   int32_t channels;           /* 1: use the grid's extra channels (tet_grid_set_channels): a real collision
                                  in tet c adds beta (1 - a_c) T_c emission, then takes the tet's albedo a_c
                                  and phase parameter g_c in place of the medium's (absent channels: the
-                                 medium's values, no emission).  Single tet-grid renders without a cache. */
+                                 medium's values, no emission).  Tet grids only; with a radiance cache the
+                                 cache at vertex k stands for the vertex's emission too; in batches every
+                                 grid must carry channels. */
   float emission[3];          /* radiance emitted per unit temperature (RGB, >= 0), with channels */
 } tet_render_opts;
 
@@ -247,8 +249,10 @@ int tet_render_noalloc(const tet_grid* grid, const tet_camera* camera, const tet
  * width_i*height_i*3 FP32, as tet_render would write it.  Per-scene
  * images equal tet_render's up to FP32 summation order.  opts (nullable):
  * max_bounces, transmittance, max_steps_per_path, sample_offset,
- * block_size, blocks_per_cu, record_layout and event_wait apply to all
- * scenes; the radiance cache is not available in batches.  1 <= n <= 4096,
+ * block_size, blocks_per_cu, record_layout, event_wait, channels and
+ * emission apply to all scenes (with channels, every grid must carry
+ * some); a grid's density model renders as in tet_render; the radiance
+ * cache is not available in batches.  1 <= n <= 4096,
  * fewer than 2^32 samples in all.  stats (nullable) receives the batch's
  * totals. */
 int tet_render_batch(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,
@@ -259,7 +263,9 @@ int tet_render_batch(int32_t n, const tet_grid* const* grids, const tet_camera* 
 /* The same batch as a reusable frame: tet_batch_create fixes the scenes,
  * allocates the scratch memory and captures the frame's kernels in a HIP
  * graph; tet_batch_render replays it with new seeds (n values).  The grids
- * and output buffers must outlive the handle. */
+ * and output buffers must outlive the handle, and the grids' channels and
+ * density models must not be replaced meanwhile (the frame reads them
+ * where they were at creation). */
 typedef struct tet_batch tet_batch;
 int tet_batch_create(int32_t n, const tet_grid* const* grids, const tet_camera* cameras, const tet_medium* media,
                      const tet_light* lights, const int32_t* spp, const tet_render_opts* opts,
@@ -344,9 +350,10 @@ int tet_grid_export_channels(const tet_grid* grid, float* temperature, float* al
  * the grid then use the model (each tentative collision evaluates the
  * extinction at its point; the analytic light transmittance of model 1
  * integrates it exactly per segment); model 2 needs ratio or delta
- * tracking for the light (transmittance 1 or 2, else TET_ERR_INVALID_ARG),
- * and neither model renders in batches or with a radiance cache
- * (TET_ERR_UNSUPPORTED).  Device memory beyond the grid: copies of its
+ * tracking for the light (transmittance 1 or 2, else TET_ERR_INVALID_ARG).
+ * Both models render in batches and with a radiance cache, whose input
+ * sigma at a vertex is then the model's extinction at the vertex.  Device
+ * memory beyond the grid: copies of its
  * records carrying the model's majorant (48 bytes per tet, plus 32 with
  * compact records), 4 bytes per tet of majorant, and 16 bytes per tet of
  * coefficients (model 1) or the volume (model 2). */
@@ -390,7 +397,8 @@ void tet_grid_free(tet_grid* grid);
  * A learned radiance cache (an addition to the paper's method, after
  * Mueller et al. 2021, "Real-time Neural Radiance Caching for Path
  * Tracing").  A small MLP maps a path vertex -- its position p, the
- * incoming direction d and the extinction sigma of the cell holding it --
+ * incoming direction d and the extinction sigma there (the cell's, or the
+ * grid's density model at the vertex) --
  * to the radiance the rest of the path brings back per unit of throughput
  * reaching the vertex (before the vertex's albedo).  Rendering with a cache
  * (tet_render_opts.nrc) stops every path at real vertex truncate_bounce

@@ -452,9 +452,13 @@ static float shadow(const medium_t* m, int64_t cell, const float x[3], const flo
  *     and stops; there is no light estimate at that vertex (the cache covers
  *     it).
  *   rec != NULL: vertices 1..max_rec are recorded, 11 floats each: the
- *     vertex x (3), the incoming direction d (3), the cell's extinction, the
- *     throughput reaching the vertex, and L gathered before it (3);
- *     *n_rec = number recorded. */
+ *     vertex x (3), the incoming direction d (3), the extinction at the
+ *     vertex, the throughput reaching the vertex, and L gathered before it
+ *     (3); *n_rec = number recorded.
+ * The extinction at a vertex, the cache's input there, is the cell's; on a
+ * grid with a density model, the model's at the vertex.  With channels the
+ * cache at vertex k stands for the vertex's own emission too (records are
+ * taken before it). */
 typedef struct {
   int32_t truncate;
   const double* params;
@@ -535,9 +539,11 @@ static void trace_path(const medium_t* m, const frame32* fr, const omedium* med,
       for (int i = 0; i < 3; i++) x[i] = o[i] + tc * d[i];
       rng.bounce++;
       memset(rng.draws, 0, sizeof(rng.draws));
+      /* s: the extinction at the collision (the tet's, or the density
+       * model's at the point), the cache's input there */
       if (hk && hk->truncate == (int32_t)rng.bounce) {
         float r[3];
-        oracle_nrc_eval_point(hk->params, hk->bf16, hk->sigma_ref, x, d, cell_sigma(m, cell), r);
+        oracle_nrc_eval_point(hk->params, hk->bf16, hk->sigma_ref, x, d, s, r);
         for (int c = 0; c < 3; c++) L[c] = L[c] + beta[c] * r[c];
         return;
       }
@@ -548,7 +554,7 @@ static void trace_path(const medium_t* m, const frame32* fr, const omedium* med,
           q[3 + i] = d[i];
           q[8 + i] = L[i];
         }
-        q[6] = cell_sigma(m, cell);
+        q[6] = s;
         q[7] = beta[0];
         *n_rec = (int32_t)rng.bounce;
       }
@@ -609,19 +615,25 @@ static int check_render_args(const ocam* cam, const omedium* med, const olight* 
   return 0;
 }
 
+/* Channels need a tet grid that carries at least one of them and a finite,
+ * non-negative emission colour.  They combine with the radiance cache: the
+ * cache at vertex k stands for all radiance from k on, the vertex's own
+ * emission included (the record of vertex k is taken before it). */
+static int check_channels(const medium_t* m, const orender_opts* op) {
+  if (!op->channels) return 0;
+  if (m->kind != 0 || (!m->g->ch[0] && !m->g->ch[1] && !m->g->ch[2])) return -1;
+  for (int c = 0; c < 3; c++)
+    if (!(op->emission[c] >= 0.0f) || isinf(op->emission[c])) return -1;
+  return 0;
+}
+
 static int render_common(const medium_t* m, const ocam* cam, const omedium* med, const olight* lt, int32_t spp,
                          uint64_t seed, const orender_opts* op, const int32_t* pixels, int64_t n_pixels,
                          float* out, orender_stats* stats, int32_t threads, const nrc_hook* hk) {
   int rc = check_render_args(cam, med, lt, spp, op, pixels, pixels ? n_pixels : 0, out);
   if (rc) return rc;
-  if (has_model(m)) { /* no radiance cache; voxel lookups have no analytic light transmittance */
-    if (hk || (m->g->model == 2 && op->transmittance == 0)) return -1;
-  }
-  if (op->channels) { /* tet grids that carry channels; not with a radiance cache */
-    if (m->kind != 0 || hk || (!m->g->ch[0] && !m->g->ch[1] && !m->g->ch[2])) return -1;
-    for (int c = 0; c < 3; c++)
-      if (!(op->emission[c] >= 0.0f) || isinf(op->emission[c])) return -1;
-  }
+  if (has_model(m) && m->g->model == 2 && op->transmittance == 0) return -1; /* voxel lookups: no analytic light */
+  if (check_channels(m, op)) return -1;
   frame32 fr;
   make_frame(cam, &fr);
   int64_t np = pixels ? n_pixels : (int64_t)cam->width * cam->height;
@@ -738,11 +750,13 @@ int oracle_nrc_collect(const ogrid* g, const ocam* cam, const omedium* med, cons
                        float* sigma, float* target, int32_t* tag, int64_t* count, int32_t* path_pixel, float* path_L,
                        int32_t threads) {
   if (!g || n_paths < 0 || n_paths > (1 << 26) || max_vertices < 1 || max_vertices > 16 || !pos || !dir || !sigma ||
-      !target || !tag || !count || g->model != 0 || opts->channels)
+      !target || !tag || !count)
     return -1;
   int rc = check_render_args(cam, med, light, 1, opts, NULL, 0, target);
   if (rc) return rc;
   medium_t m = {0, g, NULL, 0, 1.0f};
+  if (check_channels(&m, opts)) return -1;
+  if (g->model == 2 && opts->transmittance == 0) return -1;
   frame32 fr;
   make_frame(cam, &fr);
   int64_t npix = (int64_t)cam->width * cam->height;

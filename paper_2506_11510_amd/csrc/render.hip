@@ -61,6 +61,22 @@ constexpr uint32_t kMiss = 0xFFFFFFFFu;
 // Work items and entry records of all scenes are concatenated; a scene's
 // items start at a multiple of 64, so the 64-item batches waves take never
 // straddle two scenes.
+// Extra per-tet data a scene may carry: channels (null = absent) with the
+// emitted radiance per unit temperature, and the density model inside the
+// tets (0 = constant; 1 linear coefficients; 2 voxel lookup in an n^3
+// volume times a scale).
+struct ExtArgs {
+  const float* ch_t;
+  const float* ch_a;
+  const float* ch_g;
+  float emission[3];
+  int32_t model;
+  const float4* mcoef;
+  const float* mdens;
+  int32_t mn;
+  float mscale;
+};
+
 struct SceneDesc {
   Frame fr;
   float albedo, g;
@@ -79,6 +95,7 @@ struct SceneDesc {
   int64_t n;
   int32_t dmax, kbits;
   float* out;
+  ExtArgs ex;
 };
 
 // Largest k < n with key(k) <= v (key ascending, key(0) = 0).
@@ -131,37 +148,25 @@ struct RenderArgs {
   const SceneDesc* scenes;
   int32_t nscenes;
   uint64_t total_entries;
-  // extra channels per tet (null = absent) and the emitted radiance per
-  // unit temperature
-  const float* ch_t;
-  const float* ch_a;
-  const float* ch_g;
-  float emission[3];
-  // density model inside the tets (0 = constant): 1 linear coefficients,
-  // 2 voxel lookup in an n^3 volume times a scale
-  int32_t model;
-  const float4* mcoef;
-  const float* mdens;
-  int32_t mn;
-  float mscale;
+  ExtArgs ex;  // channels and density model of a single-scene render
 };
 
 // Extinction at o + t d inside tet `cell` under the grid's density model:
 // linear ((c0 + gx x) + gy y) + gz z, or the scale times the voxel
 // floor(x n) (indices clamped); FP32.
-__device__ inline float model_sigma(const RenderArgs& A, uint32_t cell, float3 o, float3 d, float t) {
+__device__ inline float model_sigma(const ExtArgs& X, uint32_t cell, float3 o, float3 d, float t) {
   const float x0 = o.x + t * d.x, x1 = o.y + t * d.y, x2 = o.z + t * d.z;
-  if (A.model == 1) {
-    const float4 c = A.mcoef[cell];
+  if (X.model == 1) {
+    const float4 c = X.mcoef[cell];
     return ((c.x + c.y * x0) + c.z * x1) + c.w * x2;
   }
-  const int32_t n = A.mn;
+  const int32_t n = X.mn;
   const float fn = (float)n;
   int64_t i = (int64_t)floorf(x0 * fn), j = (int64_t)floorf(x1 * fn), k = (int64_t)floorf(x2 * fn);
   i = i < 0 ? 0 : (i >= n ? n - 1 : i);
   j = j < 0 ? 0 : (j >= n ? n - 1 : j);
   k = k < 0 ? 0 : (k >= n ? n - 1 : k);
-  return A.mscale * A.mdens[i + (int64_t)n * (j + (int64_t)n * k)];
+  return X.mscale * X.mdens[i + (int64_t)n * (j + (int64_t)n * k)];
 }
 
 // Pixel of training path j: floor(w npix / 2^24), w = the upper 24 bits of
@@ -622,10 +627,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #define TV_ENV(i) (BATCH ? TV_SC.env[i] : A.env[i])
 #define TV_OUT (BATCH ? TV_SC.out : A.out)
 #define TV_SUN (BATCH ? make_float3(TV_SC.sun[0], TV_SC.sun[1], TV_SC.sun[2]) : sun0)
+#define TV_EX (BATCH ? TV_SC.ex : A.ex)
 
   // real collision at t: start the light ray (right after the walk step, or
   // from the event section for the collisions where a path hands over to the
   // radiance cache)
+  // extinction at the collision o + t d, the cache's input there: the
+  // tet's, or the density model's at the point
+  auto vertex_sigma = [&]() -> float {
+    if constexpr (EXT)
+      if (TV_EX.model) return model_sigma(TV_EX, cell, o, d, t);
+    return lm.sigma_at(cell);
+  };
   auto start_light = [&]() {
     n_real++;
     float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
@@ -633,7 +646,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     if ((NRC == 2 || (NRC == 1 && trainp)) && (int32_t)bounce <= A.rec_vertices) {
       uint32_t j = NRC == 2 ? ent : ent - A.train_ent0;
       float4* q = A.vrec + ((size_t)j * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
-      q[0] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
+      q[0] = make_float4(x.x, x.y, x.z, vertex_sigma());
       q[1] = make_float4(d.x, d.y, d.z, beta);
       q[2] = make_float4(L.x, L.y, L.z, 0.0f);
     }
@@ -643,12 +656,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     // the collision estimator (absorbed part of the collision), then the
     // tet's albedo in place of the medium's
     float alb = TV_ALBEDO;
-    if (EXT && A.ch_a) alb = A.ch_a[cell];
-    if (EXT && A.ch_t) {
-      const float e = (1.0f - alb) * A.ch_t[cell];
-      L.x = L.x + beta * (e * A.emission[0]);
-      L.y = L.y + beta * (e * A.emission[1]);
-      L.z = L.z + beta * (e * A.emission[2]);
+    if (EXT && TV_EX.ch_a) alb = TV_EX.ch_a[cell];
+    if (EXT && TV_EX.ch_t) {
+      const float e = (1.0f - alb) * TV_EX.ch_t[cell];
+      L.x = L.x + beta * (e * TV_EX.emission[0]);
+      L.y = L.y + beta * (e * TV_EX.emission[1]);
+      L.z = L.z + beta * (e * TV_EX.emission[2]);
     }
     beta = beta * alb;
     dsave = d;
@@ -681,7 +694,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
             n_real++;
             bounce++;
             float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-            A.qbuf[2 * (size_t)q] = make_float4(x.x, x.y, x.z, lm.sigma_at(cell));
+            A.qbuf[2 * (size_t)q] = make_float4(x.x, x.y, x.z, vertex_sigma());
             A.qbuf[2 * (size_t)q + 1] = make_float4(d.x, d.y, d.z, beta);
             A.qpix[q] = pix;
             n_query++;
@@ -693,7 +706,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
         float Tr = A.transmittance == 0 ? exp_neg(od) : od;
         float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
-        const float gg = (EXT && A.ch_g) ? A.ch_g[cell_x] : TV_G;  // the collision tet's phase parameter
+        const float gg = (EXT && TV_EX.ch_g) ? TV_EX.ch_g[cell_x] : TV_G;  // the collision tet's phase parameter
         float ph = hg_pdf(gg, mu);
         L.x = L.x + ((beta * ph) * TV_E(0)) * Tr;
         L.y = L.y + ((beta * ph) * TV_E(1)) * Tr;
@@ -871,7 +884,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
               float dtau = sb * (st.te - t);
               while (tau < dtau) {
                 tc = t + tau / sb;
-                if (EXT && A.model) sg = model_sigma(A, cell, o, d, tc);  // extinction at the tentative point
+                if (EXT && TV_EX.model) sg = model_sigma(TV_EX, cell, o, d, tc);  // extinction at the tentative point
                 bool real = true;
                 if (sg < sb) real = uniform01(TV_SEED, pix, (uint32_t)s, bounce, kStreamFlight, jf++) < sg / sb;
                 if (real) {
@@ -901,16 +914,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
         } else {  // light ray: od holds the optical depth (analytic) or the transmittance
           bool done = !st.ok;
           if (st.ok) {
-            if (A.transmittance == 0 && EXT && A.model) {
+            if (A.transmittance == 0 && EXT && TV_EX.model) {
               // linear model: exact integral over the segment (trapezoid)
-              od = od + (0.5f * (model_sigma(A, cell, o, d, t) + model_sigma(A, cell, o, d, st.te))) * (st.te - t);
+              od = od + (0.5f * (model_sigma(TV_EX, cell, o, d, t) + model_sigma(TV_EX, cell, o, d, st.te))) * (st.te - t);
             } else if (A.transmittance == 0) {
               od = od + sg * (st.te - t);
             } else if (sb > 0.0f) {
               float dtau = sb * (st.te - t);
               while (tau < dtau) {
                 t = t + tau / sb;
-                if (EXT && A.model) sg = model_sigma(A, cell, o, d, t);
+                if (EXT && TV_EX.model) sg = model_sigma(TV_EX, cell, o, d, t);
                 if (A.transmittance == 1) {
                   od = od * (1.0f - sg / sb);
                 } else {
@@ -939,6 +952,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       }
     }
   }
+#undef TV_EX
 #undef TV_SUN
 #undef TV_OUT
 #undef TV_ENV
@@ -1003,7 +1017,7 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
                       float* ms_trace, float* ms_cache, bool timed = true) {
   int bs = o.block_size ? o.block_size : 256;
   int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
-  const bool ext = A.model != 0 || A.ch_t || A.ch_a || A.ch_g;
+  const bool ext = A.ex.model != 0 || A.ex.ch_t || A.ex.ch_a || A.ex.ch_g;
   // timed: HIP events around the passes, waited for after each pass;
   // untimed: kernel launches on the stream only
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, t0 = nullptr, t1 = nullptr;
@@ -1056,7 +1070,10 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     grid = std::max<int64_t>(1, std::min(grid, need));
     if (timed) TV_HIP(hipEventRecord(t0, st));
     if (NRC != 0) {
-      hipLaunchKernelGGL((k_render<Med, 5, NRC>), dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+      if constexpr (!std::is_same<Med, VoxelMedium>::value) {
+        if (ext) hipLaunchKernelGGL((k_render<Med, 5, NRC, false, true>), dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+        else hipLaunchKernelGGL((k_render<Med, 5, NRC>), dim3((unsigned)grid), dim3(bs), 0, st, P, med);
+      }
     } else if (ext) {
       if constexpr (!std::is_same<Med, VoxelMedium>::value) {
         switch (o.waves_per_simd) {
@@ -1123,6 +1140,48 @@ static void set_scene(RenderArgs& A, const tet_camera* cam, const tet_medium* me
   }
 }
 
+// Extra channels (temperature, albedo, phase parameter per tet): a tet grid
+// that carries at least one, and a finite emission colour >= 0.  They
+// combine with the radiance cache (the cache at a vertex stands for all the
+// radiance from it on, the vertex's emission included).
+static int check_channels(const tet_render_opts& o, const tet_grid* g, const char* who) {
+  if (!o.channels) return TET_OK;
+  const std::string w(who);
+  if (o.channels != 1) return fail(TET_ERR_INVALID_ARG, w + ": channels must be 0 or 1");
+  if (!g) return fail(TET_ERR_UNSUPPORTED, w + ": channels need a tet grid");
+  if (!g->ch[0] && !g->ch[1] && !g->ch[2]) return fail(TET_ERR_INVALID_ARG, w + ": the grid has no channels");
+  for (int c = 0; c < 3; c++)
+    if (!(o.emission[c] >= 0.0f) || std::isinf(o.emission[c]))
+      return fail(TET_ERR_INVALID_ARG, w + ": emission must be finite and >= 0");
+  return TET_OK;
+}
+
+// The voxel-lookup model has no analytic light transmittance.
+static int check_model(const tet_render_opts& o, const tet_grid* g, const char* who) {
+  if (g && g->model == 2 && o.transmittance == 0)
+    return fail(TET_ERR_INVALID_ARG,
+                std::string(who) + ": the voxel-lookup model needs ratio or delta tracking for the light");
+  return TET_OK;
+}
+
+// The channels (when asked for) and the density model of grid g.
+static void set_ext(ExtArgs& X, const tet_grid* g, const tet_render_opts& o) {
+  memset(&X, 0, sizeof(X));
+  if (o.channels) {
+    X.ch_t = g->ch[0];
+    X.ch_a = g->ch[1];
+    X.ch_g = g->ch[2];
+    for (int c = 0; c < 3; c++) X.emission[c] = o.emission[c];
+  }
+  if (g->model) {
+    X.model = g->model;
+    X.mcoef = g->mcoef;
+    X.mdens = g->mdens;
+    X.mn = g->mn;
+    X.mscale = g->mscale;
+  }
+}
+
 static int render_common(int kind, const tet_grid* g, const tet_density* dens, const tet_camera* cam,
                          const tet_medium* medm, const tet_light* light, int32_t spp, uint64_t seed,
                          const tet_render_opts* opts_in, float* out_rgb, int32_t on_device, hipStream_t st,
@@ -1148,18 +1207,9 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (nrc && !(nrc->opts.sigma_ref > 0.0f))
     return fail(TET_ERR_INVALID_ARG, "render: the radiance cache has no sigma_ref yet (train it or set one)");
   if ((int64_t)o.sample_offset + spp > (1ll << 31)) return fail(TET_ERR_INVALID_ARG, "render: sample range too large");
-  if (o.channels) {
-    if (o.channels != 1) return fail(TET_ERR_INVALID_ARG, "render: channels must be 0 or 1");
-    if (kind != 0 || nrc) return fail(TET_ERR_UNSUPPORTED, "render: channels need a tet grid and no radiance cache");
-    if (!g->ch[0] && !g->ch[1] && !g->ch[2]) return fail(TET_ERR_INVALID_ARG, "render: the grid has no channels");
-    for (int c = 0; c < 3; c++)
-      if (!(o.emission[c] >= 0.0f) || std::isinf(o.emission[c]))
-        return fail(TET_ERR_INVALID_ARG, "render: emission must be finite and >= 0");
-  }
-  const bool model = kind == 0 && g->model != 0;
-  if (model && nrc) return fail(TET_ERR_UNSUPPORTED, "render: density models do not render with a radiance cache");
-  if (model && g->model == 2 && o.transmittance == 0)
-    return fail(TET_ERR_INVALID_ARG, "render: the voxel-lookup model needs ratio or delta tracking for the light");
+  if (int rc = check_channels(o, kind == 0 ? g : nullptr, "render")) return rc;
+  if (int rc = check_model(o, kind == 0 ? g : nullptr, "render")) return rc;
+  const bool model = kind == 0 && g->model != 0;  // walk the records whose majorants bound the model
   if (noalloc && (kind != 0 || nrc || !on_device || stats))
     return fail(TET_ERR_UNSUPPORTED,
                 "tet_render_noalloc: tet grids only, no radiance cache, output on the device, no stats");
@@ -1185,19 +1235,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   RenderArgs A;
   memset(&A, 0, sizeof(A));
   set_scene(A, cam, medm, light);
-  if (o.channels) {
-    A.ch_t = g->ch[0];
-    A.ch_a = g->ch[1];
-    A.ch_g = g->ch[2];
-    for (int c = 0; c < 3; c++) A.emission[c] = o.emission[c];
-  }
-  if (model) {
-    A.model = g->model;
-    A.mcoef = g->mcoef;
-    A.mdens = g->mdens;
-    A.mn = g->mn;
-    A.mscale = g->mscale;
-  }
+  if (kind == 0) set_ext(A.ex, g, o);
   A.spp = spp;
   A.pass_start = o.sample_offset;
   A.per_item = per_item;
@@ -1321,7 +1359,6 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
                          uint64_t frame_seed, const tet_render_opts* opts_in, int32_t n_paths, int32_t kv, float4* vrec,
                          float4* path_l, hipStream_t st, float* ms_out) {
   if (!g) return fail(TET_ERR_INVALID_ARG, "training paths: grid is NULL");
-  if (g->model) return fail(TET_ERR_UNSUPPORTED, "training paths: density models do not train a radiance cache");
   const uint32_t* shapes = shape_table();
   if (!shapes) return fail(TET_ERR_DEVICE, "training paths: shape table");
   if (int rc = check_camera(cam)) return rc;
@@ -1332,10 +1369,13 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
   if (opts_in) o = *opts_in;
   else tet_render_opts_defaults(&o);
   if (int rc = check_render_opts(o)) return rc;
+  if (int rc = check_channels(o, g, "training paths")) return rc;
+  if (int rc = check_model(o, g, "training paths")) return rc;
   if (n_paths < 1 || kv < 1) return fail(TET_ERR_INVALID_ARG, "training paths: bad counts");
   RenderArgs A;
   memset(&A, 0, sizeof(A));
   set_scene(A, cam, medm, light);
+  set_ext(A.ex, g, o);
   A.spp = 1;
   A.per_item = 1;
   A.max_bounces = o.max_bounces;
@@ -1364,11 +1404,13 @@ int trace_training_paths(const tet_grid* g, const tet_camera* cam, const tet_med
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
   float ms = 0.0f, ms_trace = 0.0f, ms_cache = 0.0f;
   int rc;
+  const bool model = g->model != 0;
   if (g->rec32 && o.record_layout != 48) {
-    TetMedium32 m{g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
+    TetMedium32 m{model ? g->mrec32 : g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = run_passes<TetMedium32, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
   } else {
-    TetMedium m{g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
+    if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "training paths: this grid has no compact records");
+    TetMedium m{model ? g->mrec : g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = run_passes<TetMedium, 2>(m, A, o, 1, 0, sc, entries, 1, st, &ms, &ms_trace, &ms_cache);
   }
   if (rc) return rc;
@@ -1447,6 +1489,7 @@ struct BatchState {
   int device = 0;
   int n = 0;
   bool use32 = true;
+  bool ext = false;  // some scene carries channels or a density model
   const uint32_t* shapes = nullptr;
   tet_render_opts o;
   SceneDesc* pinned = nullptr;  // host staging of the scene table (page-locked)
@@ -1478,11 +1521,11 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
   else tet_render_opts_defaults(&o);
   if (int rc = check_render_opts(o)) return rc;
   if (o.nrc) return fail(TET_ERR_UNSUPPORTED, "render batch: no radiance cache in batches");
-  if (o.channels) return fail(TET_ERR_UNSUPPORTED, "render batch: no extra channels in batches");
   bool use32 = o.record_layout != 48;
   for (int i = 0; i < n; i++) {
     if (!grids[i] || !outs[i]) return fail(TET_ERR_INVALID_ARG, "render batch: NULL grid or output");
-    if (grids[i]->model) return fail(TET_ERR_UNSUPPORTED, "render batch: no density models in batches");
+    if (int rc = check_channels(o, grids[i], "render batch")) return rc;
+    if (int rc = check_model(o, grids[i], "render batch")) return rc;
     if (int rc = check_camera(&cams[i])) return rc;
     if (!(media[i].g > -1.0f && media[i].g < 1.0f) || !(media[i].albedo >= 0.0f))
       return fail(TET_ERR_INVALID_ARG, "render batch: medium needs albedo >= 0 and -1 < g < 1");
@@ -1521,7 +1564,10 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
     S.entry0 = entry;
     S.pix0 = px;
     const tet_grid* g = grids[i];
-    S.rec = use32 ? (const void*)g->rec32 : (const void*)g->rec;
+    if (g->model) S.rec = use32 ? (const void*)g->mrec32 : (const void*)g->mrec;
+    else S.rec = use32 ? (const void*)g->rec32 : (const void*)g->rec;
+    set_ext(S.ex, g, o);
+    if (o.channels || g->model) B->ext = true;
     S.keys = g->keys;
     S.kidx = g->kidx;
     S.kbits = g->kbits;
@@ -1577,11 +1623,13 @@ static int batch_enqueue(const BatchState* B, hipStream_t st) {
   if (B->use32) {
     TetMedium32 m{nullptr, nullptr, 0, 0, B->shapes, nullptr, 0};
     hipLaunchKernelGGL(k_raygen_batch<TetMedium32>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
-    hipLaunchKernelGGL((k_render<TetMedium32, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
+    if (B->ext) hipLaunchKernelGGL((k_render<TetMedium32, 5, 0, true, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
+    else hipLaunchKernelGGL((k_render<TetMedium32, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
   } else {
     TetMedium m{nullptr, nullptr, 0, 0, B->shapes, nullptr, 0};
     hipLaunchKernelGGL(k_raygen_batch<TetMedium>, dim3(eblocks), dim3(256), 0, st, A, m, entries);
-    hipLaunchKernelGGL((k_render<TetMedium, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
+    if (B->ext) hipLaunchKernelGGL((k_render<TetMedium, 5, 0, true, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
+    else hipLaunchKernelGGL((k_render<TetMedium, 5, 0, true>), dim3((unsigned)B->grid), dim3(B->bs), 0, st, A, m);
   }
   hipLaunchKernelGGL(k_batch_images, dim3(pblocks), dim3(256), 0, st, (const SceneDesc*)B->table, B->n, B->total_px, 0);
   TV_HIP(hipGetLastError());

@@ -106,8 +106,10 @@ def test_channel_errors(tv):
     assert np.all(g.export_channels()["albedo"] == np.float32(0.5))
     with pytest.raises(tv.TetError):  # negative emission
         tv.render(g, sc["camera"], sc["medium"], sc["light"], 1, 1, dict(r, emission=[1.0, -1.0, 0.0]))
-    with pytest.raises(tv.TetError):  # batches carry no channels
-        tv.render_batch([g], [sc["camera"]], [sc["medium"]], [sc["light"]], [1], [1], r)
+    bare = tv.leb_build(torch.from_numpy(sc["density_fn"]()).cuda(), sc["n"], sc["camera"], build=sc["build"])
+    with pytest.raises(tv.TetError) as e:  # a batch whose grids do not all carry channels
+        tv.render_batch([g, bare], [sc["camera"]] * 2, [sc["medium"]] * 2, [sc["light"]] * 2, [1, 1], [1, 2], r)
+    assert e.value.status == -1
 
 
 @pytest.mark.timeout(900)

@@ -152,9 +152,9 @@ def test_model_errors(tv):
     with pytest.raises(tv.TetError) as e:  # voxel lookups: no analytic light transmittance
         tv.render(g, sc["camera"], sc["medium"], sc["light"], 1, 1, r)
     assert e.value.status == -1
-    with pytest.raises(tv.TetError) as e:
-        tv.render_batch([g], [sc["camera"]], [sc["medium"]], [sc["light"]], [1], [1], dict(r, transmittance=2))
-    assert e.value.status == -6
+    with pytest.raises(tv.TetError) as e:  # in batches too
+        tv.render_batch([g], [sc["camera"]], [sc["medium"]], [sc["light"]], [1], [1], r)
+    assert e.value.status == -1
     g.set_density_model(0)
     with pytest.raises(tv.TetError):
         g.export_density_model()
