@@ -281,12 +281,21 @@ struct TetMedium {
     bool any = false;
     float bnum = 0.0f, bden = 1.0f;
     uint32_t blink = kBoundary;
+    // the four faces' table entries, all read before any is used
+    float tden[4], tdot[4];
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      const uint32_t c = (codes >> (8 * f)) & 0xFFu;
+      tden[f] = tab[c >> 1];
+      tdot[f] = tab[9 + (c >> 1)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int f = 0; f < 4; f++) {
       uint32_t c = (codes >> (8 * f)) & 0xFFu;
       uint32_t sg = c << 31;
-      float den = __uint_as_float(__float_as_uint(tab[c >> 1]) ^ sg);
-      float dot = __uint_as_float(__float_as_uint(tab[9 + (c >> 1)]) ^ sg);
+      float den = __uint_as_float(__float_as_uint(tden[f]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(tdot[f]) ^ sg);
       float num = off[f] - dot;
       bool cand = den > 0.0f;
       bool better = cand && (!any || (double)num * (double)bden < (double)bnum * (double)den);
@@ -331,13 +340,21 @@ struct TetMedium32 {
     const int32_t ioff[4] = {((int32_t)(a.x << 9)) >> 9, ((int32_t)(o1 << 9)) >> 9, ((int32_t)(o2 << 9)) >> 9,
                              ((int32_t)(a.z << 4)) >> 9};
     const uint32_t lw[4] = {b.x, b.y, b.z, b.w};
+    // the four faces' table entries, all read before any is used
+    float tden[4], tdot[4];
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      const float* e = tab + (lw[f] >> 28);
+      tden[f] = e[0];
+      tdot[f] = e[9];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the four reads ahead of their uses
     float bnum, bden;
     uint32_t blink;
     {  // face 0 against the start quotient 1/0: it wins exactly when it is a candidate
-      const float* e = tab + (lw[0] >> 28);
       uint32_t sg = (lw[0] >> 27) << 31;
-      float den = __uint_as_float(__float_as_uint(e[0]) ^ sg);
-      float dot = __uint_as_float(__float_as_uint(e[9]) ^ sg);
+      float den = __uint_as_float(__float_as_uint(tden[0]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(tdot[0]) ^ sg);
       float num = (float)ioff[0] - dot;
       const bool cand = den > 0.0f;
       bnum = cand ? num : 1.0f;
@@ -346,10 +363,9 @@ struct TetMedium32 {
     }
 #pragma unroll
     for (int f = 1; f < 4; f++) {
-      const float* e = tab + (lw[f] >> 28);
       uint32_t sg = (lw[f] >> 27) << 31;
-      float den = __uint_as_float(__float_as_uint(e[0]) ^ sg);
-      float dot = __uint_as_float(__float_as_uint(e[9]) ^ sg);
+      float den = __uint_as_float(__float_as_uint(tden[f]) ^ sg);
+      float dot = __uint_as_float(__float_as_uint(tdot[f]) ^ sg);
       float num = (float)ioff[f] - dot;
       bool better = den > 0.0f && (double)num * (double)bden < (double)bnum * (double)den;
       bnum = better ? num : bnum;
