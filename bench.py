@@ -34,6 +34,7 @@ BYTES_PER_TET_STEP = 32  # algorithmic bytes per walk step (compact tet record)
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 NRC_FLOP_PER_QUERY = 2 * (76 * 64 + 3 * 64 * 64 + 64 * 3)  # multiply-adds of the 76-64-64-64-64-3 network
 TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "render_cloud1024*_traffic.txt")
+PLUME_TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "render_plume1024*_traffic.txt")
 LAUNCH_KEYS = ("waves_per_simd", "event_wait", "batch_items", "block_size", "record_layout", "samples_per_item")
 COPY_BYTES = 1 << 30  # plain device copy used to calibrate the traffic counters
 KERNEL_SOURCES = ["paper_2506_11510_amd/csrc/render.hip", "paper_2506_11510_amd/csrc/common.h"]
@@ -60,13 +61,13 @@ def read_kv(path):
     return out
 
 
-def measured_traffic(launch: dict):
+def measured_traffic(launch: dict, pattern: str = TRAFFIC_GLOB):
     """HBM bytes per tracing-kernel launch from the committed rocprofv3
     counter runs of this launch configuration, or None when none was
     profiled or the kernel source changed since."""
     import glob
     want = {k: int(launch[k]) for k in LAUNCH_KEYS}
-    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+    for path in sorted(glob.glob(pattern)):
         t = read_kv(path)
         if t.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in t:
             continue
@@ -77,6 +78,15 @@ def measured_traffic(launch: dict):
         if {k: got.get(k) for k in LAUNCH_KEYS} == want:
             return float(t["traffic_bytes_per_launch"])
     return None
+
+
+def traffic_fractions(traffic, algorithmic_bytes: float, kernel_ms: float) -> dict:
+    """Counter traffic over the kernel time against the HBM peak, and the
+    share of it the method needs (algorithmic / counted bytes)."""
+    if not traffic:
+        return {"frac_traffic": None, "line_utilisation": None}
+    return {"frac_traffic": round(traffic / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "line_utilisation": round(algorithmic_bytes / traffic, 4)}
 
 
 def _counter_rows(d):
@@ -428,7 +438,11 @@ def host_io_leg(tv, torch, d, sc, steps: int = 3) -> dict:
             "bytes_over_pcie_per_step": int(d.nbytes + img.nbytes)}
 
 
-def plume_leg(tv, torch, host_rounds: bool = False) -> dict:
+PLUME_LAUNCH = {"waves_per_simd": 5, "event_wait": 48, "batch_items": 64, "block_size": 256, "record_layout": 32,
+                "samples_per_item": 1}
+
+
+def plume_leg(tv, torch, host_rounds: bool = False, launch: dict | None = None) -> dict:
     """The production-scale configuration: 1024^3 plume density resident in
     HBM, adaptive LEB build (~86 M tets), 1024^2 renders at 32 and 1024 spp
     with 64 bounces.  Returns the figures and (grid, scene, 1024-spp image)
@@ -436,8 +450,7 @@ def plume_leg(tv, torch, host_rounds: bool = False) -> dict:
     import numpy as np
     import synthetic
     sc = synthetic.scene("plume")
-    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
-                        event_wait=48)
+    sc["render"] = dict(sc["render"], **(launch or PLUME_LAUNCH))
     if host_rounds:
         sc["build"] = dict(sc["build"], host_rounds=1)
     t0 = time.perf_counter()
@@ -461,6 +474,7 @@ def plume_leg(tv, torch, host_rounds: bool = False) -> dict:
     steps32 = float(np.mean([r["tet_steps"] for r in r32]))
     px = cam["width"] * cam["height"]
     achieved = steps32 * BYTES_PER_TET_STEP / (tr32 / 1e3) / 1e9
+    traffic = measured_traffic(sc["render"], PLUME_TRAFFIC_GLOB)
     out = {"workload": "1024^3 curl-advected fBm plume (seed 2, 5% occupancy, sigma_t max 50) -> adaptive LEB grid "
                        "(1 px target, tau 0.2, depth <= 30) -> 1024x1024, 64 bounces, albedo 0.95, HG g 0.6",
            "density_gen_s_host": round(gen_s, 2), "num_tets": builds[-1]["num_tets"],
@@ -469,7 +483,9 @@ def plume_leg(tv, torch, host_rounds: bool = False) -> dict:
            "spp32": {"ms": round(ms32, 3), "trace_ms": round(tr32, 3),
                      "msamples_per_s": round(px * 32 / (ms32 / 1e3) / 1e6, 3),
                      "tet_steps_per_s": round(steps32 / (tr32 / 1e3), 1), "tet_steps": int(steps32),
-                     "roofline_frac_algorithmic": round(achieved / HBM_PEAK_GBS, 4)},
+                     "roofline_frac_algorithmic": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic_bytes_per_launch": traffic,
+                     **traffic_fractions(traffic, steps32 * BYTES_PER_TET_STEP, tr32)},
            "spp1024": {"ms": round(st1024["ms"], 3), "msamples_per_s": round(px * 1024 / (st1024["ms"] / 1e3) / 1e6, 3),
                        "tet_steps": int(st1024["tet_steps"])}}
     return out, (g, sc, ref)
@@ -685,7 +701,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the method's hot path is "
-              "single-GPU here; sharding across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+              "single-GPU here; sharding across GPUs (sample ranges per GPU, one image reduce) is not built.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -695,7 +712,7 @@ def main():
     import paper_2506_11510_amd as tv
 
     if args.plume_only:
-        plume, _ = plume_leg(tv, torch, args.host_rounds)
+        plume, _ = plume_leg(tv, torch, args.host_rounds, json.loads(args.launch) if args.launch else None)
         if args.calibrate_copy:
             calibrate_copy(torch)
         print(json.dumps({"plume": plume}), flush=True)
@@ -790,6 +807,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(sc["render"]),
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP),
+                     **traffic_fractions(measured_traffic(sc["render"]), mean_steps * BYTES_PER_TET_STEP,
+                                         mean_trace_ms),
                      "note": "the cloud grid's compact records (32 B x %d tets = %.0f MB) fit the 256 MB "
                              "Infinity Cache, so this is a cache-resident figure; the plume leg's (records "
                              "streaming from HBM) is plume.spp32.roofline_frac_algorithmic"
@@ -829,8 +848,8 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(torch)
     if not args.no_cpu_baseline:
-        # the host threads this process may use: the GPU machine grants one
-        # GPU's share of its cores (16), whatever os.cpu_count() reports
+        # the host threads this process may use: one GPU's share of the
+        # host's cores (16 per GPU), whatever os.cpu_count() reports
         n_threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         res["cpu_baseline"] = cpu_baseline(sc, d, n_threads)
     print(json.dumps(res), flush=True)

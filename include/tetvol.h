@@ -39,7 +39,7 @@ typedef enum {
   TET_ERR_CAPACITY = -3,      /* grid would exceed max_tets */
   TET_ERR_DEVICE = -4,        /* a HIP call failed */
   TET_ERR_NUMERIC = -5,       /* NaN, infinite or negative density */
-  TET_ERR_UNSUPPORTED = -6,   /* option not supported by this build */
+  TET_ERR_UNSUPPORTED = -6,   /* option or combination not supported */
   TET_ERR_INTERNAL = -7       /* invariant violated (non-conforming mesh) */
 } tet_status;
 
