@@ -488,7 +488,10 @@ int tet_nrc_train_frame(tet_nrc* nrc, const tet_grid* grid, const tet_camera* ca
                         const tet_light* light, uint64_t frame_seed, const tet_render_opts* opts, void* hip_stream,
                         tet_nrc_stats* stats /* nullable */);
 
-/* Frees device memory cached by the library between calls. */
+/* Frees device memory cached by the library between calls: the blocks the
+ * calling thread's calls released and those of threads that have ended
+ * (each thread reuses only the blocks its own calls released, so calls on
+ * different threads and streams never share scratch memory). */
 void tet_release_cache(void);
 
 const char* tet_last_error(void);

@@ -51,10 +51,34 @@ int fail(int status, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------- device memory cache
+// Freed blocks are kept for reuse by the thread that freed them.  A call
+// frees a block while its own kernels may still be queued on its stream;
+// reuse in the same call is ordered on that stream, and by the time the call
+// returns (calls are synchronous) the block is idle.  Another thread's call,
+// on another stream, could otherwise take the block while those kernels
+// still run.  Blocks of threads that have ended are idle and shared.
 namespace {
+using FreeList = std::multimap<std::pair<int, size_t>, void*>;  // (device, bytes) -> block
 std::mutex g_mu;
-std::multimap<std::pair<int, size_t>, void*> g_free;  // (device, bytes) -> block
-std::unordered_map<void*, std::pair<int, size_t>> g_size;
+FreeList g_idle;                                           // blocks of ended threads
+std::unordered_map<void*, std::pair<int, size_t>> g_size;  // every block the cache made
+
+struct ThreadBlocks {
+  FreeList free;
+  ~ThreadBlocks() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_idle.insert(free.begin(), free.end());
+  }
+};
+thread_local ThreadBlocks t_blocks;
+
+void* take(FreeList& fl, int dev, size_t bytes) {
+  auto it = fl.lower_bound({dev, bytes});
+  if (it == fl.end() || it->first.first != dev || it->first.second > 2 * bytes) return nullptr;
+  void* p = it->second;
+  fl.erase(it);
+  return p;
+}
 }  // namespace
 
 void* dev_alloc(size_t bytes) {
@@ -62,14 +86,10 @@ void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (void* p = take(t_blocks.free, dev, bytes)) return p;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_free.lower_bound({dev, bytes});
-    if (it != g_free.end() && it->first.first == dev && it->first.second <= 2 * bytes) {
-      void* p = it->second;
-      g_free.erase(it);
-      return p;
-    }
+    if (void* p = take(g_idle, dev, bytes)) return p;
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -87,10 +107,14 @@ void* dev_alloc(size_t bytes) {
 
 void dev_free(void* p) {
   if (!p) return;
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_size.find(p);
-  if (it == g_size.end()) return;
-  g_free.insert({it->second, p});
+  std::pair<int, size_t> key;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_size.find(p);
+    if (it == g_size.end()) return;
+    key = it->second;
+  }
+  t_blocks.free.insert({key, p});
 }
 
 // ---------------------------------------------------------------- cameras
@@ -434,11 +458,13 @@ void tet_release_cache(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;
   (void)hipGetDevice(&cur);
-  for (auto it = g_free.begin(); it != g_free.end();) {
-    (void)hipSetDevice(it->first.first);
-    (void)hipFree(it->second);
-    g_size.erase(it->second);
-    it = g_free.erase(it);
+  for (FreeList* fl : {&t_blocks.free, &g_idle}) {
+    for (auto it = fl->begin(); it != fl->end();) {
+      (void)hipSetDevice(it->first.first);
+      (void)hipFree(it->second);
+      g_size.erase(it->second);
+      it = fl->erase(it);
+    }
   }
   (void)hipSetDevice(cur);
 }
