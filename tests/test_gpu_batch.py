@@ -2,8 +2,8 @@
 the same batch replayed as a captured HIP graph frame.  A scene's samples
 follow the same paths as in a single render (same Philox streams), so the
 images differ from single renders only by the order in which FP32 sample
-values are summed per pixel: relative 1e-5 at these sample counts.  Two
-scenes are also checked against the oracle at the image bar."""
+values are summed per pixel: relative 1e-5 at these sample counts.  Every
+scene is also checked against the oracle at the image bar."""
 import sys
 
 import numpy as np
@@ -84,7 +84,7 @@ def test_batch_matches_single_renders(tv, scenes):
     assert st["tet_steps"] == total  # the same paths, step for step
 
 
-@pytest.mark.parametrize("i", [1, 4])
+@pytest.mark.parametrize("i", range(6))
 def test_batch_matches_oracle(tv, scenes, i):
     say(f"case batch vs oracle, scene {i}")
     S = scenes
