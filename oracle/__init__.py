@@ -198,7 +198,7 @@ def make_build_opts(b: dict) -> OBuildOpts:
 
 def make_render_opts(r: dict) -> ORenderOpts:
     o = ORenderOpts(int(r.get("max_bounces", 8)), int(r.get("transmittance", 0)),
-                    int(r.get("max_steps_per_path", 1 << 20)), int(r.get("sample_offset", 0)),
+                    int(r.get("max_steps_per_path", (1 << 31) - 1)), int(r.get("sample_offset", 0)),
                     int(r.get("channels", 0)))
     o.emission[:] = [float(x) for x in r.get("emission", (0.0, 0.0, 0.0))]
     return o

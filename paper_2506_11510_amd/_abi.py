@@ -72,7 +72,8 @@ class TetRenderStats(ctypes.Structure):
     _fields_ = [("tet_steps", ctypes.c_int64), ("null_collisions", ctypes.c_int64),
                 ("real_collisions", ctypes.c_int64), ("escapes", ctypes.c_int64), ("truncated", ctypes.c_int64),
                 ("ms", ctypes.c_double), ("trace_ms", ctypes.c_double), ("cache_ms", ctypes.c_double),
-                ("cache_queries", ctypes.c_int64), ("cache_records", ctypes.c_int64), ("cache_loss", ctypes.c_double)]
+                ("cache_queries", ctypes.c_int64), ("cache_records", ctypes.c_int64), ("cache_loss", ctypes.c_double),
+                ("light_rays_queued", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -351,7 +351,7 @@ void tet_render_opts_defaults(tet_render_opts* o) {
   memset(o, 0, sizeof(*o));
   o->max_bounces = 32;
   o->transmittance = 0;
-  o->max_steps_per_path = 1 << 20;
+  o->max_steps_per_path = 0x7FFFFFFF;
 }
 
 int leb_build(const tet_density* density, const tet_camera* camera, float target_cell_px, const tet_build_opts* opts,

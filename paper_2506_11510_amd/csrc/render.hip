@@ -43,6 +43,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "nrc.h"
 
 namespace tv {
@@ -110,6 +112,16 @@ __device__ inline int scene_search(int n, uint64_t v, F key) {
   return lo;
 }
 
+// A light ray whose walk is deferred: its origin (the real collision), the
+// collision's tet, the light estimate's weight per channel (throughput after
+// the albedo x phase function x irradiance) and the pixel it adds to.
+struct alignas(16) LightRec {
+  float x, y, z;
+  uint32_t cell;
+  float w0, w1, w2;
+  uint32_t pix;
+};
+
 struct RenderArgs {
   Frame fr;
   float albedo, g;
@@ -149,6 +161,14 @@ struct RenderArgs {
   int32_t nscenes;
   uint64_t total_entries;
   ExtArgs ex;  // channels and density model of a single-scene render
+  // deferred light rays (defer != 0): block b of the tracing kernel queues
+  // its light rays at lq + b * lq_region (lq_count[b] of them), walked after
+  // the pass in the order of their start tets
+  LightRec* lq;
+  uint32_t* lq_count;
+  uint32_t lq_cap;
+  uint32_t lq_region;
+  int32_t defer;
 };
 
 // Extinction at o + t d inside tet `cell` under the grid's density model:
@@ -620,6 +640,7 @@ __device__ inline void set_segment(float* tab, float3 o, float3 d, float oscale)
 template <class Med, int W, int NRC, bool BATCH = false, bool EXT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void k_render(RenderArgs A, Med med) {
   __shared__ float s_tab[256 * kTabStride];
+  __shared__ uint32_t s_lq;  // light rays this block queued
   float* tab = s_tab + threadIdx.x * kTabStride;
   const int lane = __lane_id();
   int mode = M_FETCH;
@@ -635,6 +656,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   uint32_t sc = 0, bsc = 0;  // lane's scene; wave-uniform scene of the current batch
   bool trainp = false;       // cache mode 1: the lane's path is a training path
   Med lm = med;              // the lane's medium (its scene's records)
+  // plain single-scene walks on tet grids may queue their light rays
+  constexpr bool DEFER = NRC == 0 && !EXT && !BATCH && !std::is_same<Med, VoxelMedium>::value;
+  if constexpr (DEFER) {
+    if (threadIdx.x == 0) s_lq = 0;
+    __syncthreads();
+  }
 #define TV_SC A.scenes[sc]
 #define TV_SEED (BATCH ? TV_SC.seed : ((NRC == 1 && trainp) ? A.train_seed : A.seed))
 #define TV_ALBEDO (BATCH ? TV_SC.albedo : A.albedo)
@@ -659,6 +686,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     n_real++;
     float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
     bounce++;
+    if constexpr (DEFER) {
+      if (A.defer) {  // queue the light ray (weight now, walk later); the path goes on to its scatter
+        const unsigned long long act = __ballot(1);
+        const int lead = __builtin_ctzll(act);
+        uint32_t base = 0;
+        if (lane == lead) base = atomicAdd(&s_lq, (uint32_t)__popcll(act));  // the block's own count, in LDS
+        base = __shfl(base, lead);
+        const uint32_t q = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+        if (q < A.lq_region) {  // a full region leaves the walk to the lane
+          beta = beta * TV_ALBEDO;
+          const float mu = (d.x * sun0.x + d.y * sun0.y) + d.z * sun0.z;
+          const float bp = beta * hg_pdf(TV_G, mu);
+          LightRec r;
+          r.x = x.x;
+          r.y = x.y;
+          r.z = x.z;
+          r.cell = cell;
+          r.w0 = bp * A.E[0];
+          r.w1 = bp * A.E[1];
+          r.w2 = bp * A.E[2];
+          r.pix = pix;
+          A.lq[(size_t)blockIdx.x * A.lq_region + q] = r;
+          jf = 0;
+          jn = 0;
+          dsave = d;
+          o = x;
+          t = 0.0f;
+          cell_x = cell;
+          od = -1.0f;  // no light term at the scatter
+          mode = M_SCATTER;
+          return;
+        }
+      }
+    }
     if ((NRC == 2 || (NRC == 1 && trainp)) && (int32_t)bounce <= A.rec_vertices) {
       uint32_t j = NRC == 2 ? ent : ent - A.train_ent0;
       float4* q = A.vrec + ((size_t)j * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
@@ -720,13 +781,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       }
       if (mode == M_COLLIDE) start_light();
       if (mode == M_SCATTER) {  // light ray done: light estimate, then phase sampling
-        float Tr = A.transmittance == 0 ? exp_neg(od) : od;
-        float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
         const float gg = (EXT && TV_EX.ch_g) ? TV_EX.ch_g[cell_x] : TV_G;  // the collision tet's phase parameter
-        float ph = hg_pdf(gg, mu);
-        L.x = L.x + ((beta * ph) * TV_E(0)) * Tr;
-        L.y = L.y + ((beta * ph) * TV_E(1)) * Tr;
-        L.z = L.z + ((beta * ph) * TV_E(2)) * Tr;
+        if (!DEFER || od >= 0.0f) {  // (od < 0: the light ray was queued)
+          float Tr = A.transmittance == 0 ? exp_neg(od) : od;
+          float mu = (dsave.x * TV_SUN.x + dsave.y * TV_SUN.y) + dsave.z * TV_SUN.z;
+          float ph = hg_pdf(gg, mu);
+          L.x = L.x + ((beta * ph) * TV_E(0)) * Tr;
+          L.y = L.y + ((beta * ph) * TV_E(1)) * Tr;
+          L.z = L.z + ((beta * ph) * TV_E(2)) * Tr;
+        }
         if ((int32_t)bounce >= A.max_bounces) {
           mode = M_FINISH;
         } else {
@@ -977,6 +1040,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #undef TV_ALBEDO
 #undef TV_SEED
 #undef TV_SC
+  if constexpr (DEFER) {
+    if (A.defer) {
+      __syncthreads();
+      if (threadIdx.x == 0) A.lq_count[blockIdx.x] = min(s_lq, A.lq_region);
+    }
+  }
   // ---- counters: wave reductions, one atomic per wave and counter
   unsigned long long v[6] = {n_steps, n_null, n_real, n_esc, n_trunc, n_query};
 #pragma unroll
@@ -986,6 +1055,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane == 0 && x) atomicAdd(A.stats + q, x);
   }
+}
+
+// ---------------------------------------------------------------- deferred light rays
+// Offsets of the tracing blocks' light rays in one list (exclusive sum of
+// their counts, in order; off[nb] = the total).
+__global__ void k_light_offsets(const uint32_t* __restrict__ cnt, int nb, uint32_t* __restrict__ off) {
+  if (threadIdx.x != 0) return;
+  uint32_t s = 0;
+  for (int b = 0; b < nb; b++) {
+    off[b] = s;
+    s += cnt[b];
+  }
+  off[nb] = s;
+}
+
+// Keys (start tets) and queue positions of the light rays of tracing block
+// blockIdx.x, listed from its offset, for the sort.
+__global__ void k_light_keys(const LightRec* __restrict__ lq, uint32_t region, const uint32_t* __restrict__ cnt,
+                             const uint32_t* __restrict__ off, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ idx) {
+  const uint32_t b = blockIdx.x, n = cnt[b], o = off[b];
+  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const uint32_t q = b * region + j;
+    keys[o + j] = lq[q].cell;
+    idx[o + j] = q;
+  }
+}
+
+// The queued light rays in the order of their start tets: neighbouring lanes
+// start in neighbouring tets and walk the same direction, so they read the
+// same records.  Each walks to the grid boundary summing the optical depth
+// (analytic transmittance, as the tracer's own light walk), then adds its
+// weight times e^-depth to its pixel.  A straight walk meets a tet at most
+// once, so the tet count bounds it.
+template <class Med>
+__global__ __launch_bounds__(256) void k_light(RenderArgs A, Med med, const LightRec* __restrict__ lq,
+                                               const uint32_t* __restrict__ order, uint32_t n) {
+  __shared__ float s_tab[256 * kTabStride];
+  float* tab = s_tab + threadIdx.x * kTabStride;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t steps = 0;
+  if (i < n) {
+    const LightRec r = lq[order[i]];
+    const float3 o = make_float3(r.x, r.y, r.z);
+    const float3 d = make_float3(A.sun[0], A.sun[1], A.sun[2]);
+    set_segment(tab, o, d, Med::kOriginScale);
+    uint32_t cell = r.cell;
+    float t = 0.0f, od = 0.0f;
+    for (;;) {
+      const Step st = med.step(cell, o, d, tab, t);
+      steps++;
+      if (!st.ok) break;
+      od = od + st.sigma * (st.te - t);
+      t = st.te;
+      if (st.next < 0 || (int64_t)steps > med.n) break;
+      cell = (uint32_t)st.next;
+    }
+    const float Tr = exp_neg(od);
+    float* px = A.out + 3 * (size_t)r.pix;
+    atomicAdd(px, r.w0 * Tr);
+    atomicAdd(px + 1, r.w1 * Tr);
+    atomicAdd(px + 2, r.w2 * Tr);
+  }
+  unsigned long long x = steps;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  if (__lane_id() == 0 && x) atomicAdd(A.stats + 0, x);
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
@@ -1026,11 +1162,45 @@ static int cu_count() {
 }
 
 constexpr int64_t kMaxEntriesPerPass = 1ll << 25;  // 1 GiB of entry records
+constexpr int kMaxTraceBlocks = 8192;               // blocks of one tracing launch with a light-ray queue
+
+// Sort buffers of the deferred light rays (keys and positions, both ways)
+// and the sort's own scratch.
+struct LightSort {
+  uint32_t* keys[2];
+  uint32_t* idx[2];
+  void* temp;
+  size_t temp_bytes;
+  unsigned end_bit;  // start tets fit in this many bits
+  int64_t queued;    // light rays walked from the queue so far
+};
+
+// The pass's queued light rays: their count, the sort by start tet, the walks.
+template <class Med>
+static int walk_light_queue(const Med& med, const RenderArgs& P, int nblocks, LightSort& ls, hipStream_t st) {
+  uint32_t* off = P.lq_count + kMaxTraceBlocks;
+  hipLaunchKernelGGL(k_light_offsets, dim3(1), dim3(64), 0, st, (const uint32_t*)P.lq_count, nblocks, off);
+  uint32_t n = 0;
+  TV_HIP(hipMemcpyAsync(&n, off + nblocks, 4, hipMemcpyDeviceToHost, st));
+  TV_HIP(hipStreamSynchronize(st));
+  ls.queued += n;
+  if (!n) return TET_OK;
+  hipLaunchKernelGGL(k_light_keys, dim3((unsigned)nblocks), dim3(256), 0, st, (const LightRec*)P.lq, P.lq_region,
+                     (const uint32_t*)P.lq_count, (const uint32_t*)off, ls.keys[0], ls.idx[0]);
+  size_t tb = ls.temp_bytes;
+  if (rocprim::radix_sort_pairs(ls.temp, tb, ls.keys[0], ls.keys[1], ls.idx[0], ls.idx[1], n, 0u, ls.end_bit, st) !=
+      hipSuccess)
+    return fail(TET_ERR_DEVICE, "render: sort of the light rays");
+  hipLaunchKernelGGL(k_light<Med>, dim3((n + 255) / 256), dim3(256), 0, st, P, med, (const LightRec*)P.lq,
+                     (const uint32_t*)ls.idx[1], n);
+  TV_HIP(hipGetLastError());
+  return TET_OK;
+}
 
 template <class Med, int NRC>
 static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, int32_t spp, int64_t npix,
                       char* sc, RayEntry* entries, int64_t pass_cap, hipStream_t st, float* ms_total,
-                      float* ms_trace, float* ms_cache, bool timed = true) {
+                      float* ms_trace, float* ms_cache, bool timed = true, LightSort* ls = nullptr) {
   int bs = o.block_size ? o.block_size : 256;
   int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
   const bool ext = A.ex.model != 0 || A.ex.ch_t || A.ex.ch_a || A.ex.ch_g;
@@ -1084,6 +1254,10 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
     int64_t grid = (int64_t)cu_count() * bpc;
     int64_t need = ((int64_t)P.items + bs - 1) / bs;
     grid = std::max<int64_t>(1, std::min(grid, need));
+    if (A.defer) {  // one queue region per block
+      grid = std::min<int64_t>(grid, kMaxTraceBlocks);
+      P.lq_region = (uint32_t)(A.lq_cap / (uint64_t)grid);
+    }
     if (timed) TV_HIP(hipEventRecord(t0, st));
     if (NRC != 0) {
       if constexpr (!std::is_same<Med, VoxelMedium>::value) {
@@ -1108,6 +1282,10 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
       }
     }
     TV_HIP(hipGetLastError());
+    if constexpr (NRC == 0 && !std::is_same<Med, VoxelMedium>::value) {
+      if (A.defer)  // the pass's queued light rays, part of the tracing time
+        if (int rc = walk_light_queue(med, P, (int)grid, *ls, st)) return rc;
+    }
     if (timed) TV_HIP(hipEventRecord(t1, st));
     if (NRC == 1)  // the pass's cache queries, added to their pixels
       if (int rc = nrc_query_pass(A.nrc, A.qbuf, A.qpix, A.qcount, A.out, (int64_t)ne, st)) return rc;
@@ -1263,7 +1441,16 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.tiles_x = tiles_x;
   A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
   A.event_wait = o.event_wait ? o.event_wait : 48;
-  A.accumulate = (pass_cap < spp) || (per_item < pass_cap) || nrc != nullptr;
+  // Light rays are queued and walked after each pass, sorted by start tet,
+  // for plain tet grids with analytic light transmittance when the step
+  // guard is at its largest value (2^31 - 1: each light walk then runs on its
+  // own, bounded by the tet count, while the guard would count all of a
+  // path's walks together; the estimate is the same unless a path takes
+  // more than 2^31 - 1 steps).  Their terms are added to the pixels apart
+  // from the rest of their samples.
+  const bool defer = kind == 0 && !model && !o.channels && !nrc && !noalloc && o.transmittance == 0 &&
+                     o.max_steps_per_path >= 0x7FFFFFFF;
+  A.accumulate = (pass_cap < spp) || (per_item < pass_cap) || nrc != nullptr || defer;
   if (nrc) {
     A.nrc = nrc;
     A.truncate = nrc->opts.truncate_bounce;
@@ -1301,6 +1488,37 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   }
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (uint32_t*)sc, 64);
 
+  // the light-ray queue of a pass (at most 4 light rays per sample, 2^26 in
+  // all; a full queue leaves the rest to the tracing lanes) and its sort
+  LightSort ls;
+  memset(&ls, 0, sizeof(ls));
+  struct FreeQ {
+    void* p;
+    ~FreeQ() { if (p) dev_free(p); }
+  } frq_{nullptr};
+  if (defer) {
+    const uint32_t cap = (uint32_t)std::min<int64_t>(1ll << 26, std::max<int64_t>(1024, slots * pass_cap * 4));
+    while (ls.end_bit < 32 && (int64_t)(1ull << ls.end_bit) < g->n) ls.end_bit++;
+    if (rocprim::radix_sort_pairs(nullptr, ls.temp_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                  (uint32_t*)nullptr, cap, 0u, ls.end_bit, st) != hipSuccess)
+      return fail(TET_ERR_DEVICE, "render: light-ray sort size");
+    const size_t head = (size_t)(2 * kMaxTraceBlocks + 64) * 4;  // per-block counts, then their offsets
+    const size_t qb = head + (size_t)cap * sizeof(LightRec) + 4 * (size_t)cap * 4 + ((ls.temp_bytes + 255) & ~size_t(255));
+    char* q = (char*)dev_alloc(qb);
+    if (!q) return fail(TET_ERR_OUT_OF_MEMORY, "render: light-ray queue");
+    frq_.p = q;
+    A.defer = 1;
+    A.lq_count = (uint32_t*)q;
+    A.lq_cap = cap;
+    A.lq = (LightRec*)(q + head);
+    uint32_t* k = (uint32_t*)(q + head + (size_t)cap * sizeof(LightRec));
+    ls.keys[0] = k;
+    ls.keys[1] = k + cap;
+    ls.idx[0] = k + 2 * (size_t)cap;
+    ls.idx[1] = k + 3 * (size_t)cap;
+    ls.temp = k + 4 * (size_t)cap;
+  }
+
   if (nrc) {
     char* qb = sc + 256 + ent_bytes + (on_device ? 0 : img_bytes) + vrec_bytes + pl_bytes;
     A.qbuf = (float4*)qb;
@@ -1314,14 +1532,14 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
                                           !noalloc)
              : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
-                                          !noalloc);
+                                          !noalloc, &ls);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
     TetMedium m{model ? g->mrec : g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
                                         !noalloc)
              : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
-                                        !noalloc);
+                                        !noalloc, &ls);
   } else {
     VoxelMedium m{dens->data, dens->n, dens->density_scale};
     rc = run_passes<VoxelMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
@@ -1367,6 +1585,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
     stats->cache_queries = (int64_t)hs[5];
     stats->cache_records = records;
     stats->cache_loss = loss;
+    stats->light_rays_queued = ls.queued;
   }
   return TET_OK;
 }

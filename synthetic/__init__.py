@@ -139,7 +139,7 @@ def scene(name: str, **over) -> dict:
                  medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
                  build=dict(want_mode=1, uniform_depth=9, max_depth=9, majorant_mode=0, variation_tau=0.0,
                             target_px=1.0, density_scale=1.0, max_tets=1 << 20),
-                 render=dict(spp=16, max_bounces=8, transmittance=0, max_steps_per_path=1 << 20))
+                 render=dict(spp=16, max_bounces=8, transmittance=0, max_steps_per_path=(1 << 31) - 1))
     elif name == "cloud":
         s = dict(density_fn=lambda: cloud(1, 256), n=256,
                  camera=dict(pos=[0.5, 0.45, -0.9], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=45.0,
@@ -147,7 +147,7 @@ def scene(name: str, **over) -> dict:
                  medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
                  build=dict(want_mode=0, uniform_depth=0, max_depth=24, majorant_mode=0, variation_tau=0.2,
                             target_px=1.0, density_scale=1.0, max_tets=1 << 26),
-                 render=dict(spp=32, max_bounces=32, transmittance=0, max_steps_per_path=1 << 20))
+                 render=dict(spp=32, max_bounces=32, transmittance=0, max_steps_per_path=(1 << 31) - 1))
     elif name == "plume":
         s = dict(density_fn=lambda: plume(2, 1024), n=1024,
                  camera=dict(pos=[0.5, 0.45, -0.9], look_at=[0.5, 0.5, 0.5], up=[0, 1, 0], fov_y_deg=45.0,
@@ -155,7 +155,7 @@ def scene(name: str, **over) -> dict:
                  medium=dict(albedo=0.95, g=0.6), light=dict(LIGHT_DEFAULT),
                  build=dict(want_mode=0, uniform_depth=0, max_depth=30, majorant_mode=0, variation_tau=0.2,
                             target_px=1.0, density_scale=1.0, max_tets=1 << 27),
-                 render=dict(spp=32, max_bounces=64, transmittance=0, max_steps_per_path=1 << 20))
+                 render=dict(spp=32, max_bounces=64, transmittance=0, max_steps_per_path=(1 << 31) - 1))
     elif name == "plume_small":
         s = scene("plume")
         s["density_fn"] = lambda: plume(2, 256)
@@ -167,7 +167,7 @@ def scene(name: str, **over) -> dict:
                  medium=dict(albedo=0.8, g=-0.2), light=dict(LIGHT_DEFAULT),
                  build=dict(want_mode=0, uniform_depth=0, max_depth=15, majorant_mode=1, variation_tau=0.3,
                             target_px=2.0, density_scale=1.5, max_tets=1 << 22),
-                 render=dict(spp=8, max_bounces=6, transmittance=0, max_steps_per_path=1 << 20))
+                 render=dict(spp=8, max_bounces=6, transmittance=0, max_steps_per_path=(1 << 31) - 1))
     else:
         raise KeyError(name)
     for k, v in over.items():
@@ -222,5 +222,5 @@ def scene_batch(count: int = 64, first_seed: int = 100) -> list:
                          target_px=1.0, density_scale=1.0, max_tets=1 << 24)
         out.append(dict(density_fn=fn, n=n, camera=cam, medium=dict(albedo=0.9, g=0.3), light=dict(LIGHT_DEFAULT),
                         build=build, render=dict(spp=spp, max_bounces=16, transmittance=0,
-                                                 max_steps_per_path=1 << 20), seed=seed))
+                                                 max_steps_per_path=(1 << 31) - 1), seed=seed))
     return out

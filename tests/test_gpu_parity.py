@@ -146,13 +146,16 @@ def render_both(tv, g, o, sc, cam, spp, seed, ropts):
     return img.cpu().numpy(), st, ref, rst
 
 
-@pytest.mark.parametrize("layout,waves", [(32, 8), (48, 8), (32, 5), (48, 4)])
-def test_render_tiny_parity(tv, tiny_density, layout, waves):
-    say(f"case render tiny 64x64 16spp, {layout}-byte records, {waves} waves")
+QUEUED, OWN = (1 << 31) - 1, 1 << 20  # step guards: light rays queued and sorted / walked by their lanes
+
+
+@pytest.mark.parametrize("layout,waves,guard", [(32, 8, QUEUED), (48, 8, OWN), (32, 5, OWN), (48, 4, QUEUED)])
+def test_render_tiny_parity(tv, tiny_density, layout, waves, guard):
+    say(f"case render tiny 64x64 16spp, {layout}-byte records, {waves} waves, step guard {guard}")
     sc = TINY
     g = gpu_build(tv, tiny_density, 64, sc["camera"], sc["build"])
     o = oracle.leb_build(tiny_density, 64, sc["camera"], sc["build"])
-    r = dict(sc["render"], record_layout=layout, waves_per_simd=waves)
+    r = dict(sc["render"], record_layout=layout, waves_per_simd=waves, max_steps_per_path=guard)
     img, st, ref, rst = render_both(tv, g, o, sc, sc["camera"], 16, 1234, r)
     assert_image_parity(img, ref, "tiny")
     assert st["real_collisions"] > 0 and st["escapes"] > 0
@@ -175,6 +178,42 @@ def test_render_modes_parity(tv, mode, per_item):
     assert_image_parity(img, ref, f"mode {mode}")
     if mode == 0:
         assert st["null_collisions"] > 0
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_queued_light_rays_equal_lane_walks(tv, dense):
+    """Light rays queued and walked after the pass in the order of their
+    start tets give the paths, steps and collisions of the lanes' own light
+    walks, and the image up to the order of FP32 sums per pixel (relative
+    1e-5); both against the oracle.  The dense case (thick, bright medium,
+    many bounces) has more light rays than the queue holds: the rest are
+    walked by their lanes."""
+    sc = synthetic.scene("blobs_adaptive")
+    d = sc["density_fn"]() * (30.0 if dense else 1.0)
+    med = dict(albedo=0.99, g=0.5) if dense else sc["medium"]
+    say(f"case queued light rays, dense {dense}")
+    g = gpu_build(tv, d, 32, sc["camera"], sc["build"])
+    o = oracle.leb_build(d, 32, sc["camera"], sc["build"])
+    cam = dict(sc["camera"], width=48, height=40)
+    base = dict(sc["render"], max_bounces=64 if dense else 8)
+    out = {}
+    for guard in (QUEUED, OWN):
+        img, st = tv.render(g, cam, med, sc["light"], 8, 31, dict(base, max_steps_per_path=guard))
+        out[guard] = (img.cpu().numpy().astype(np.float64), st)
+    (a, sa), (b, sb) = out[QUEUED], out[OWN]
+    say(f"  queued {sa['light_rays_queued']} of {sa['real_collisions']} light rays")
+    for k in ("tet_steps", "real_collisions", "null_collisions", "escapes", "truncated"):
+        assert sa[k] == sb[k], k
+    assert sb["light_rays_queued"] == 0 and sa["light_rays_queued"] > 0
+    if dense:
+        assert sa["light_rays_queued"] < sa["real_collisions"]
+    else:
+        assert sa["light_rays_queued"] == sa["real_collisions"]
+    floor = 1e-4 * np.abs(b).mean()
+    assert (np.abs(a - b) / np.maximum(np.abs(b), floor)).max() <= 1e-5
+    ref, rst = o.render(cam, med, sc["light"], 8, 31, dict(base, max_steps_per_path=QUEUED), threads=8)
+    assert_image_parity(a.reshape(-1, 3), ref, f"queued light rays, dense {dense}")
+    assert abs(sa["tet_steps"] - rst["tet_steps"]) <= 1e-4 * rst["tet_steps"]
 
 
 def test_render_ragged_sizes_and_offsets(tv, tiny_density):
