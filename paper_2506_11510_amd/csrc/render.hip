@@ -657,7 +657,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   bool trainp = false;       // cache mode 1: the lane's path is a training path
   Med lm = med;              // the lane's medium (its scene's records)
   // plain single-scene walks on tet grids may queue their light rays
-  constexpr bool DEFER = NRC == 0 && !EXT && !BATCH && !std::is_same<Med, VoxelMedium>::value;
+  constexpr bool DEFER = NRC != 2 && !BATCH && !std::is_same<Med, VoxelMedium>::value;
   if constexpr (DEFER) {
     if (threadIdx.x == 0) s_lq = 0;
     __syncthreads();
@@ -686,40 +686,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     n_real++;
     float3 x = make_float3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
     bounce++;
-    if constexpr (DEFER) {
-      if (A.defer) {  // queue the light ray (weight now, walk later); the path goes on to its scatter
-        const unsigned long long act = __ballot(1);
-        const int lead = __builtin_ctzll(act);
-        uint32_t base = 0;
-        if (lane == lead) base = atomicAdd(&s_lq, (uint32_t)__popcll(act));  // the block's own count, in LDS
-        base = __shfl(base, lead);
-        const uint32_t q = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
-        if (q < A.lq_region) {  // a full region leaves the walk to the lane
-          beta = beta * TV_ALBEDO;
-          const float mu = (d.x * sun0.x + d.y * sun0.y) + d.z * sun0.z;
-          const float bp = beta * hg_pdf(TV_G, mu);
-          LightRec r;
-          r.x = x.x;
-          r.y = x.y;
-          r.z = x.z;
-          r.cell = cell;
-          r.w0 = bp * A.E[0];
-          r.w1 = bp * A.E[1];
-          r.w2 = bp * A.E[2];
-          r.pix = pix;
-          A.lq[(size_t)blockIdx.x * A.lq_region + q] = r;
-          jf = 0;
-          jn = 0;
-          dsave = d;
-          o = x;
-          t = 0.0f;
-          cell_x = cell;
-          od = -1.0f;  // no light term at the scatter
-          mode = M_SCATTER;
-          return;
-        }
-      }
-    }
     if ((NRC == 2 || (NRC == 1 && trainp)) && (int32_t)bounce <= A.rec_vertices) {
       uint32_t j = NRC == 2 ? ent : ent - A.train_ent0;
       float4* q = A.vrec + ((size_t)j * (uint32_t)A.rec_vertices + (bounce - 1)) * 3;
@@ -741,6 +707,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       L.z = L.z + beta * (e * TV_EX.emission[2]);
     }
     beta = beta * alb;
+    if constexpr (DEFER) {
+      // queue the light ray (weight now, walk later); the path goes on to its
+      // scatter (training paths of the cache keep their own walks: their
+      // records need the light gathered before each vertex)
+      if (A.defer && !(NRC == 1 && trainp)) {
+        const unsigned long long act = __ballot(1);
+        const int lead = __builtin_ctzll(act);
+        uint32_t base = 0;
+        if (lane == lead) base = atomicAdd(&s_lq, (uint32_t)__popcll(act));  // the block's own count, in LDS
+        base = __shfl(base, lead);
+        const uint32_t q = base + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+        if (q < A.lq_region) {  // a full region leaves the walk to the lane
+          const float gg = (EXT && TV_EX.ch_g) ? TV_EX.ch_g[cell] : TV_G;
+          const float mu = (d.x * sun0.x + d.y * sun0.y) + d.z * sun0.z;
+          const float bp = beta * hg_pdf(gg, mu);
+          LightRec r;
+          r.x = x.x;
+          r.y = x.y;
+          r.z = x.z;
+          r.cell = cell;
+          r.w0 = bp * A.E[0];
+          r.w1 = bp * A.E[1];
+          r.w2 = bp * A.E[2];
+          r.pix = pix;
+          A.lq[(size_t)blockIdx.x * A.lq_region + q] = r;
+          dsave = d;
+          o = x;
+          t = 0.0f;
+          cell_x = cell;
+          od = -1.0f;  // no light term at the scatter
+          mode = M_SCATTER;
+          return;
+        }
+      }
+    }
     dsave = d;
     o = x;
     d = TV_SUN;
@@ -1201,6 +1202,7 @@ template <class Med, int NRC>
 static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, int32_t spp, int64_t npix,
                       char* sc, RayEntry* entries, int64_t pass_cap, hipStream_t st, float* ms_total,
                       float* ms_trace, float* ms_cache, bool timed = true, LightSort* ls = nullptr) {
+  if (A.defer && !ls) return fail(TET_ERR_INTERNAL, "render: light-ray queue without its sort");
   int bs = o.block_size ? o.block_size : 256;
   int bpc = o.blocks_per_cu ? o.blocks_per_cu : 8;
   const bool ext = A.ex.model != 0 || A.ex.ch_t || A.ex.ch_a || A.ex.ch_g;
@@ -1282,8 +1284,8 @@ static int run_passes(const Med& med, RenderArgs& A, const tet_render_opts& o, i
       }
     }
     TV_HIP(hipGetLastError());
-    if constexpr (NRC == 0 && !std::is_same<Med, VoxelMedium>::value) {
-      if (A.defer)  // the pass's queued light rays, part of the tracing time
+    if constexpr (NRC != 2 && !std::is_same<Med, VoxelMedium>::value) {
+      if (A.defer && ls)  // the pass's queued light rays, part of the tracing time
         if (int rc = walk_light_queue(med, P, (int)grid, *ls, st)) return rc;
     }
     if (timed) TV_HIP(hipEventRecord(t1, st));
@@ -1442,14 +1444,14 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
   A.event_wait = o.event_wait ? o.event_wait : 48;
   // Light rays are queued and walked after each pass, sorted by start tet,
-  // for plain tet grids with analytic light transmittance when the step
+  // on tet grids without a density model (channels and the radiance cache's
+  // renders included) with analytic light transmittance when the step
   // guard is at its largest value (2^31 - 1: each light walk then runs on its
   // own, bounded by the tet count, while the guard would count all of a
   // path's walks together; the estimate is the same unless a path takes
   // more than 2^31 - 1 steps).  Their terms are added to the pixels apart
   // from the rest of their samples.
-  const bool defer = kind == 0 && !model && !o.channels && !nrc && !noalloc && o.transmittance == 0 &&
-                     o.max_steps_per_path >= 0x7FFFFFFF;
+  const bool defer = kind == 0 && !model && !noalloc && o.transmittance == 0 && o.max_steps_per_path >= 0x7FFFFFFF;
   A.accumulate = (pass_cap < spp) || (per_item < pass_cap) || nrc != nullptr || defer;
   if (nrc) {
     A.nrc = nrc;
@@ -1530,14 +1532,14 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   if (kind == 0 && g->rec32 && o.record_layout != 48) {
     TetMedium32 m{model ? g->mrec32 : g->rec32, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium32, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
-                                          !noalloc)
+                                          !noalloc, &ls)
              : run_passes<TetMedium32, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
                                           !noalloc, &ls);
   } else if (kind == 0) {
     if (o.record_layout == 32) return fail(TET_ERR_UNSUPPORTED, "render: this grid has no compact records");
     TetMedium m{model ? g->mrec : g->rec, g->keys, g->n, g->max_depth, shapes, g->kidx, g->kbits};
     rc = nrc ? run_passes<TetMedium, 1>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
-                                        !noalloc)
+                                        !noalloc, &ls)
              : run_passes<TetMedium, 0>(m, A, o, spp, npix, sc, entries, pass_cap, st, &ms, &ms_trace, &ms_cache,
                                         !noalloc, &ls);
   } else {

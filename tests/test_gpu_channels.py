@@ -77,11 +77,21 @@ def test_constant_channels_are_the_plain_tracer(tv):
     n = 16
     g.set_channels(n, temperature=np.zeros(n ** 3, np.float32), albedo=np.full(n ** 3, 0.55, np.float32),
                    g=np.full(n ** 3, -0.5, np.float32))
-    a, _ = tv.render(g, sc["camera"], dict(albedo=0.55, g=-0.5), sc["light"], 8, 99, sc["render"])
+    # bit for bit with the lanes' own light walks (pixels written once)...
+    own = dict(sc["render"], max_steps_per_path=1 << 20)
+    a, _ = tv.render(g, sc["camera"], dict(albedo=0.55, g=-0.5), sc["light"], 8, 99, own)
     b, _ = tv.render(g, sc["camera"], dict(albedo=0.9, g=0.3), sc["light"], 8, 99,
-                     dict(sc["render"], channels=1, emission=EMISSION))
+                     dict(own, channels=1, emission=EMISSION))
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+    # ...and with queued light rays, whose terms reach the pixels in any
+    # order: the same steps, the image up to FP32 summation order
+    a, sa = tv.render(g, sc["camera"], dict(albedo=0.55, g=-0.5), sc["light"], 8, 99, sc["render"])
+    b, sb = tv.render(g, sc["camera"], dict(albedo=0.9, g=0.3), sc["light"], 8, 99,
+                      dict(sc["render"], channels=1, emission=EMISSION))
+    assert sa["tet_steps"] == sb["tet_steps"] and sa["light_rays_queued"] == sb["light_rays_queued"] > 0
+    x, y = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+    assert (np.abs(x - y) / np.maximum(np.abs(x), 1e-4 * np.abs(x).mean())).max() <= 1e-5
 
 
 def test_channel_errors(tv):
