@@ -98,24 +98,39 @@ def _counter_rows(d):
     return rows
 
 
+def tracing_part(kernel_name: str):
+    """Which part of a plain render's tracing a dispatch is: "main" (the
+    persistent tracing kernel), "light" (the queued light rays: their keys,
+    sort and walks), or None."""
+    if "k_render<" in kernel_name and ", 0, false, false>" in kernel_name:
+        return "main"
+    if "k_light" in kernel_name or "rocprim" in kernel_name:
+        return "light"
+    return None
+
+
 def summarize_pmc(fetch_dir, write_dir, out_path, command, workload="the 1024^2 x 32 spp cloud frame"):
-    """Traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE runs (KiB
-    per dispatch), each scaled by the factor that maps the same counter on
-    a plain 1 GiB device copy to its true size."""
+    """Traffic of the tracing from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), each scaled by the factor that maps the same counter on a
+    plain 1 GiB device copy to its true size; per launch of the tracing
+    kernel, with the dispatches of its queued light rays."""
     def per_kernel(rows, counter):
-        trace, copies = [], []
+        parts, copies = {"main": [], "light": []}, []
         for r in rows:
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"])
-            if "k_render<" in r["Kernel_Name"] and ", 0, false, false>" in r["Kernel_Name"]:
-                trace.append(v)
+            part = tracing_part(r["Kernel_Name"])
+            if part:
+                parts[part].append(v)
             elif "copyBuffer" in r["Kernel_Name"]:
                 copies.append(v)
-        return trace, copies
-    ft, fc = per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
-    wt, wc = per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
-    f_kib, w_kib = sum(ft) / len(ft), sum(wt) / len(wt)
+        return parts, copies
+    fp, fc = per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    wp, wc = per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    ft, wt = fp["main"], wp["main"]
+    f_kib = (sum(ft) + sum(fp["light"])) / len(ft)
+    w_kib = (sum(wt) + sum(wp["light"])) / len(wt)
     f_fac = (COPY_BYTES / 1024) / max(fc)
     w_fac = (COPY_BYTES / 1024) / max(wc)
     traffic = (f_kib * f_fac + w_kib * w_fac) * 1024
@@ -130,6 +145,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command, workload="the 1024^2 
         f.write(f"dispatches = {len(ft)}\n")
         f.write(f"fetch_kib_per_launch = {f_kib:.1f}\n")
         f.write(f"write_kib_per_launch = {w_kib:.1f}\n")
+        f.write(f"fetch_kib_per_launch_light_rays = {sum(fp['light']) / len(ft):.1f}\n")
+        f.write(f"write_kib_per_launch_light_rays = {sum(wp['light']) / len(wt):.1f}\n")
         f.write(f"copy_fetch_kib = {max(fc):.1f}\n")
         f.write(f"copy_write_kib = {max(wc):.1f}\n")
         f.write(f"copy_fetch_factor = {f_fac:.4f}\n")
@@ -139,18 +156,20 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command, workload="the 1024^2 
 
 
 def summarize_counters(pmc_dir, out_path, command, steps_per_launch: float = 0.0):
-    """Per-dispatch averages of every counter collected on the tracing
-    kernel, with the L2 hit rate and VALU instructions per tet step."""
-    rows = [r for r in _counter_rows(pmc_dir)
-            if "k_render<" in r["Kernel_Name"] and ", 0, false, false>" in r["Kernel_Name"]]
+    """Every counter collected on the tracing, per launch of the tracing
+    kernel (with the dispatches of its queued light rays), with the L2 hit
+    rate and VALU instructions per tet step."""
+    rows = [r for r in _counter_rows(pmc_dir) if tracing_part(r["Kernel_Name"])]
     acc, cnt = {}, {}
     for r in rows:
         k = r["Counter_Name"]
         acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
-        cnt[k] = cnt.get(k, 0) + 1
-    avg = {k: acc[k] / cnt[k] for k in acc}
+        if tracing_part(r["Kernel_Name"]) == "main":
+            cnt[k] = cnt.get(k, 0) + 1
+    avg = {k: acc[k] / cnt[k] for k in acc if cnt.get(k)}
     with open(out_path, "w") as f:
-        f.write("# rocprofv3 counters of the tracing kernel k_render<TetMedium32>, per dispatch\n")
+        f.write("# rocprofv3 counters of the tracing (k_render<TetMedium32> and the walks of its queued light rays),"
+                " per launch\n")
         f.write(f"# command: {command}\n")
         f.write(f"source_hash = {kernel_source_hash()}\n")
         m = re.search(r"--launch '(\{[^']*\})'", command)
@@ -181,6 +200,16 @@ def summarize_trace(trace_dir, out_path, command):
         for r in rows[:16]:
             f.write(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>12.1f} {float(r['TotalDurationNs']) / 1e6:>10.2f} "
                     f"{float(r['Percentage']):>6.2f}  {r['Name'][:110]}\n")
+        main = [r for r in rows if tracing_part(r["Name"]) == "main"]
+        light = [r for r in rows if tracing_part(r["Name"]) == "light"]
+        if main:
+            launches = sum(int(r["Calls"]) for r in main)
+            t_main = sum(float(r["TotalDurationNs"]) for r in main) / 1e6
+            t_light = sum(float(r["TotalDurationNs"]) for r in light) / 1e6
+            f.write(f"tracing_launches = {launches}\n")
+            f.write(f"tracing_kernel_ms_per_launch = {t_main / launches:.3f}\n")
+            f.write(f"queued_light_rays_ms_per_launch = {t_light / launches:.3f}  (keys, sort, walks)\n")
+            f.write(f"tracing_ms_per_launch = {(t_main + t_light) / launches:.3f}\n")
     print(open(out_path).read())
 
 
@@ -799,11 +828,13 @@ def main():
         "build_ms": round(float(np.mean(build_ms)), 3),
         "render_only_msamples_per_s": round(samples / (mean_render_ms / 1e3) / 1e6, 3),
         "tet_steps_per_frame": int(mean_steps),
-        "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated")},
+        "events_per_frame": {k: int(st[k]) for k in ("real_collisions", "null_collisions", "escapes", "truncated",
+                                                      "light_rays_queued")},
         "image_mean": float(img.mean()),
         "roofline": {"bound": "hbm",
-                     "kernel": "k_render<TetMedium%s, %d, 0, false, false>" % ("32" if sc["render"]["record_layout"] == 32 else "",
-                                                                 sc["render"]["waves_per_simd"]), "achieved": round(achieved, 2),
+                     "kernel": "k_render<TetMedium%s, %d, 0, false, false> + queued light rays (k_light, sort)"
+                               % ("32" if sc["render"]["record_layout"] == 32 else "", sc["render"]["waves_per_simd"]),
+                     "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(sc["render"]),
                      "algorithmic_bytes_per_launch": int(mean_steps * BYTES_PER_TET_STEP),
