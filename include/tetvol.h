@@ -99,12 +99,15 @@ typedef struct {
   int32_t max_bounces;        /* real collisions per path, >= 1 */
   int32_t transmittance;      /* light: 0 analytic, 1 ratio tracking, 2 delta tracking */
   int64_t max_steps_per_path; /* exit evaluations per path (all walks); default 2^31 - 1.  At that value
-                                 (and above), on plain tet grids (no channels, no density model, no cache)
-                                 with analytic light transmittance, the light rays of a pass are queued,
-                                 sorted by start tet and walked together after it (a light walk then runs
-                                 on its own, bounded by the tet count; the estimate is the same unless a
-                                 path takes more than 2^31 - 1 steps); their terms reach the pixels apart
-                                 from the rest of their samples (FP32 sums in another order) */
+                                 (and above), on tet grids without a density model, with analytic light
+                                 transmittance, the light rays of a render's passes are queued, sorted by
+                                 where they start (column of the grid along the light, then depth) and
+                                 walked together after each pass (a light walk then runs on its own,
+                                 bounded by the tet count; the estimate is the same unless a path takes
+                                 more than 2^31 - 1 steps); their terms reach the pixels apart from the
+                                 rest of their samples (FP32 sums in another order).  Grids with extra
+                                 channels and the radiance cache's image paths queue theirs too; its
+                                 training paths, batches and tet_render_noalloc walk their own */
   int32_t sample_offset;      /* render samples [offset, offset + spp) */
   int32_t samples_per_item;   /* samples one lane takes at a time (0 = all of a pixel) */
   int32_t block_size;         /* threads per block: 64, 128, 192 or 256 (0 = default) */

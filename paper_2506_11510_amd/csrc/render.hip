@@ -1071,22 +1071,68 @@ __global__ void k_light_offsets(const uint32_t* __restrict__ cnt, int nb, uint32
   off[nb] = s;
 }
 
-// Keys (start tets) and queue positions of the light rays of tracing block
-// blockIdx.x, listed from its offset, for the sort.
+// Bits 0..15 of x to the even bit positions.
+__device__ inline uint32_t spread_bits2(uint32_t x) {
+  x &= 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+// Sort keys of the light rays: every ray walks along the sun direction d,
+// so rays whose starts project to nearby points of the plane normal to d
+// cross the same column of tets.  With (u, v) the start's coordinates in
+// that plane and w its coordinate along d (all about the cube's centre,
+// mapped from [-0.87, 0.87] to [0, 1)), the 32-bit key is the Z-order of
+// (u, v) at cbits bits each (a column bundle), then w at kDepthBits bits,
+// then the Z-order of the position within the bundle (fbits bits each).
+// Rays of one wave start close together at one depth (walks of similar
+// length), and the waves in flight together cover a compact set of
+// bundles, whose records stay in the caches.
+constexpr int kDepthBits = 10;
+
+__device__ inline uint32_t light_key(float3 p, float3 d, float3 t1, float3 t2, int cbits, int fbits) {
+  const float3 c = make_float3(p.x - 0.5f, p.y - 0.5f, p.z - 0.5f);
+  const float cu = (c.x * t1.x + c.y * t1.y) + c.z * t1.z;
+  const float cv = (c.x * t2.x + c.y * t2.y) + c.z * t2.z;
+  const float cw = (c.x * d.x + c.y * d.y) + c.z * d.z;
+  auto quant = [](float x, int bits) {
+    float f = (x + 0.87f) * (1.0f / 1.74f);
+    f = f < 0.0f ? 0.0f : (f > 0.99999f ? 0.99999f : f);
+    return (uint32_t)(f * (float)(1u << bits));
+  };
+  const uint32_t uq = quant(cu, cbits + fbits), vq = quant(cv, cbits + fbits), wq = quant(cw, kDepthBits);
+  const uint32_t fm = (1u << fbits) - 1u;
+  const uint32_t bundle = spread_bits2(uq >> fbits) | (spread_bits2(vq >> fbits) << 1);
+  const uint32_t fine = spread_bits2(uq & fm) | (spread_bits2(vq & fm) << 1);
+  return (bundle << (kDepthBits + 2 * fbits)) | (wq << (2 * fbits)) | fine;
+}
+
+// Keys and queue positions of the light rays of tracing block blockIdx.x,
+// listed from its offset, for the sort.
 __global__ void k_light_keys(const LightRec* __restrict__ lq, uint32_t region, const uint32_t* __restrict__ cnt,
-                             const uint32_t* __restrict__ off, uint32_t* __restrict__ keys,
-                             uint32_t* __restrict__ idx) {
+                             const uint32_t* __restrict__ off, uint32_t* __restrict__ keys, uint32_t* __restrict__ idx,
+                             float3 d, int cbits, int fbits) {
   const uint32_t b = blockIdx.x, n = cnt[b], o = off[b];
+  // an orthonormal basis (t1, t2) of the plane normal to d (Duff et al. 2017)
+  const float sg = copysignf(1.0f, d.z);
+  const float a = -1.0f / (sg + d.z);
+  const float bxy = (d.x * d.y) * a;
+  const float3 t1 = make_float3(1.0f + ((sg * d.x) * d.x) * a, sg * bxy, -sg * d.x);
+  const float3 t2 = make_float3(bxy, sg + (d.y * d.y) * a, -d.y);
   for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
     const uint32_t q = b * region + j;
-    keys[o + j] = lq[q].cell;
+    const LightRec r = lq[q];
+    keys[o + j] = light_key(make_float3(r.x, r.y, r.z), d, t1, t2, cbits, fbits);
     idx[o + j] = q;
   }
 }
 
-// The queued light rays in the order of their start tets: neighbouring lanes
-// start in neighbouring tets and walk the same direction, so they read the
-// same records.  Each walks to the grid boundary summing the optical depth
+// The queued light rays in the order of their keys (light_key): neighbouring
+// lanes start close together and walk the same direction through the same
+// column of tets, so they read the same records.  Each walks to the grid boundary summing the optical depth
 // (analytic transmittance, as the tracer's own light walk), then adds its
 // weight times e^-depth to its pixel.  A straight walk meets a tet at most
 // once, so the tet count bounds it.
@@ -1172,11 +1218,11 @@ struct LightSort {
   uint32_t* idx[2];
   void* temp;
   size_t temp_bytes;
-  unsigned end_bit;  // start tets fit in this many bits
+  int cbits, fbits;  // key layout (light_key)
   int64_t queued;    // light rays walked from the queue so far
 };
 
-// The pass's queued light rays: their count, the sort by start tet, the walks.
+// The pass's queued light rays: their count, the sort by key, the walks.
 template <class Med>
 static int walk_light_queue(const Med& med, const RenderArgs& P, int nblocks, LightSort& ls, hipStream_t st) {
   uint32_t* off = P.lq_count + kMaxTraceBlocks;
@@ -1187,9 +1233,10 @@ static int walk_light_queue(const Med& med, const RenderArgs& P, int nblocks, Li
   ls.queued += n;
   if (!n) return TET_OK;
   hipLaunchKernelGGL(k_light_keys, dim3((unsigned)nblocks), dim3(256), 0, st, (const LightRec*)P.lq, P.lq_region,
-                     (const uint32_t*)P.lq_count, (const uint32_t*)off, ls.keys[0], ls.idx[0]);
+                     (const uint32_t*)P.lq_count, (const uint32_t*)off, ls.keys[0], ls.idx[0],
+                     make_float3(P.sun[0], P.sun[1], P.sun[2]), ls.cbits, ls.fbits);
   size_t tb = ls.temp_bytes;
-  if (rocprim::radix_sort_pairs(ls.temp, tb, ls.keys[0], ls.keys[1], ls.idx[0], ls.idx[1], n, 0u, ls.end_bit, st) !=
+  if (rocprim::radix_sort_pairs(ls.temp, tb, ls.keys[0], ls.keys[1], ls.idx[0], ls.idx[1], n, 0u, 32u, st) !=
       hipSuccess)
     return fail(TET_ERR_DEVICE, "render: sort of the light rays");
   hipLaunchKernelGGL(k_light<Med>, dim3((n + 255) / 256), dim3(256), 0, st, P, med, (const LightRec*)P.lq,
@@ -1500,9 +1547,14 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   } frq_{nullptr};
   if (defer) {
     const uint32_t cap = (uint32_t)std::min<int64_t>(1ll << 26, std::max<int64_t>(1024, slots * pass_cap * 4));
-    while (ls.end_bit < 32 && (int64_t)(1ull << ls.end_bit) < g->n) ls.end_bit++;
+    // column bundles about as wide as the grid's typical tet: bits per
+    // axis ~ log2(tets) / 3 (8 on a 7 M-tet grid, 9 on 86 M tets)
+    int tet_bits = 0;
+    while (tet_bits < 40 && (int64_t)(1ull << tet_bits) < g->n) tet_bits++;
+    ls.cbits = std::max(4, std::min(11, (tet_bits + 1) / 3));
+    ls.fbits = (32 - kDepthBits - 2 * ls.cbits) / 2;
     if (rocprim::radix_sort_pairs(nullptr, ls.temp_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                  (uint32_t*)nullptr, cap, 0u, ls.end_bit, st) != hipSuccess)
+                                  (uint32_t*)nullptr, cap, 0u, 32u, st) != hipSuccess)
       return fail(TET_ERR_DEVICE, "render: light-ray sort size");
     const size_t head = (size_t)(2 * kMaxTraceBlocks + 64) * 4;  // per-block counts, then their offsets
     const size_t qb = head + (size_t)cap * sizeof(LightRec) + 4 * (size_t)cap * 4 + ((ls.temp_bytes + 255) & ~size_t(255));

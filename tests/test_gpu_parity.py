@@ -182,8 +182,8 @@ def test_render_modes_parity(tv, mode, per_item):
 
 @pytest.mark.parametrize("dense", [False, True])
 def test_queued_light_rays_equal_lane_walks(tv, dense):
-    """Light rays queued and walked after the pass in the order of their
-    start tets give the paths, steps and collisions of the lanes' own light
+    """Light rays queued and walked after the pass in the order of where
+    they start give the paths, steps and collisions of the lanes' own light
     walks, and the image up to the order of FP32 sums per pixel (relative
     1e-5); both against the oracle.  The dense case (thick, bright medium,
     many bounces) has more light rays than the queue holds: the rest are
