@@ -1499,7 +1499,7 @@ __global__ __launch_bounds__(kRecordsBlock) void k_records(int64_t n, const uint
       }
       if (bnd) {
         rec[t].nbr[f] = kBoundary;
-        if (rec32) rec32[t].w[4 + f] = kLink27Boundary | ((uint32_t)code << 27);
+        if (rec32) rec32[t].w[4 + f] = kLink27Boundary | code_bits32((uint32_t)code);
       } else if (!(code & 1)) {
         owned |= 1u << f;
       }
@@ -1613,11 +1613,11 @@ __global__ void k_links(const uint32_t* __restrict__ items, const uint32_t* __re
       link = ((uint32_t)nb << 2) | (uint32_t)bf;
       // the neighbour sees this face as -dir_N across its face bf
       rec[nb].nbr[bf] = ((uint32_t)t << 2) | (uint32_t)f;
-      if (rec32) rec32[nb].w[4 + bf] = (uint32_t)t | ((uint32_t)(code ^ 1) << 27);
+      if (rec32) rec32[nb].w[4 + bf] = (uint32_t)t | code_bits32((uint32_t)(code ^ 1));
     }
   }
   rec[t].nbr[f] = link;
-  if (rec32) rec32[t].w[4 + f] = (link == kBoundary ? kLink27Boundary : (link >> 2)) | ((uint32_t)code << 27);
+  if (rec32) rec32[t].w[4 + f] = (link == kBoundary ? kLink27Boundary : (link >> 2)) | code_bits32((uint32_t)code);
 }
 
 // ---------------------------------------------------------------- host

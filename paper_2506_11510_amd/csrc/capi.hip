@@ -270,7 +270,7 @@ __global__ void k_export_faces(int64_t n, const TetRec* __restrict__ rec, const 
     const int32_t io[4] = {((int32_t)(r.w[0] << 9)) >> 9, ((int32_t)(o1 << 9)) >> 9, ((int32_t)(o2 << 9)) >> 9,
                            ((int32_t)(r.w[2] << 4)) >> 9};
     for (int f = 0; f < 4; f++) {
-      if (codes) codes[4 * i + f] = (uint8_t)(r.w[4 + f] >> 27);
+      if (codes) codes[4 * i + f] = (uint8_t)code_of32(r.w[4 + f]);
       if (offs) offs[4 * i + f] = io[f];
       if (links) links[4 * i + f] = r.w[4 + f] & kLink27Boundary;
     }

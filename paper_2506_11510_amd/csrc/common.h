@@ -37,12 +37,15 @@ static_assert(sizeof(TetRec) == 48, "record size");
 //            (world offset = offset * 2^-20, exact in FP32);
 //   w[3]:    extinction (FP32 bits);
 //   w[4+f]:  neighbour index across face f (27 bits; kLink27Boundary on the
-//            boundary) | face f's orientation code << 27.
+//            boundary) | face f's orientation code 2 N + s as N << 27 and
+//            s << 31 (the sign then flips a float with one masked XOR).
 struct alignas(32) TetRec32 {
   uint32_t w[8];
 };
 static_assert(sizeof(TetRec32) == 32, "compact record size");
 constexpr uint32_t kLink27Boundary = (1u << 27) - 1;
+__host__ __device__ inline uint32_t code_bits32(uint32_t code) { return ((code >> 1) << 27) | ((code & 1u) << 31); }
+__host__ __device__ inline uint32_t code_of32(uint32_t w) { return (((w >> 27) & 15u) << 1) | (w >> 31); }
 constexpr int64_t kMaxTets32 = (1ll << 27) - 1;
 
 // The 9 plane directions of these grids' faces; a face's outward normal is

@@ -353,7 +353,9 @@ struct TetMedium32 {
   __device__ inline int64_t locate(float3 p) const { return locate_point(keys, kidx, kbits, dmax, shapes, p); }
   __device__ inline float sigma_at(uint32_t cell) const { return __uint_as_float(rec[cell].w[3]); }
   __device__ inline Step step(uint32_t cell, float3, float3, const float* tab, float t) const {
-    const uint4* q = (const uint4*)(rec + cell);
+    // byte offset in 32 bits (cell < 2^27): a uniform base takes the load's
+    // scalar-base form
+    const uint4* q = (const uint4*)((const char*)rec + (cell << 5));
     const uint4 a = q[0], b = q[1];
     uint32_t o1 = (uint32_t)((((uint64_t)a.y << 32) | a.x) >> 23);
     uint32_t o2 = (uint32_t)((((uint64_t)a.z << 32) | a.y) >> 14);
@@ -364,7 +366,11 @@ struct TetMedium32 {
     float tden[4], tdot[4];
 #pragma unroll
     for (int f = 0; f < 4; f++) {
-      const float* e = tab + (lw[f] >> 28);
+      // direction index N (bits 27..30) as one bit-field extract: left to
+      // the compiler it becomes shift, mask and add before the address add
+      uint32_t dn;
+      asm("v_bfe_u32 %0, %1, 27, 4" : "=v"(dn) : "v"(lw[f]));
+      const float* e = tab + dn;
       tden[f] = e[0];
       tdot[f] = e[9];
     }
@@ -372,7 +378,7 @@ struct TetMedium32 {
     float bnum, bden;
     uint32_t blink;
     {  // face 0 against the start quotient 1/0: it wins exactly when it is a candidate
-      uint32_t sg = (lw[0] >> 27) << 31;
+      uint32_t sg = lw[0] & 0x80000000u;
       float den = __uint_as_float(__float_as_uint(tden[0]) ^ sg);
       float dot = __uint_as_float(__float_as_uint(tdot[0]) ^ sg);
       float num = (float)ioff[0] - dot;
@@ -383,7 +389,7 @@ struct TetMedium32 {
     }
 #pragma unroll
     for (int f = 1; f < 4; f++) {
-      uint32_t sg = (lw[f] >> 27) << 31;
+      uint32_t sg = lw[f] & 0x80000000u;
       float den = __uint_as_float(__float_as_uint(tden[f]) ^ sg);
       float dot = __uint_as_float(__float_as_uint(tdot[f]) ^ sg);
       float num = (float)ioff[f] - dot;
