@@ -376,7 +376,7 @@ struct TetMedium32 {
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the four reads ahead of their uses
     float bnum, bden;
-    uint32_t blink;
+    uint32_t bw;  // link word of the best face (all ones: none yet)
     {  // face 0 against the start quotient 1/0: it wins exactly when it is a candidate
       uint32_t sg = lw[0] & 0x80000000u;
       float den = __uint_as_float(__float_as_uint(tden[0]) ^ sg);
@@ -384,8 +384,10 @@ struct TetMedium32 {
       float num = (float)ioff[0] - dot;
       const bool cand = den > 0.0f;
       bnum = cand ? num : 1.0f;
-      bden = cand ? den : 0.0f;
-      blink = cand ? (lw[0] & kLink27Boundary) : kLink27Boundary;
+      // -0 when there is no candidate: the same comparisons as +0 below (a
+      // candidate's 1 * den is > 0), and a plain select rather than a max
+      bden = cand ? den : -0.0f;
+      bw = cand ? lw[0] : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int f = 1; f < 4; f++) {
@@ -396,8 +398,9 @@ struct TetMedium32 {
       bool better = den > 0.0f && (double)num * (double)bden < (double)bnum * (double)den;
       bnum = better ? num : bnum;
       bden = better ? den : bden;
-      blink = better ? (lw[f] & kLink27Boundary) : blink;
+      bw = better ? lw[f] : bw;
     }
+    const uint32_t blink = bw & kLink27Boundary;
     Step s;
     bool any = bden > 0.0f;
     float bt = (bnum / bden) * 0x1p-20f;
