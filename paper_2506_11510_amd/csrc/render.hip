@@ -1497,8 +1497,8 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.seed = seed;
   A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
-  A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
-  A.event_wait = o.event_wait ? o.event_wait : 48;
+  A.batch = o.batch_items ? (uint32_t)o.batch_items : 128u;
+  A.event_wait = o.event_wait ? o.event_wait : 32;
   // Light rays are queued and walked after each pass, sorted by start tet,
   // on tet grids without a density model (channels and the radiance cache's
   // renders included) with analytic light transmittance when the step
@@ -1895,8 +1895,8 @@ static int batch_setup(BatchState* B, int32_t n, const tet_grid* const* grids, c
   A.per_item = 1;
   A.items = (uint32_t)item;
   A.range_size = (uint32_t)(((item + 7) / 8 + 63) / 64 * 64);
-  A.batch = 64;
-  A.event_wait = o.event_wait ? o.event_wait : 48;
+  A.batch = 64;  // a wave's batch stays within one scene (scenes' items are padded to 64)
+  A.event_wait = o.event_wait ? o.event_wait : 32;
   A.accumulate = 1;
   A.counter = (uint32_t*)B->scratch;
   A.stats = (unsigned long long*)(B->scratch + 64);
