@@ -467,7 +467,7 @@ def host_io_leg(tv, torch, d, sc, steps: int = 3) -> dict:
             "bytes_over_pcie_per_step": int(d.nbytes + img.nbytes)}
 
 
-PLUME_LAUNCH = {"waves_per_simd": 5, "event_wait": 32, "batch_items": 128, "block_size": 256, "record_layout": 32,
+PLUME_LAUNCH = {"waves_per_simd": 5, "event_wait": 32, "batch_items": 64, "block_size": 256, "record_layout": 32,
                 "samples_per_item": 1}
 
 
@@ -752,10 +752,10 @@ def main():
         sc["build"] = dict(sc["build"], host_rounds=1)
     # launch configuration of the tracing kernel: the library's autotuner
     # times probe renders of this frame (8 spp) from this starting point
-    # (the library's defaults: one sample per work item, batches of 128
+    # (the library's defaults: one sample per work item, batches of 64
     # items per wave, compact 32-byte records, 5 waves per SIMD, events once
     # 32 lanes wait)
-    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=128, record_layout=32, waves_per_simd=5,
+    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
                         event_wait=32)
     cam, spp = sc["camera"], sc["render"]["spp"]
     d = sc["density_fn"]()

@@ -114,8 +114,7 @@ typedef struct {
   int32_t blocks_per_cu;      /* persistent blocks per compute unit (0 = default) */
   int32_t waves_per_simd;     /* register budget of the tracing kernel: 4, 5, 6 or 8 waves (0 = default 5) */
   int32_t record_layout;      /* tet records walked: 32 (compact), 48, or 0 = compact when the grid has them */
-  int32_t batch_items;        /* work items a wave takes at a time (0 = default: 128; 64 when collecting
-                                 training paths; batches always take 64) */
+  int32_t batch_items;        /* work items a wave takes at a time (0 = default 64; batches always take 64) */
   int32_t event_wait;         /* lanes of a wave that wait for an event before events run (0 = default: 32;
                                  48 when collecting training paths) */
   const tet_nrc* nrc;         /* radiance cache: NULL = plain estimator; else paths stop at the cache's

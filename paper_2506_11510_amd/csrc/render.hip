@@ -1497,7 +1497,7 @@ static int render_common(int kind, const tet_grid* g, const tet_density* dens, c
   A.seed = seed;
   A.slots = (uint32_t)slots;
   A.tiles_x = tiles_x;
-  A.batch = o.batch_items ? (uint32_t)o.batch_items : 128u;
+  A.batch = o.batch_items ? (uint32_t)o.batch_items : 64u;
   A.event_wait = o.event_wait ? o.event_wait : 32;
   // Light rays are queued and walked after each pass, sorted by start tet,
   // on tet grids without a density model (channels and the radiance cache's

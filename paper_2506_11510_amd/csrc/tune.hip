@@ -163,7 +163,7 @@ int autotune(const tet_grid* g, const tet_camera* cam, const tet_medium* med, co
   tet_render_opts cur = base;
   if (!cur.waves_per_simd) cur.waves_per_simd = 5;
   if (!cur.event_wait) cur.event_wait = 32;
-  if (!cur.batch_items) cur.batch_items = 128;
+  if (!cur.batch_items) cur.batch_items = 64;
   if (!cur.block_size) cur.block_size = 256;
   if (!cur.record_layout) cur.record_layout = g->rec32 ? 32 : 48;
   const size_t img = (size_t)cam->width * cam->height * 3 * sizeof(float);
