@@ -753,10 +753,10 @@ def main():
     # launch configuration of the tracing kernel: the library's autotuner
     # times probe renders of this frame (8 spp) from this starting point
     # (the library's defaults: one sample per work item, batches of 64
-    # items per wave, compact 32-byte records, 5 waves per SIMD, events once
-    # 32 lanes wait)
-    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, record_layout=32, waves_per_simd=5,
-                        event_wait=32)
+    # items per wave, 256-thread blocks, compact 32-byte records, 5 waves
+    # per SIMD, events once 32 lanes wait)
+    sc["render"] = dict(sc["render"], samples_per_item=1, batch_items=64, block_size=256, record_layout=32,
+                        waves_per_simd=5, event_wait=32)
     cam, spp = sc["camera"], sc["render"]["spp"]
     d = sc["density_fn"]()
     dev = torch.from_numpy(d).cuda()

@@ -975,9 +975,10 @@ int nrc_query_pass(const tet_nrc* n, const float4* q, const uint32_t* qpix, cons
   Q.out = out;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  // persistent blocks (the number of queries is on the device): 2 per CU
+  // persistent blocks (the number of queries is on the device): 4 per CU,
+  // as many as the weights' 40 KB of LDS per block allow
   int64_t waves = (capacity + 63) / 64;
-  unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, (int64_t)cus * 2));
+  unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, (int64_t)cus * 4));
   hipLaunchKernelGGL(k_nrc_query<1>, dim3(grid), dim3(256), 0, st, Q);
   TV_HIP(hipGetLastError());
   return TET_OK;
